@@ -1,0 +1,159 @@
+"""Exact-arithmetic oracle pieces for tiny inputs -- test infrastructure only.
+
+Everything here works on Python Fractions, so no rounding is involved:
+
+* `exact_member` / `exact_range_search`: the membership decision cos(q,f) >= rho
+  of the problem statement (Sec. 1; cosine of non-negative vectors, Sec. 2),
+  decided without square roots: for rho >= 0 it is dot >= 0 and
+  dot^2 >= rho^2 * qq * ff; for rho < 0 it is dot >= 0 or dot^2 <= rho^2 qq ff.
+* `binary_splitting`: the paper's iterative binary splitting (Sec. 2, Alg. 1),
+  driven by a stack of (start, end, score) triples over the cumulative sums of
+  Eq. 1, with the right half tested directly and the left half's score obtained
+  by subtraction.  Similarity is the dot product q.f as in Sec. 2.
+* `levelwise_walk`: the same implicit tree visited one level ("round") at a
+  time (Sec. 5 analyses pruning per round), over a power-of-two capacity with
+  zero padding, testing both children of every surviving pool directly.
+
+The binary-splitting and level-wise walks are the paper's method, kept here to
+show that it returns exactly the brute-force set; the GPU path is compared with
+the brute-force definition, not with these walks.
+"""
+from __future__ import annotations
+
+from decimal import Decimal, getcontext
+from fractions import Fraction
+
+
+def to_frac_rows(a):
+    """Exact Fractions of float values (float32/float64 are dyadic rationals)."""
+    return [[Fraction(float(x)) for x in row] for row in a]
+
+
+def dot(a, b):
+    s = Fraction(0)
+    for x, y in zip(a, b):
+        s += x * y
+    return s
+
+
+def exact_member(q, f, rho) -> bool:
+    """cos(q, f) >= rho in exact arithmetic; a zero vector is never a member
+    (its cosine is undefined)."""
+    qq, ff, dq = dot(q, q), dot(f, f), dot(q, f)
+    if qq == 0 or ff == 0:
+        return False
+    r = Fraction(float(rho))
+    rhs = r * r * qq * ff
+    if r >= 0:
+        return dq >= 0 and dq * dq >= rhs
+    return dq >= 0 or dq * dq <= rhs
+
+
+def exact_range_search(F, Q, rho):
+    """List of sorted id lists, one per query."""
+    Ff, Qf = to_frac_rows(F), to_frac_rows(Q)
+    rhos = list(rho) if hasattr(rho, "__len__") else [rho] * len(Qf)
+    return [[i for i, f in enumerate(Ff) if exact_member(q, f, r)] for q, r in zip(Qf, rhos)]
+
+
+def cos_decimal(q, f, prec: int = 60) -> Decimal:
+    """cos(q, f) to `prec` significant digits (NaN for a zero vector)."""
+    getcontext().prec = prec
+    qf, ff_ = [Fraction(float(x)) for x in q], [Fraction(float(x)) for x in f]
+    qq, ff, dq = dot(qf, qf), dot(ff_, ff_), dot(qf, ff_)
+    if qq == 0 or ff == 0:
+        return Decimal("NaN")
+    num = Decimal(dq.numerator) / Decimal(dq.denominator)
+    den = (Decimal(qq.numerator) / Decimal(qq.denominator) *
+           Decimal(ff.numerator) / Decimal(ff.denominator)).sqrt()
+    return num / den
+
+
+def prefix_sums(F):
+    """Cumulative sums of Eq. 1, with a leading zero row so that the sum of rows
+    a..b (0-based, inclusive) is C[b+1] - C[a]."""
+    d = len(F[0]) if F else 0
+    C = [[Fraction(0)] * d]
+    for f in F:
+        C.append([c + x for c, x in zip(C[-1], f)])
+    return C
+
+
+def binary_splitting(F, q, rho):
+    """Sec. 2, Alg. 1, in exact arithmetic with sim = q.f.  Returns the sorted
+    list of flagged (neighbour) indices, 0-based, and the number of dot products.
+
+    A pool is a contiguous index range [si, ei].  A pool whose score is below
+    rho is dropped whole.  Otherwise a pool of more than two members is split
+    with floor(n/2) members on the left; the right half is tested with one dot
+    product against a difference of cumulative sums, and the left half's score
+    is the parent's score minus the right half's.  Two-member pools test the
+    right member and derive the left; a single member is flagged directly.
+    """
+    N = len(F)
+    if N == 0:
+        return [], 0
+    qf = [Fraction(float(x)) for x in q]
+    F = [[Fraction(float(x)) for x in f] for f in F]
+    C = prefix_sums(F)
+    r = Fraction(float(rho))
+
+    def pool_score(a, b):  # rows a..b inclusive
+        return dot(qf, [hi - lo for hi, lo in zip(C[b + 1], C[a])])
+
+    flags = [0] * N
+    ndots = 1
+    stack = [(0, N - 1, pool_score(0, N - 1))]
+    while stack:
+        si, ei, sim = stack.pop()
+        if sim < r:
+            continue
+        n = ei - si + 1
+        if n > 2:
+            half = n // 2
+            rsim = pool_score(si + half, ei)
+            ndots += 1
+            stack.append((si + half, ei, rsim))
+            stack.append((si, si + half - 1, sim - rsim))
+        elif n == 2:
+            rsim = pool_score(ei, ei)
+            ndots += 1
+            if rsim >= r:
+                flags[ei] = 1
+            if sim - rsim >= r:
+                flags[si] = 1
+        else:
+            flags[si] = 1
+    return [i for i in range(N) if flags[i]], ndots
+
+
+def levelwise_walk(F, q, rho, capacity: int | None = None):
+    """Level-by-level walk of an explicit pool-sum tree (Sec. 2 pools, visited
+    per round as in Sec. 5) over a power-of-two capacity, zero-padded; both
+    children of each surviving pool are tested directly, and a leaf is a
+    member iff its own score reaches rho.  Returns (ids, tests per level)."""
+    N = len(F)
+    if N == 0:
+        return [], []
+    cap = capacity or 1 << max(0, (N - 1).bit_length())
+    assert cap >= N and cap & (cap - 1) == 0
+    d = len(F[0])
+    qf = [Fraction(float(x)) for x in q]
+    leaves = [[Fraction(float(x)) for x in f] for f in F] + [[Fraction(0)] * d] * (cap - N)
+    levels = [leaves]
+    while len(levels[0]) > 1:
+        below = levels[0]
+        levels.insert(0, [[a + b for a, b in zip(below[2 * j], below[2 * j + 1])]
+                          for j in range(len(below) // 2)])
+    r = Fraction(float(rho))
+    frontier = [0] if dot(qf, levels[0][0]) >= r else []
+    tests = [1]
+    for lvl in range(1, len(levels)):
+        nxt = []
+        for p in frontier:
+            for c in (2 * p, 2 * p + 1):
+                if dot(qf, levels[lvl][c]) >= r:
+                    nxt.append(c)
+        tests.append(2 * len(frontier))
+        frontier = nxt
+    return sorted(i for i in frontier if i < N), tests
