@@ -1,0 +1,226 @@
+"""Benchmark of the group-testing range search on one MI355X.
+
+One step = one gt_query_batch call over a batch of queries: query preparation,
+the level-wise pool walk, the exact leaf test, the float64 recheck and the
+result compaction (the whole query path; the index is built once, offline, as
+in the paper).  Workload: N = 2^20 softmax feature vectors, d = 1000, 1024
+queries per batch, rho = 0.9, bfloat16 pool sums.  Beside it: the plain float32
+walk, the float8 walk and the exhaustive float32 GEMM on the same batch, and
+the CPU float64 oracle on a bounded sample of the same queries.
+
+Prints one JSON line.  Only one GPU is used; --gpus > 1 exits.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "queries/sec at N=1M,d=1000,100% recall vs exhaustive GEMM; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pct(a, p):
+    return float(np.percentile(np.asarray(a), p))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--d", type=int, default=1000)
+    ap.add_argument("--nq", type=int, default=1024)
+    ap.add_argument("--rho", type=float, default=0.9)
+    ap.add_argument("--pool", default="bf16", choices=["bf16", "fp8", "f32"])
+    ap.add_argument("--side-steps", type=int, default=5)
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-side", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU (this build has no multi-GPU path); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2311_02573_amd import gt, synth
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    t0 = time.time()
+    w = synth.workload1(nq=args.nq, rho=args.rho, n=args.n, d=args.d)
+    log(f"generated N={w.n} d={w.d} nq={args.nq} in {time.time() - t0:.1f}s")
+    feats = torch.from_numpy(w.feats).to(dev)
+    q = torch.from_numpy(w.queries).to(dev)
+    torch.cuda.synchronize()
+
+    t0 = time.time()
+    idx = gt.GTIndex(feats, pools=("f32", "bf16", "fp8"))
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    st0 = idx.stats()
+    log(f"index built in {build_s * 1e3:.1f} ms, depth {st0['depth']}, head {st0['head_level']}, "
+        f"{st0['bytes_device'] / 2**30:.2f} GiB")
+    del feats
+    torch.cuda.empty_cache()
+
+    def run(pool, steps, warmup):
+        fn = (lambda: idx.exhaustive(q, args.rho)) if pool == "exh" else \
+            (lambda: idx.query(q, args.rho, pool=pool))
+        res = None
+        for _ in range(warmup):
+            res = fn()
+        torch.cuda.synchronize()
+        lat = []
+        t_start = time.perf_counter()
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t1) * 1e3)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        return res, wall, lat
+
+    # ---- headline: the walk on the chosen pool format
+    res, wall, lat = run(args.pool, args.steps, args.warmup)
+    ms_step = wall / args.steps * 1e3
+    qps = args.nq * args.steps / wall
+    log(f"{args.pool} walk: {ms_step:.3f} ms/batch, {qps:.0f} queries/s, {res.total} results")
+
+    # ---- kernel timing with HIP events on the call's stream (profiling on)
+    idx.set_option("profile", 1)
+    prof = []
+    for _ in range(max(3, args.side_steps)):
+        idx.query(q, args.rho, pool=args.pool)
+        prof.append(idx.stats())
+    idx.set_option("profile", 0)
+    ms_front = float(np.median([p["ms_frontier"] for p in prof]))
+    ms_leaf = float(np.median([p["ms_leaf"] for p in prof]))
+    launches = prof[-1]["frontier_launches"]
+
+    # ---- algorithmic bytes of the walk: each distinct pool row read once
+    idx.set_option("count_unique", 1)
+    idx.query(q, args.rho, pool=args.pool)
+    su = idx.stats()
+    idx.set_option("count_unique", 0)
+    esz = {"bf16": 2, "fp8": 1, "f32": 4}[args.pool]
+    dp = su["d_pad"]
+    uniq_pools = int(sum(su["unique_rows"][:su["depth"]]))
+    uniq_leaves = int(su["unique_rows"][su["depth"]])
+    pool_bytes = uniq_pools * dp * esz
+    leaf_bytes = uniq_leaves * dp * 4
+    achieved = pool_bytes / (ms_front * 1e-3) / 1e9 if ms_front > 0 else None
+    roofline = {
+        "kernel": f"k_walk_level<{args.pool}>",
+        "bound": "hbm",
+        "achieved": round(achieved, 1) if achieved else None,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": None,
+        "algorithmic_bytes_per_batch": pool_bytes,
+        "launches_per_batch": launches,
+        "avg_launch_ms": ms_front / max(1, launches),
+        "leaf_kernel": {"bytes": leaf_bytes, "ms": ms_leaf,
+                        "GBps": round(leaf_bytes / (ms_leaf * 1e-3) / 1e9, 1) if ms_leaf > 0 else None},
+    }
+
+    # ---- comparators and recall against the exhaustive GEMM
+    comparators = {}
+    exh = None
+    if not args.no_side:
+        for pool in ("f32", "fp8", "bf16"):
+            if pool == args.pool:
+                continue
+            r2, wall2, lat2 = run(pool, args.side_steps, 1)
+            comparators[f"walk_{pool}_qps"] = round(args.nq * args.side_steps / wall2, 1)
+            comparators[f"walk_{pool}_ms"] = round(wall2 / args.side_steps * 1e3, 3)
+        exh, wall3, lat3 = run("exh", max(2, args.side_steps // 2), 1)
+        n3 = max(2, args.side_steps // 2)
+        comparators["exhaustive_f32_qps"] = round(args.nq * n3 / wall3, 1)
+        comparators["exhaustive_f32_ms"] = round(wall3 / n3 * 1e3, 3)
+        idx.set_option("profile", 1)
+        exh = idx.exhaustive(q, args.rho)
+        se = idx.stats()
+        idx.set_option("profile", 0)
+        comparators["exhaustive_gemm_ms"] = se["ms_gemm"]
+        flops = 2.0 * args.nq * w.n * dp
+        comparators["exhaustive_gemm_tflops"] = round(flops / (se["ms_gemm"] * 1e-3) / 1e12, 1) \
+            if se["ms_gemm"] > 0 else None
+    walk_lists = res.to_lists()
+    recall = None
+    if exh is not None:
+        ex_lists = exh.to_lists()
+        same = all(np.array_equal(a[0], b[0]) for a, b in zip(walk_lists, ex_lists))
+        tot_ex = sum(len(b[0]) for b in ex_lists)
+        hit = sum(len(np.intersect1d(a[0], b[0])) for a, b in zip(walk_lists, ex_lists))
+        recall = hit / tot_ex if tot_ex else 1.0
+        if not same:
+            log("WARNING: walk and exhaustive results differ")
+
+    # ---- CPU oracle on a bounded sample of the same batch
+    cpu = None
+    if not args.no_cpu and args.cpu_sample > 0:
+        import oracle.brute as ob
+
+        threads = ob.default_threads()
+        ns = min(args.cpu_sample, args.nq)
+        t1 = time.perf_counter()
+        ora = ob.range_search(w.feats, w.queries[:ns], args.rho, nthreads=threads)
+        cpu_s = time.perf_counter() - t1
+        match = all(np.array_equal(walk_lists[b][0], ora[b][0]) for b in range(ns))
+        cpu = {"value": round(ns / cpu_s, 3), "unit": "queries/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {ns} of the {args.nq} queries against the full database "
+                         f"(N={w.n}, d={w.d}); canonical float64 scan, {cpu_s:.1f} s",
+               "ids_match_gpu": bool(match)}
+        log(f"oracle: {ns} queries in {cpu_s:.1f}s on {threads} threads, match={match}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.pool,
+        "data": "synthetic",
+        "config": {"workload": f"softmax(z/0.2) unit features N={w.n} d={w.d} float32, "
+                               f"{args.nq} queries per batch with planted neighbours, "
+                               f"rho={args.rho}, {args.pool} pool sums",
+                   "global_batch": args.nq, "n": w.n, "d": w.d, "rho": args.rho,
+                   "pool": args.pool},
+        "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
+        "results_per_batch": res.total,
+        "recall_vs_exhaustive": recall,
+        "index_build_ms": round(build_s * 1e3, 1),
+        "roofline": roofline,
+        "comparators": comparators,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    idx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * gt.h -- exact range search by adaptive group testing (binary splitting with
+ * sum pools) on one AMD MI355X (gfx950).
+ *
+ * Problem (paper Sec. 1): given database vectors f_1..f_N in R^d, a query q and
+ * a threshold rho, return every i with sim(q, f_i) >= rho.  Similarity is the
+ * cosine; the paper works with non-negative unit vectors, for which it is the
+ * dot product (Sec. 2).  Method (Sec. 2, Alg. 1): a pool is the sum of its
+ * members; because every term q_k * f_ik is non-negative, a pool whose score is
+ * below the threshold holds no neighbour and is discarded whole, and surviving
+ * pools are halved down to single vectors, which get an exact test.  The
+ * method is exact: its result is the brute-force set.
+ *
+ * Conventions for every entry point:
+ *  - Returns a gt_status; nothing is thrown across this interface.  On any
+ *    error the index is left as it was.  gt_last_error() gives a message for
+ *    the calling thread.
+ *  - Pointers named *_dev are device pointers (HIP device memory on the
+ *    current device); *_host are host pointers.  Inputs are borrowed and read
+ *    in stream order: the caller keeps them alive until `stream` reaches the
+ *    call.  Outputs are caller-owned device buffers.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are asynchronous except where a host value is returned (documented).
+ *  - One host thread may use an index at a time.
+ *  - Matrices are row-major with row stride d (elements).
+ */
+#ifndef GT_H
+#define GT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gt_index gt_index; /* opaque, owned by the library */
+
+typedef enum {
+  GT_OK = 0,
+  GT_ERR_INVALID_ARG = 1,      /* bad size, pointer, dtype or format */
+  GT_ERR_INVALID_INPUT = 2,    /* a NaN, infinite or negative value (the prune
+                                  rule needs non-negative vectors, Sec. 2) */
+  GT_ERR_OUT_OF_MEMORY = 3,
+  GT_ERR_CAPACITY = 4,         /* insert beyond the capacity given at build */
+  GT_ERR_RESULT_OVERFLOW = 5,  /* more results than max_results; see queries */
+  GT_ERR_DEVICE = 6            /* a HIP runtime error */
+} gt_status;
+
+typedef enum { GT_F32 = 0, GT_F16 = 1, GT_BF16 = 2 } gt_dtype; /* feature storage */
+
+/* Pool-sum storage formats.  Pool sums are kept as float32 master values
+ * rounded upward; the reduced formats are upward-rounded copies (bfloat16, and
+ * float8 e4m3 with one power-of-two scale per tree level).  Bit mask at build
+ * time, one value per query call. */
+typedef enum { GT_POOL_F32 = 1, GT_POOL_BF16 = 2, GT_POOL_FP8E4M3 = 4 } gt_pool;
+
+#define GT_MAX_LEVELS 40
+
+typedef struct {
+  int64_t n;              /* vectors currently indexed (ids 0..n-1) */
+  int64_t capacity;       /* leaves of the tree (power of two) */
+  int32_t d, d_pad;       /* dimension and padded row length */
+  int32_t depth;          /* log2(capacity): leaves are at this level */
+  int32_t head_level;     /* first level whose pools are tested */
+  uint32_t pool_formats;
+  double m_min;           /* smallest norm over non-zero rows */
+  uint64_t epoch;         /* bumped by every successful insert */
+  int64_t bytes_device;   /* device memory held by the index */
+  /* last gt_query_batch / gt_exhaustive call */
+  int32_t last_nq, last_tiles, last_format;
+  int64_t entries[GT_MAX_LEVELS]; /* (tile, pool) frontier entries per level */
+  int64_t pairs[GT_MAX_LEVELS];   /* (query, pool) tests per level */
+  int64_t leaf_pairs;     /* (query, vector) exact tests */
+  int64_t candidates;     /* leaf tests that passed or fell in the recheck band */
+  int64_t rechecked;      /* candidates re-decided in float64 */
+  int64_t results;        /* total neighbours returned */
+  /* device time of the last call, per kernel group, from HIP events on the
+   * call's stream; zero unless profiling is on (gt_set_option "profile") */
+  double ms_prep, ms_frontier, ms_leaf, ms_recheck, ms_compact, ms_gemm, ms_total;
+  int32_t frontier_launches;
+  int32_t fp8_exp[GT_MAX_LEVELS]; /* float8 pools of level l are code * 2^fp8_exp[l] */
+  /* distinct rows of each level read by the last gt_query_batch (level depth =
+   * leaves); filled only while option "count_unique" is on */
+  int64_t unique_rows[GT_MAX_LEVELS];
+} gt_stats;
+
+/* Build the index (paper Sec. 2: pools of the binary-splitting tree, created
+ * offline; explicit pool sums replace the prefix sums of Eq. 1).
+ *   feats_dev  [n x d] features of type `dtype`; every value finite and >= 0.
+ *   capacity   number of leaves; 0 = smallest power of two >= n, else a power
+ *              of two >= n.  Room for later inserts.
+ *   pool_formats  bit mask of gt_pool (GT_POOL_F32 is always built).
+ * Copies the features; the index owns all its device memory until
+ * gt_destroy.  Synchronises `stream` (validation result).  Errors:
+ * INVALID_ARG (d < 1 or d > 4096, n < 0, n > capacity, capacity not a power of
+ * two, dtype), INVALID_INPUT, OUT_OF_MEMORY, DEVICE. */
+gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dtype,
+                        int64_t capacity, uint32_t pool_formats, void* stream,
+                        gt_index** out);
+
+/* Append n_new vectors (paper Sec. 4, streaming setting: the database grows
+ * between queries).  Ids n..n+n_new-1 are assigned in order; *first_id_out
+ * (host, may be NULL) receives n.  Every pool on a root-to-leaf path of a new
+ * vector is re-derived from its two children, so the index equals one built
+ * from scratch over the same rows.  Queries issued after this call returns see
+ * the new vectors.  Synchronises `stream`.  Errors: CAPACITY (n + n_new >
+ * capacity), INVALID_INPUT (index unchanged), DEVICE. */
+gt_status gt_insert(gt_index* index, const void* feats_dev, int64_t n_new, void* stream,
+                    int64_t* first_id_out);
+
+/* Range query by the level-wise binary-splitting walk (paper Sec. 2, Alg. 1,
+ * visited one level per round as analysed in Sec. 5).
+ *   q_dev      [nq x d] float32 queries, finite and >= 0.
+ *   rho_host   [nq] float64 thresholds.  rho <= 0 returns every non-zero row.
+ *   fmt        pool format for the walk (must have been built).
+ *   offsets_dev [nq + 1] int64: query b's results are ids[offsets[b] ..
+ *              offsets[b+1]).
+ *   ids_dev    [max_results] int64, ascending within each query.
+ *   sims_dev   [max_results] float32 cosines: the float32 value, or the
+ *              float64 value rounded to float32 where it was re-decided.
+ *   total_out  host: number of results.
+ * Membership is decided exactly as the float64 definition
+ *   cos = dot / (sqrt(qq) * sqrt(ff)),  sums sequential over k,
+ * so the id sets equal a float64 brute-force scan; a zero query or row never
+ * matches.  Synchronises `stream` once (result count).  On
+ * GT_ERR_RESULT_OVERFLOW, *total_out holds the required max_results and
+ * offsets_dev is valid; ids/sims are not written.  Other errors:
+ * INVALID_ARG (format not built, d too large for the format), INVALID_INPUT
+ * (a NaN/Inf/negative query value), OUT_OF_MEMORY, DEVICE. */
+gt_status gt_query_batch(gt_index* index, const float* q_dev, int32_t nq, const double* rho_host,
+                         gt_pool fmt, int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
+                         float* sims_dev, int64_t* total_out, void* stream);
+
+/* Exhaustive baseline (the paper's Exh, Sec. 4): every (query, vector) dot
+ * product by a float32 matrix-core GEMM with a threshold epilogue, followed by
+ * the same exact test as gt_query_batch, so results are identical to it.
+ * Arguments, synchronisation and errors as gt_query_batch. */
+gt_status gt_exhaustive(gt_index* index, const float* q_dev, int32_t nq, const double* rho_host,
+                        int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
+                        float* sims_dev, int64_t* total_out, void* stream);
+
+/* Counters of the index and of its last query call.  Synchronises the device
+ * stream of the last call.  Errors: INVALID_ARG. */
+gt_status gt_get_stats(const gt_index* index, gt_stats* out);
+
+/* Copies stored pool sums of one tree level to host memory (inspection and
+ * tests).  level in [0, depth]; level == depth gives the float32 leaf rows.
+ * Rows first .. first+count-1 of the level, each d_pad values:
+ *   GT_POOL_F32 -> float32 master sums (upward-rounded, >= the exact sums),
+ *   GT_POOL_BF16 -> uint16 bfloat16 codes, GT_POOL_FP8E4M3 -> uint8 e4m3 codes
+ *   (value = decoded code * 2^fp8_exp[level], see gt_stats).
+ * host_out must hold count * d_pad elements of that type.  Synchronises the
+ * device.  Errors: INVALID_ARG (range, format not built), DEVICE. */
+gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int64_t count,
+                        gt_pool fmt, void* host_out);
+
+/* Runtime knobs (benchmarking and tests; results never depend on them):
+ *   "profile"     0/1: time kernel groups with HIP events (gt_stats.ms_*)
+ *   "head_level"  first tested level, 0..depth-1 (-1 = automatic)
+ *   "grid"        workgroups of the persistent walk kernels (0 = one per CU)
+ *   "count_unique" 0/1: count distinct rows read per level (gt_stats.unique_rows);
+ *                 adds atomics to the walk, for measurement runs only
+ * Errors: INVALID_ARG for an unknown key or a value out of range. */
+gt_status gt_set_option(gt_index* index, const char* key, int64_t value);
+
+/* Frees every device allocation of the index.  NULL is ignored. */
+void gt_destroy(gt_index* index);
+
+/* Message for the last error on the calling thread ("" if none).  The string
+ * stays valid until the next call on this thread. */
+const char* gt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GT_H */

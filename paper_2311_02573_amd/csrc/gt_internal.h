@@ -1,0 +1,195 @@
+// Internal structures of the index and the launch wrappers of its kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "gt.h"
+
+namespace gt {
+
+constexpr int kWalkThreads = 512;     // threads per workgroup of the walk kernels
+constexpr int kQueriesPerTile16 = 64; // queries per tile for 16/8-bit pools
+constexpr int kQueriesPerTileF32 = 32;
+constexpr int kMaxTiles = 1024;       // tiles per call (64K queries)
+constexpr int kGroupEntries = 16;     // frontier entries per wave step (32 child rows)
+
+// Largest padded dimension each walk format supports (query tile in LDS).
+constexpr int kMaxDpBf16 = 1152, kMaxDpFp8 = 2304, kMaxDpF32 = 1152;
+
+enum : uint32_t { HIT_ACCEPT = 1u, HIT_BAND = 2u, HIT_REJECT = 3u };
+
+struct Hit {           // one candidate (query, vector) pair
+  uint32_t q, id;
+  float sim;
+  uint32_t flag;
+};
+
+// Counters written by the device during a query call.  Zeroed at call start.
+struct DevCounters {
+  unsigned long long nhits;         // candidates produced (may exceed capacity)
+  unsigned long long ncand;         // exhaustive-GEMM candidate pairs
+  unsigned long long total;         // results after the recheck
+  unsigned long long leaf_pairs;
+  unsigned long long rechecked;
+  unsigned int err;                 // invalid query input seen
+  unsigned int pad;
+  unsigned long long pairs[GT_MAX_LEVELS];
+};
+
+// Arguments of one level step of the frontier walk (parents at `level`,
+// children at `level + 1`).
+struct WalkLevelArgs {
+  int level, dense, nt, dp, cap;
+  const void* child_rows;   // first row of level+1 in the pool format
+  const uint32_t* in_node;
+  const uint64_t* in_mask;
+  const uint32_t* in_count;
+  uint32_t* out_node;
+  uint64_t* out_mask;
+  uint32_t* out_count;
+  const uint64_t* tile_mask;
+  const void* qtile;        // [nt * TQ * dp] queries in the pool format
+  const float* thr;         // [nt * TQ] lowered thresholds tau'
+  const int* qexp;          // [nt * TQ] float8 query scale exponents
+  int lexp;                 // float8 scale exponent of level+1
+  unsigned long long* stat_pairs;
+  uint32_t* bitmap;         // optional: one bit per tree row read
+  int64_t bit_base;         // tree row of node 0 of level+1
+};
+
+struct LeafArgs {
+  int level, dense, nt, dp, cap, tq;
+  const uint32_t* in_node;
+  const uint64_t* in_mask;
+  const uint32_t* in_count;
+  const uint64_t* tile_mask;
+  const float* leaves;      // [capacity x dp] float32
+  const float* invn_f;      // [capacity]
+  const float* qf;          // [nt * tq x dp] float32 queries
+  const float* invn_q;      // [nt * tq]
+  const double* rho;        // [nt * tq]
+  int64_t n_epoch;
+  Hit* hits;
+  unsigned long long hit_cap;
+  unsigned int* qcount;     // [nt * tq] accepted results per query
+  DevCounters* ctr;
+  uint32_t* bitmap;         // optional: one bit per tree row read
+  int64_t bit_base;         // tree row of leaf 0
+};
+
+struct Index {
+  int device = 0;
+  int n_cu = 256;
+  int64_t n = 0, cap = 0;
+  int d = 0, dp = 0, depth = 0;
+  gt_dtype dtype = GT_F32;
+  uint32_t formats = 0;
+  uint64_t epoch = 0;
+  int head_level = -1;       // -1: automatic
+  int grid = 0;              // 0: one workgroup per CU
+  bool profile = false;
+  bool count_unique = false;
+  bool counted = false;      // bitmap holds the last call's rows
+  uint32_t* bitmap = nullptr;
+  double m_min = 0.0;        // host copy
+
+  // device memory of the tree
+  float* leaves = nullptr;   // [cap x dp]
+  float* invn = nullptr;     // [cap]
+  double* ff = nullptr;      // [cap] canonical squared norms
+  double* d_mmin = nullptr;  // device copy of m_min (as a double)
+  float* master = nullptr;   // levels 0..depth-1, level l at row (2^l - 1)
+  uint16_t* pbf16 = nullptr;
+  uint8_t* pfp8 = nullptr;
+  int* d_lexp = nullptr;     // [depth + 1] float8 scale exponents per level
+  int lexp[GT_MAX_LEVELS] = {0};
+  float* d_levelmax = nullptr;
+  unsigned int* d_flags = nullptr;  // [depth + 1] float8 overflow flags per level
+
+  // per-call work buffers (grown on demand)
+  int nt_alloc = 0;
+  int nq_alloc = 0;
+  uint32_t* fr_node[2] = {nullptr, nullptr};
+  uint64_t* fr_mask[2] = {nullptr, nullptr};
+  int64_t fr_cap = 0;        // entries per tile per buffer
+  uint32_t* lvl_count = nullptr;    // [(depth + 1) x kMaxTiles]
+  uint64_t* tile_mask = nullptr;    // [kMaxTiles]
+  float* qf = nullptr;       // [nq_pad x dp]
+  uint16_t* qbf = nullptr;
+  uint8_t* q8 = nullptr;
+  int* qexp = nullptr;
+  float* invn_q = nullptr;
+  double* qq = nullptr;
+  double* rho = nullptr;
+  float* thr = nullptr;
+  float* thr_gemm = nullptr;
+  float* nf = nullptr;       // [cap] float32 norms rounded down (GEMM epilogue)
+  unsigned int* qcount = nullptr;
+  unsigned int* qcursor = nullptr;
+  int64_t* offs = nullptr;   // [nq + 1] internal offsets
+  Hit* hits = nullptr;
+  int64_t hit_cap = 0;
+  uint2* cand = nullptr;     // exhaustive candidates
+  int64_t cand_cap = 0;
+  uint32_t* out_id = nullptr;    // sorted staging
+  float* out_sim = nullptr;
+  uint32_t* tmp_id = nullptr;
+  float* tmp_sim = nullptr;
+  int64_t out_cap = 0;
+  DevCounters* ctr = nullptr;
+  DevCounters* h_ctr = nullptr;  // pinned
+  double* h_rho = nullptr;       // pinned staging for thresholds
+  int h_rho_cap = 0;
+  int64_t bytes = 0;
+
+  // stats of the last call
+  int last_nq = 0, last_nt = 0, last_fmt = 0, last_head = 0;
+  double ms[7] = {0};
+  int frontier_launches = 0;
+};
+
+// ---- launch wrappers (kernels in k_build.hip, k_walk.hip, k_exhaustive.hip) ----
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
+hipError_t launch_ingest(const void* src, int dtype, int64_t rows, int d, int dp, float* leaves,
+                         double* ff, float* invn, float* nf, double* mmin, unsigned int* err,
+                         hipStream_t s);
+hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, int dp,
+                              int64_t first, hipStream_t s);
+hipError_t launch_level_max(const float* rows, int64_t nrows, int dp, float* out_max, hipStream_t s);
+hipError_t launch_quant_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
+hipError_t launch_quant_fp8(const float* src, uint8_t* dst, int64_t count, int lexp,
+                            unsigned int* overflow, hipStream_t s);
+hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, const double* rho,
+                             const double* mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
+                             float* invn_q, double* qq, float* thr, float* thr_gemm,
+                             uint64_t* tile_mask, unsigned int* err, int nq_pad, hipStream_t s);
+hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s);
+hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s);
+hipError_t launch_recheck(Hit* hits, const unsigned long long* nhits, unsigned long long cap,
+                          const float* qf, const float* leaves, int d, int dp, const double* qq,
+                          const double* ff, const double* rho, unsigned int* qcount,
+                          DevCounters* ctr, hipStream_t s);
+hipError_t launch_scan_offsets(const unsigned int* qcount, int nq, int64_t* offs_internal,
+                               int64_t* offs_out, DevCounters* ctr, hipStream_t s);
+hipError_t launch_scatter(const Hit* hits, const unsigned long long* nhits, unsigned long long cap,
+                          const int64_t* offs, unsigned int* cursor, uint32_t* out_id,
+                          float* out_sim, hipStream_t s);
+hipError_t launch_sort_segments(const int64_t* offs, int nq, uint32_t* id, float* sim,
+                                uint32_t* tmp_id, float* tmp_sim, int64_t* ids_out,
+                                float* sims_out, hipStream_t s);
+hipError_t launch_exhaustive_gemm(const float* qf, int nq_pad, const float* leaves, int64_t n,
+                                  int dp, const float* thr_gemm, const float* nf, uint2* cand,
+                                  unsigned long long cand_cap, DevCounters* ctr, int nq,
+                                  hipStream_t s);
+hipError_t launch_pair_check(const uint2* cand, const unsigned long long* ncand,
+                             unsigned long long cap, const float* qf, const float* leaves,
+                             const float* invn_q, const float* invn_f, const double* rho, int dp,
+                             Hit* hits, unsigned long long hit_cap, unsigned int* qcount,
+                             DevCounters* ctr, int grid, hipStream_t s);
+hipError_t launch_insert_paths(float* master, const float* leaves, int depth, int dp, int64_t lo,
+                               int64_t hi, uint16_t* pbf16, uint8_t* pfp8, const int* lexp,
+                               unsigned int* flags, hipStream_t s);
+
+}  // namespace gt

@@ -1,0 +1,127 @@
+// Device-side numerics shared by the kernels: upward-rounded conversions and
+// additions, and the fixed-order float32 dot product of the exact leaf test.
+//
+// Soundness of pruning rests on three facts (paper Sec. 2, sum pooling):
+//  (1) every stored pool value is >= the exact sum of its members' values,
+//  (2) every stored query value is >= the query value,
+//  (3) all values are >= 0,
+// so the real dot product of the stored vectors is >= q . f_i for every member
+// i.  The helpers here provide (1) and (2) by rounding toward +infinity.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gt {
+
+// Next float32 above a finite x >= 0.
+__device__ __forceinline__ float next_up_nonneg(float x) {
+  return __uint_as_float(__float_as_uint(x) + 1u);
+}
+
+// a + b rounded toward +infinity, for finite a, b >= 0.  TwoSum (Knuth) gives
+// the exact error of the round-to-nearest sum; a positive error means the
+// nearest sum lies below the exact one.
+__device__ __forceinline__ float add_up(float a, float b) {
+  float s = __fadd_rn(a, b);
+  float bv = __fsub_rn(s, a);
+  float av = __fsub_rn(s, bv);
+  float err = __fadd_rn(__fsub_rn(a, av), __fsub_rn(b, bv));
+  return err > 0.0f ? next_up_nonneg(s) : s;
+}
+
+// Least bfloat16 >= x for finite x >= 0.  Values below the smallest normal
+// (2^-126) go to that normal, so no subnormal reaches the matrix cores.
+__device__ __forceinline__ uint16_t bf16_up(float x) {
+  uint32_t u = __float_as_uint(x);
+  if (u != 0u && u < 0x00800000u) u = 0x00800000u;
+  uint32_t hi = u >> 16;
+  if (u & 0xFFFFu) hi += 1u;
+  return (uint16_t)hi;
+}
+
+// Least OCP float8 e4m3 value >= x, for x >= 0 given exactly as a double.
+// e4m3: exponent bias 7, 3 mantissa bits, subnormals m * 2^-9, largest finite
+// 448 (code 0x7E); 0x7F is NaN.  Returns 0xFF when x > 448.
+__device__ __forceinline__ uint32_t e4m3_up(double x) {
+  if (!(x > 0.0)) return 0u;
+  if (x > 448.0) return 0xFFu;
+  int e;
+  double m = frexp(x, &e);            // x = m * 2^e, m in [0.5, 1)
+  int E = e - 1;                      // x = (2m) * 2^E
+  if (E < -6) {                       // below the smallest normal 2^-6
+    double k = ceil(ldexp(x, 9));     // multiples of 2^-9; k == 8 is 2^-6 = code 8
+    return (uint32_t)k;
+  }
+  int mm = (int)ceil(ldexp(2.0 * m - 1.0, 3));
+  if (mm == 8) { mm = 0; E += 1; }
+  uint32_t code = (uint32_t)(((E + 7) << 3) | mm);
+  return code > 0x7Eu ? 0xFFu : code;
+}
+
+// float64 -> float32 rounded toward -infinity (thresholds are lowered, never
+// raised).
+__device__ __forceinline__ float f64_to_f32_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = __uint_as_float(f > 0.0f ? __float_as_uint(f) - 1u
+                                                 : (f == 0.0f ? 0x80000001u : __float_as_uint(f) + 1u));
+  return f;
+}
+
+// Relative slack of a float32-accumulated pool score of K non-negative terms:
+// every rounding inside the accumulation (any rounding mode, including
+// truncation) loses less than one unit in the last place, 2^-23 relative to a
+// partial sum that never exceeds the final sum, so the computed score is at
+// least (1 - (K + 1) * 2^-23) times the real one.  A factor of two on top.
+__host__ __device__ __forceinline__ double pool_slack(int K) {
+  return (double)(K + 2) * 0x1p-22;
+}
+
+// Fixed-order float32 dot product of two rows, wave-wide (64 lanes).  Lane l
+// owns elements [c*1024 + 16 l, +16) of chunk c; products are summed pairwise
+// within the lane, chunks in order, then a butterfly over lanes.  The result
+// is identical in every lane and depends only on the two rows.
+// Bound: |error| <= (5 + (chunks - 1) + 6) * 2^-24 * exact sum.
+__device__ __forceinline__ float wave_dot_f32(const float* __restrict__ a,
+                                              const float* __restrict__ b, int dp, int lane) {
+  float acc = 0.0f;
+  for (int c = 0; c * 1024 < dp; ++c) {
+    int base = c * 1024 + lane * 16;
+    float p[16];
+    if (base < dp) {
+      const float4* a4 = reinterpret_cast<const float4*>(a + base);
+      const float4* b4 = reinterpret_cast<const float4*>(b + base);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float4 x = a4[v], y = b4[v];
+        p[4 * v + 0] = __fmul_rn(x.x, y.x);
+        p[4 * v + 1] = __fmul_rn(x.y, y.y);
+        p[4 * v + 2] = __fmul_rn(x.z, y.z);
+        p[4 * v + 3] = __fmul_rn(x.w, y.w);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) p[v] = 0.0f;
+    }
+#pragma unroll
+    for (int w = 1; w < 16; w *= 2)
+#pragma unroll
+      for (int i = 0; i < 16; i += 2 * w) p[i] = __fadd_rn(p[i], p[i + w]);
+    acc = (c == 0) ? p[0] : __fadd_rn(acc, p[0]);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) acc = __fadd_rn(acc, __shfl_xor(acc, m, 64));
+  return acc;
+}
+
+// Canonical float64 cosine: sequential sums over k, then
+// dot / (sqrt(qq) * sqrt(ff)).  Products of float32 values are exact in
+// float64, so fused or separate multiply-add give the same value.
+__device__ __forceinline__ double canonical_cos(const float* __restrict__ q,
+                                                const float* __restrict__ f, int d, double qq,
+                                                double ff) {
+  double dot = 0.0;
+  for (int k = 0; k < d; ++k) dot = __dadd_rn(dot, __dmul_rn((double)q[k], (double)f[k]));
+  return __ddiv_rn(dot, __dmul_rn(__dsqrt_rn(qq), __dsqrt_rn(ff)));
+}
+
+}  // namespace gt

@@ -1,0 +1,270 @@
+// Index construction and query preparation kernels.
+//
+// Tree layout (paper Sec. 2: the pools of binary splitting are fixed offline):
+// level l (0 = root) has 2^l pools; pool j of level l covers leaves
+// [j * 2^(depth-l), (j+1) * 2^(depth-l)).  Level l is stored at rows
+// (2^l - 1) .. (2^(l+1) - 2) of one array, so the two children of a pool are
+// adjacent rows.  Leaves (level `depth`) are the float32 feature rows.
+#include <float.h>
+#include <hip/hip_fp16.h>
+#include <math.h>
+
+#include "gt_internal.h"
+#include "gt_numerics.h"
+
+namespace gt {
+
+namespace {
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__device__ __forceinline__ float load_feature(const void* src, int dtype, int64_t idx) {
+  if (dtype == GT_F16) return __half2float(reinterpret_cast<const __half*>(src)[idx]);
+  if (dtype == GT_BF16)
+    return __uint_as_float((uint32_t)reinterpret_cast<const uint16_t*>(src)[idx] << 16);
+  return reinterpret_cast<const float*>(src)[idx];
+}
+
+// One workgroup of 64 threads per 64 rows.  Column tiles of 64 are staged
+// through LDS so that loads and stores are coalesced while each thread still
+// sums its own row sequentially in float64 (the canonical squared norm).
+__global__ __launch_bounds__(64) void k_ingest(const void* src, int dtype, int64_t rows, int d,
+                                               int dp, float* leaves, double* ff, float* invn,
+                                               float* nf, double* mmin, unsigned int* err) {
+  __shared__ float tile[64][65];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  double acc = 0.0;
+  bool bad = false;
+  for (int c0 = 0; c0 < dp; c0 += 64) {
+    const int c = c0 + t;
+    for (int r = 0; r < 64; ++r) {
+      const int64_t row = r0 + r;
+      if (row >= rows) break;
+      float v = 0.0f;
+      if (c < d) {
+        v = load_feature(src, dtype, row * d + c);
+        if (!(v >= 0.0f) || isinf(v)) bad = true;
+      }
+      if (c < dp) leaves[row * dp + c] = v;
+      tile[r][t] = v;
+    }
+    __syncthreads();
+    if (r0 + t < rows) {
+      const int lim = min(64, d - c0);
+      for (int k = 0; k < lim; ++k) {
+        const double x = (double)tile[t][k];
+        acc = __dadd_rn(acc, __dmul_rn(x, x));
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(err, 1u);
+  const int64_t row = r0 + t;
+  if (row < rows) {
+    ff[row] = acc;
+    const double nrm = __dsqrt_rn(acc);
+    invn[row] = acc > 0.0 ? (float)__ddiv_rn(1.0, nrm) : 0.0f;
+    nf[row] = acc > 0.0 ? f64_to_f32_down(nrm) : 0.0f;
+    if (acc > 0.0 && !bad)
+      atomicMin(reinterpret_cast<unsigned long long*>(mmin),
+                (unsigned long long)__double_as_longlong(nrm));
+  }
+}
+
+// parent = children summed with upward rounding, 4 columns per thread.
+__global__ void k_build_level(const float* __restrict__ child, float* __restrict__ parent,
+                              int64_t first, int64_t nodes, int dp) {
+  const int q = dp / 4;
+  const int64_t total = nodes * q;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = first + i / q;
+    const int k = (int)(i % q) * 4;
+    const float4 a = *reinterpret_cast<const float4*>(child + (2 * j) * dp + k);
+    const float4 b = *reinterpret_cast<const float4*>(child + (2 * j + 1) * dp + k);
+    float4 s;
+    s.x = add_up(a.x, b.x);
+    s.y = add_up(a.y, b.y);
+    s.z = add_up(a.z, b.z);
+    s.w = add_up(a.w, b.w);
+    *reinterpret_cast<float4*>(parent + j * dp + k) = s;
+  }
+}
+
+__global__ void k_level_max(const float* __restrict__ rows, int64_t count, float* out) {
+  float m = 0.0f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, rows[i]);
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(reinterpret_cast<unsigned int*>(out), __float_as_uint(m));
+}
+
+__global__ void k_quant_bf16(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                             int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = bf16_up(src[i]);
+}
+
+__global__ void k_quant_fp8(const float* __restrict__ src, uint8_t* __restrict__ dst,
+                            int64_t count, int lexp, unsigned int* overflow) {
+  bool over = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t c = e4m3_up(ldexp((double)src[i], -lexp));
+    if (c == 0xFFu) {
+      over = true;
+      c = 0x7Eu;
+    }
+    dst[i] = (uint8_t)c;
+  }
+  if (over) atomicOr(overflow, 1u);
+}
+
+// One workgroup of 256 threads per (padded) query.
+__global__ __launch_bounds__(256) void k_query_prep(
+    const float* __restrict__ q, int nq, int d, int dp, int tq, const double* __restrict__ rho,
+    const double* __restrict__ mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
+    float* invn_q, double* qq_out, float* thr, float* thr_gemm, uint64_t* tile_mask,
+    unsigned int* err) {
+  __shared__ float qs[4096];
+  __shared__ float red[4];
+  __shared__ double qq_s;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const bool real = b < nq;
+  float mx = 0.0f;
+  bool bad = false;
+  for (int k = t; k < d; k += blockDim.x) {
+    const float v = real ? q[(int64_t)b * d + k] : 0.0f;
+    if (!(v >= 0.0f) || isinf(v)) bad = true;
+    qs[k] = v;
+    mx = fmaxf(mx, v);
+  }
+  if (bad) atomicOr(err, 1u);
+  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  if ((t & 63) == 0) red[t >> 6] = mx;
+  __syncthreads();
+  if (t == 0) {
+    double acc = 0.0;
+    for (int k = 0; k < d; ++k) acc = __dadd_rn(acc, __dmul_rn((double)qs[k], (double)qs[k]));
+    qq_s = acc;
+    red[0] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  }
+  __syncthreads();
+  const double qq = qq_s;
+  const float qmax = red[0];
+  // float8 query scale 2^e with qmax / 2^e in (224, 448]
+  int e = 0;
+  if (qmax > 0.0f) {
+    int ex;
+    const double m = frexp((double)qmax / 448.0, &ex);
+    e = (m == 0.5) ? ex - 1 : ex;
+  }
+  for (int k = t; k < dp; k += blockDim.x) {
+    const float v = k < d ? qs[k] : 0.0f;
+    qf[(int64_t)b * dp + k] = v;
+    qbf[(int64_t)b * dp + k] = bf16_up(v);
+    q8[(int64_t)b * dp + k] = (uint8_t)e4m3_up(ldexp((double)v, -e));
+  }
+  if (t == 0) {
+    const bool live = real && qq > 0.0 && !bad;
+    const double nrm = __dsqrt_rn(qq);
+    qq_out[b] = qq;
+    qexp[b] = e;
+    invn_q[b] = qq > 0.0 ? (float)__ddiv_rn(1.0, nrm) : 0.0f;
+    float th = INFINITY, tg = INFINITY;
+    if (live) {
+      const double r = rho[b];
+      if (r <= 0.0) {
+        th = -INFINITY;
+        tg = -INFINITY;
+      } else {
+        // cos >= rho with the float64 definition implies the real cosine is
+        // at least rho * (1 - 2e-11) for d <= 4096; every member norm is at
+        // least m_min, so a pool holding a neighbour scores >= tau (reals).
+        const double reff = r * (1.0 - 4e-11);
+        const double tau = reff * nrm * (*mmin) * (1.0 - 4e-11);
+        const double sl = pool_slack(dp);
+        th = f64_to_f32_down(tau * (1.0 - sl) - 2.0 * dp * 0x1p-126);
+        tg = f64_to_f32_down(reff * nrm * (1.0 - 4e-11) * (1.0 - sl));
+      }
+      atomicOr(reinterpret_cast<unsigned long long*>(&tile_mask[b / tq]),
+               (unsigned long long)(1ull << (b % tq)));
+    }
+    thr[b] = th;
+    thr_gemm[b] = tg;
+  }
+}
+
+inline int grid_for(int64_t work, int block) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ingest(const void* src, int dtype, int64_t rows, int d, int dp, float* leaves,
+                         double* ff, float* invn, float* nf, double* mmin, unsigned int* err,
+                         hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ingest, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, src, dtype, rows,
+                     d, dp, leaves, ff, invn, nf, mmin, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, int dp,
+                              int64_t first, hipStream_t s) {
+  if (nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_level, dim3(grid_for(nodes * (dp / 4), 256)), dim3(256), 0, s, child,
+                     parent, first, nodes, dp);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_max(const float* rows, int64_t nrows, int dp, float* out_max,
+                            hipStream_t s) {
+  const int64_t count = nrows * dp;
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_max, dim3(grid_for(count, 256 * 8)), dim3(256), 0, s, rows, count,
+                     out_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quant_bf16, dim3(grid_for(count, 256 * 4)), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_fp8(const float* src, uint8_t* dst, int64_t count, int lexp,
+                            unsigned int* overflow, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quant_fp8, dim3(grid_for(count, 256 * 4)), dim3(256), 0, s, src, dst, count,
+                     lexp, overflow);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, const double* rho,
+                             const double* mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
+                             float* invn_q, double* qq, float* thr, float* thr_gemm,
+                             uint64_t* tile_mask, unsigned int* err, int nq_pad, hipStream_t s) {
+  if (nq_pad <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_query_prep, dim3(nq_pad), dim3(256), 0, s, q, nq, d, dp, tq, rho, mmin, qf,
+                     qbf, q8, qexp, invn_q, qq, thr, thr_gemm, tile_mask, err);
+  return hipGetLastError();
+}
+
+}  // namespace gt

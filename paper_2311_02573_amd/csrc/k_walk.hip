@@ -1,0 +1,582 @@
+// The level-wise binary-splitting walk (paper Sec. 2, Alg. 1; one level per
+// round as in the pruning analysis of Sec. 5), the exact leaf test, the
+// float64 recheck and the result compaction.
+//
+// Frontier representation.  Queries are grouped in tiles of TQ (64 for bf16 /
+// float8 pools, 32 for float32 pools).  The frontier of a tile at level l is a
+// list of entries (pool j, mask): pool j of level l survived for the queries
+// whose bits are set.  One level step reads both children of every entry (two
+// adjacent rows), scores them against all TQ queries of the tile with matrix
+// cores, and keeps child c for query b iff the parent's bit b is set and the
+// score reaches the query's lowered threshold tau'_b.  Children with a
+// non-empty mask are appended to the tile's next frontier.
+#include <math.h>
+
+#include "gt_internal.h"
+#include "gt_numerics.h"
+
+namespace gt {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+template <int FMT>
+struct WalkFmt;
+template <>
+struct WalkFmt<GT_POOL_F32> {
+  static constexpr int TQ = kQueriesPerTileF32, ESZ = 4, MAXDP = kMaxDpF32;
+};
+template <>
+struct WalkFmt<GT_POOL_BF16> {
+  static constexpr int TQ = kQueriesPerTile16, ESZ = 2, MAXDP = kMaxDpBf16;
+};
+template <>
+struct WalkFmt<GT_POOL_FP8E4M3> {
+  static constexpr int TQ = kQueriesPerTile16, ESZ = 1, MAXDP = kMaxDpFp8;
+};
+
+// One 16-byte slice of a row (per lane) against the same slice of a query:
+// bf16: one 32x32x16 step; float8: two 32x32x16 steps; float32: four 32x32x2
+// steps.  Lanes 0-31 and 32-63 carry different slices, and the A (pool) and B
+// (query) operands of a lane always hold the same dimensions, so the sum over
+// all slices is the full dot product whatever order the hardware uses inside.
+template <int FMT>
+__device__ __forceinline__ void mma16(const uint4& a, const uint4& b, f32x16& acc);
+
+template <>
+__device__ __forceinline__ void mma16<GT_POOL_BF16>(const uint4& a, const uint4& b, f32x16& acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void mma16<GT_POOL_FP8E4M3>(const uint4& a, const uint4& b,
+                                                       f32x16& acc) {
+  const long a0 = (long)(((unsigned long)a.y << 32) | a.x);
+  const long a1 = (long)(((unsigned long)a.w << 32) | a.z);
+  const long b0 = (long)(((unsigned long)b.y << 32) | b.x);
+  const long b1 = (long)(((unsigned long)b.w << 32) | b.z);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a0, b0, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a1, b1, acc, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void mma16<GT_POOL_F32>(const uint4& a, const uint4& b, f32x16& acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+}
+
+// Exclusive prefix over tiles of ceil(count / per) (per = 1: entry counts),
+// computed by wave 0 into pre[0..nt]; nt <= 1024.
+__device__ __forceinline__ void tile_prefix(uint32_t* pre, int nt, int dense, int level,
+                                            const uint64_t* tile_mask, const uint32_t* in_count,
+                                            uint32_t per) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int per_lane = (nt + 63) / 64;
+    const int t0 = lane * per_lane;
+    uint32_t loc[16];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int t = t0 + i;
+      uint32_t c = 0;
+      if (i < per_lane && t < nt) {
+        c = dense ? (tile_mask[t] ? (1u << level) : 0u) : in_count[t];
+        c = (c + per - 1) / per;
+      }
+      loc[i] = sum;
+      sum += c;
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const uint32_t excl = incl - sum;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int t = t0 + i;
+      if (i < per_lane && t < nt) pre[t] = excl + loc[i];
+    }
+    if (lane == 63) pre[nt] = incl;
+  }
+  __syncthreads();
+}
+
+// Index t of the tile with pre[t] <= g < pre[t + 1] (pre ascending).
+__device__ __forceinline__ int find_tile(const uint32_t* pre, int nt, uint32_t g) {
+  int lo = 0, hi = nt;  // invariant pre[lo] <= g < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint4 ld_global16(const unsigned char* p) {
+  return *reinterpret_cast<const uint4*>(p);
+}
+__device__ __forceinline__ uint4 ld_lds16(const unsigned char* p) {
+  return *reinterpret_cast<const uint4*>(p);
+}
+
+constexpr int kPipe = 8;  // 16-byte slices per lane fetched ahead
+
+template <int FMT>
+__global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a) {
+  using F = WalkFmt<FMT>;
+  constexpr int TQ = F::TQ;
+  constexpr int NB = TQ / 32;  // 32-query column blocks
+  __shared__ __attribute__((aligned(16))) unsigned char qlds[TQ * (F::MAXDP * F::ESZ + 16)];
+  __shared__ uint32_t gpre[kMaxTiles + 1];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int rowbytes = a.dp * F::ESZ;
+  const int rs = rowbytes + 16;           // LDS row stride (bank spread)
+  const int nslices = rowbytes / 32;      // 16-byte slices per lane half
+  const int r = lane & 31, half = lane >> 5;
+
+  tile_prefix(gpre, a.nt, a.dense, a.level, a.tile_mask, a.in_count, kGroupEntries);
+  const uint32_t gtot = gpre[a.nt];
+  const uint32_t g0 = (uint32_t)(((uint64_t)gtot * blockIdx.x) / gridDim.x);
+  const uint32_t g1 = (uint32_t)(((uint64_t)gtot * (blockIdx.x + 1)) / gridDim.x);
+  unsigned long long pairs = 0;
+  if (g0 < g1) {
+    int t = find_tile(gpre, a.nt, g0);
+    uint32_t g = g0;
+    while (g < g1) {
+      const uint32_t tend = gpre[t + 1];
+      if (tend <= g) {
+        ++t;
+        continue;
+      }
+      const uint32_t send = tend < g1 ? tend : g1;
+      // stage the tile's queries in LDS
+      __syncthreads();
+      {
+        const unsigned char* src =
+            reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)t * TQ * rowbytes;
+        const int vec_per_row = rowbytes / 16;
+        for (int v = tid; v < TQ * vec_per_row; v += blockDim.x) {
+          const int row = v / vec_per_row, col = v - row * vec_per_row;
+          *reinterpret_cast<uint4*>(qlds + row * rs + col * 16) =
+              *reinterpret_cast<const uint4*>(src + (size_t)row * rowbytes + col * 16);
+        }
+      }
+      __syncthreads();
+      float thr[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int qi = t * TQ + 32 * j + r;
+        float th = a.thr[qi];
+        if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+        thr[j] = th;
+      }
+      const uint32_t count = a.dense ? (1u << a.level) : a.in_count[t];
+      const uint64_t tmask = a.tile_mask[t];
+      const size_t tbase = (size_t)t * a.cap;
+
+      for (uint32_t gg = g + wave; gg < send; gg += nwaves) {
+        const uint32_t gl = gg - gpre[t];
+        const uint32_t e = gl * kGroupEntries + (r >> 1);
+        const bool valid = e < count;
+        uint32_t p;
+        uint64_t pm;
+        if (a.dense) {
+          p = valid ? e : gl * kGroupEntries;
+          pm = valid ? tmask : 0ull;
+        } else {
+          const uint32_t ee = valid ? e : gl * kGroupEntries;
+          p = a.in_node[tbase + ee];
+          pm = valid ? a.in_mask[tbase + ee] : 0ull;
+        }
+        const uint32_t child = 2u * p + (uint32_t)(r & 1);
+        if (a.bitmap && lane < 32 && pm) {
+          const uint64_t row = (uint64_t)a.bit_base + child;
+          atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
+        }
+        const unsigned char* arow = reinterpret_cast<const unsigned char*>(a.child_rows) +
+                                    (size_t)child * rowbytes + 16 * half;
+        const unsigned char* brow = qlds + r * rs + 16 * half;
+
+        f32x16 acc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) acc[j][i] = 0.0f;
+
+        uint4 bufA[kPipe], bufB[kPipe];
+#pragma unroll
+        for (int u = 0; u < kPipe; ++u)
+          if (u < nslices) bufA[u] = ld_global16(arow + 32 * u);
+        for (int s0 = 0; s0 < nslices; s0 += 2 * kPipe) {
+#pragma unroll
+          for (int u = 0; u < kPipe; ++u)
+            if (s0 + kPipe + u < nslices) bufB[u] = ld_global16(arow + 32 * (s0 + kPipe + u));
+#pragma unroll
+          for (int u = 0; u < kPipe; ++u)
+            if (s0 + u < nslices) {
+#pragma unroll
+              for (int j = 0; j < NB; ++j)
+                mma16<FMT>(bufA[u], ld_lds16(brow + j * 32 * rs + 32 * (s0 + u)), acc[j]);
+            }
+#pragma unroll
+          for (int u = 0; u < kPipe; ++u)
+            if (s0 + 2 * kPipe + u < nslices) bufA[u] = ld_global16(arow + 32 * (s0 + 2 * kPipe + u));
+#pragma unroll
+          for (int u = 0; u < kPipe; ++u)
+            if (s0 + kPipe + u < nslices) {
+#pragma unroll
+              for (int j = 0; j < NB; ++j)
+                mma16<FMT>(bufB[u], ld_lds16(brow + j * 32 * rs + 32 * (s0 + kPipe + u)), acc[j]);
+            }
+        }
+
+        // 32x32 accumulator layout: register i of lane l holds
+        // row 8*(i/4) + 4*(l/32) + (i%4), column l%32.
+        uint64_t mine = 0ull;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const uint64_t b0 = __ballot(acc[0][i] >= thr[0]);
+          uint64_t lo, hi;
+          if (NB == 2) {
+            const uint64_t b1 = __ballot(acc[NB - 1][i] >= thr[NB - 1]);
+            lo = (b0 & 0xffffffffull) | (b1 << 32);
+            hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
+          } else {
+            lo = b0 & 0xffffffffull;
+            hi = b0 >> 32;
+          }
+          const int row0 = 8 * (i >> 2) + (i & 3);
+          if (lane == row0) mine = lo;
+          if (lane == row0 + 4) mine = hi;
+        }
+        mine &= pm;  // lane r < 32 holds child row r, whose parent mask is pm
+        if (lane < 32) pairs += (unsigned long long)__popcll(pm);
+        const bool emit = lane < 32 && mine != 0ull;
+        const uint64_t eb = __ballot(emit);
+        if (eb) {
+          const uint32_t cnt = (uint32_t)__popcll(eb);
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&a.out_count[t], cnt);
+          base = __shfl(base, 0, 64);
+          if (emit) {
+            const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
+            a.out_node[tbase + pos] = child;
+            a.out_mask[tbase + pos] = mine;
+          }
+        }
+      }
+      g = send;
+      ++t;
+    }
+  }
+  if (a.stat_pairs) {
+    for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
+    if (lane == 0 && pairs) atomicAdd(a.stat_pairs, pairs);
+  }
+}
+
+// Exact leaf test: entries (pool p at level depth-1, mask) -> vectors 2p, 2p+1
+// for every query of the mask.  One wave per entry.
+__global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
+  __shared__ uint32_t epre[kMaxTiles + 1];
+  const int lane = threadIdx.x & 63;
+  tile_prefix(epre, a.nt, a.dense, a.level, a.tile_mask, a.in_count, 1);
+  const uint32_t etot = epre[a.nt];
+  const uint32_t nw = blockDim.x >> 6;
+  unsigned long long npairs = 0;
+  for (uint32_t idx = blockIdx.x * nw + (threadIdx.x >> 6); idx < etot; idx += gridDim.x * nw) {
+    const int t = find_tile(epre, a.nt, idx);
+    const uint32_t e = idx - epre[t];
+    uint32_t p;
+    uint64_t pm;
+    if (a.dense) {
+      p = e;
+      pm = a.tile_mask[t];
+    } else {
+      p = a.in_node[(size_t)t * a.cap + e];
+      pm = a.in_mask[(size_t)t * a.cap + e];
+    }
+#pragma unroll 1
+    for (int c = 0; c < 2; ++c) {
+      const int64_t i = 2 * (int64_t)p + c;
+      if (i >= a.n_epoch) continue;
+      const float invf = a.invn_f[i];
+      if (invf == 0.0f) continue;  // zero vector: cosine undefined, never a member
+      const float* frow = a.leaves + i * a.dp;
+      if (a.bitmap && lane == 0 && pm) {
+        const uint64_t row = (uint64_t)a.bit_base + (uint64_t)i;
+        atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
+      }
+      uint64_t m = pm;
+      while (m) {
+        const int b = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1ull;
+        const int qg = t * a.tq + b;
+        const float dot = wave_dot_f32(a.qf + (size_t)qg * a.dp, frow, a.dp, lane);
+        const float cs = __fmul_rn(__fmul_rn(dot, a.invn_q[qg]), invf);
+        ++npairs;
+        if (lane == 0) {
+          const double rho = a.rho[qg];
+          const double c64 = (double)cs;
+          uint32_t flag = 0;
+          if (c64 >= rho + 1e-5) flag = HIT_ACCEPT;
+          else if (c64 > rho - 1e-5) flag = HIT_BAND;
+          if (flag) {
+            const unsigned long long slot = atomicAdd(&a.ctr->nhits, 1ull);
+            if (slot < a.hit_cap) {
+              Hit h;
+              h.q = (uint32_t)qg;
+              h.id = (uint32_t)i;
+              h.sim = cs;
+              h.flag = flag;
+              a.hits[slot] = h;
+            }
+            if (flag == HIT_ACCEPT) atomicAdd(&a.qcount[qg], 1u);
+          }
+        }
+      }
+    }
+  }
+  if (lane == 0 && npairs) atomicAdd(&a.ctr->leaf_pairs, npairs);
+}
+
+// Band candidates (|cos32 - rho| < 1e-5) are re-decided with the canonical
+// float64 cosine; one thread per candidate.
+__global__ void k_recheck(Hit* hits, const unsigned long long* nhits, unsigned long long cap,
+                          const float* __restrict__ qf, const float* __restrict__ leaves, int d,
+                          int dp, const double* __restrict__ qq, const double* __restrict__ ff,
+                          const double* __restrict__ rho, unsigned int* qcount, DevCounters* ctr) {
+  const unsigned long long n = *nhits < cap ? *nhits : cap;
+  for (unsigned long long h = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; h < n;
+       h += (unsigned long long)gridDim.x * blockDim.x) {
+    Hit x = hits[h];
+    if (x.flag != HIT_BAND) continue;
+    const double c = canonical_cos(qf + (size_t)x.q * dp, leaves + (size_t)x.id * dp, d, qq[x.q],
+                                   ff[x.id]);
+    atomicAdd(&ctr->rechecked, 1ull);
+    if (c >= rho[x.q]) {
+      x.flag = HIT_ACCEPT;
+      x.sim = (float)c;
+      atomicAdd(&qcount[x.q], 1u);
+    } else {
+      x.flag = HIT_REJECT;
+    }
+    hits[h] = x;
+  }
+}
+
+// Exclusive scan of per-query counts -> offsets (one workgroup of 1024).
+__global__ __launch_bounds__(1024) void k_scan_offsets(const unsigned int* qcount, int nq,
+                                                       int64_t* offs, int64_t* offs_out,
+                                                       DevCounters* ctr) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (nq + 1023) / 1024;
+  const int lo = t * per, hi = min(nq, lo + per);
+  int64_t s = 0;
+  for (int i = lo; i < hi; ++i) s += qcount[i];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;
+  for (int i = lo; i < hi; ++i) {
+    offs[i] = run;
+    if (offs_out) offs_out[i] = run;
+    run += qcount[i];
+  }
+  if (t == 1023) {
+    offs[nq] = part[1023];
+    if (offs_out) offs_out[nq] = part[1023];
+    ctr->total = (unsigned long long)part[1023];
+  }
+}
+
+__global__ void k_scatter(const Hit* hits, const unsigned long long* nhits, unsigned long long cap,
+                          const int64_t* offs, unsigned int* cursor, uint32_t* out_id,
+                          float* out_sim) {
+  const unsigned long long n = *nhits < cap ? *nhits : cap;
+  for (unsigned long long h = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; h < n;
+       h += (unsigned long long)gridDim.x * blockDim.x) {
+    const Hit x = hits[h];
+    if (x.flag != HIT_ACCEPT) continue;
+    const int64_t pos = offs[x.q] + atomicAdd(&cursor[x.q], 1u);
+    out_id[pos] = x.id;
+    out_sim[pos] = x.sim;
+  }
+}
+
+// Sort each query's results by id.  Up to 4096: bitonic sort in LDS; larger
+// segments: stable 4-bit LSD radix sort by the same workgroup.
+__global__ __launch_bounds__(256) void k_sort_segments(const int64_t* offs, uint32_t* id,
+                                                       float* sim, uint32_t* tmp_id,
+                                                       float* tmp_sim, int64_t* ids_out,
+                                                       float* sims_out) {
+  __shared__ uint32_t key[4096];
+  __shared__ float val[4096];
+  __shared__ uint32_t hist[16 * 256];
+  __shared__ uint32_t tot[256];
+  const int q = blockIdx.x, t = threadIdx.x;
+  const int64_t lo = offs[q], n = offs[q + 1] - lo;
+  if (n <= 0) return;
+  if (n <= 4096) {
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = t; i < P; i += 256) {
+      key[i] = i < n ? id[lo + i] : 0xFFFFFFFFu;
+      val[i] = i < n ? sim[lo + i] : 0.0f;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = t; i < P; i += 256) {
+          const int ixj = i ^ j;
+          if (ixj > i) {
+            const bool asc = (i & k) == 0;
+            const uint32_t ki = key[i], kj = key[ixj];
+            if ((ki > kj) == asc) {
+              key[i] = kj;
+              key[ixj] = ki;
+              const float v = val[i];
+              val[i] = val[ixj];
+              val[ixj] = v;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = t; i < n; i += 256) {
+      ids_out[lo + i] = (int64_t)key[i];
+      sims_out[lo + i] = val[i];
+    }
+    return;
+  }
+  uint32_t *si = id + lo, *di = tmp_id + lo;
+  float *sv = sim + lo, *dv = tmp_sim + lo;
+  const int64_t chunk = (n + 255) / 256;
+  const int64_t a0 = min(n, t * chunk), a1 = min(n, a0 + chunk);
+  for (int pass = 0; pass < 8; ++pass) {
+    const int sh = 4 * pass;
+    uint32_t h[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) h[b] = 0;
+    for (int64_t i = a0; i < a1; ++i) h[(si[i] >> sh) & 15u]++;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) hist[b * 256 + t] = h[b];
+    __syncthreads();
+    // exclusive scan over hist in (digit, thread) order: thread t owns 16 slots
+    uint32_t s = 0;
+    for (int k = 0; k < 16; ++k) s += hist[t * 16 + k];
+    tot[t] = s;
+    __syncthreads();
+    if (t == 0) {
+      uint32_t run = 0;
+      for (int k = 0; k < 256; ++k) {
+        const uint32_t v = tot[k];
+        tot[k] = run;
+        run += v;
+      }
+    }
+    __syncthreads();
+    uint32_t run = tot[t];
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t v = hist[t * 16 + k];
+      hist[t * 16 + k] = run;
+      run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 16; ++b) h[b] = hist[b * 256 + t];
+    for (int64_t i = a0; i < a1; ++i) {
+      const uint32_t k = si[i];
+      const uint32_t pos = h[(k >> sh) & 15u]++;
+      di[pos] = k;
+      dv[pos] = sv[i];
+    }
+    __syncthreads();
+    uint32_t* ti = si; si = di; di = ti;
+    float* tv = sv; sv = dv; dv = tv;
+  }
+  for (int64_t i = t; i < n; i += 256) {
+    ids_out[lo + i] = (int64_t)si[i];
+    sims_out[lo + i] = sv[i];
+  }
+}
+
+int grid_for(int64_t work, int block) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s) {
+  switch (fmt) {
+    case GT_POOL_BF16:
+      hipLaunchKernelGGL(k_walk_level<GT_POOL_BF16>, dim3(grid), dim3(kWalkThreads), 0, s, a);
+      break;
+    case GT_POOL_FP8E4M3:
+      hipLaunchKernelGGL(k_walk_level<GT_POOL_FP8E4M3>, dim3(grid), dim3(kWalkThreads), 0, s, a);
+      break;
+    case GT_POOL_F32:
+      hipLaunchKernelGGL(k_walk_level<GT_POOL_F32>, dim3(grid), dim3(kWalkThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_leaf, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_recheck(Hit* hits, const unsigned long long* nhits, unsigned long long cap,
+                          const float* qf, const float* leaves, int d, int dp, const double* qq,
+                          const double* ff, const double* rho, unsigned int* qcount,
+                          DevCounters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, s, hits, nhits, cap, qf, leaves, d, dp, qq,
+                     ff, rho, qcount, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_offsets(const unsigned int* qcount, int nq, int64_t* offs_internal,
+                               int64_t* offs_out, DevCounters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, qcount, nq, offs_internal, offs_out,
+                     ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const Hit* hits, const unsigned long long* nhits, unsigned long long cap,
+                          const int64_t* offs, unsigned int* cursor, uint32_t* out_id,
+                          float* out_sim, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(1024), dim3(256), 0, s, hits, nhits, cap, offs, cursor, out_id,
+                     out_sim);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_segments(const int64_t* offs, int nq, uint32_t* id, float* sim,
+                                uint32_t* tmp_id, float* tmp_sim, int64_t* ids_out,
+                                float* sims_out, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_segments, dim3(nq), dim3(256), 0, s, offs, id, sim, tmp_id, tmp_sim,
+                     ids_out, sims_out);
+  return hipGetLastError();
+}
+
+}  // namespace gt

@@ -1,0 +1,224 @@
+"""Python binding of the C interface in include/gt.h (argument marshalling only).
+
+Every computation runs in the HIP kernels of libgt.so; PyTorch only provides
+device memory and the current stream.  There is no CPU fallback: importing
+this module raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgt.so")
+
+GT_OK, GT_ERR_INVALID_ARG, GT_ERR_INVALID_INPUT, GT_ERR_OUT_OF_MEMORY = 0, 1, 2, 3
+GT_ERR_CAPACITY, GT_ERR_RESULT_OVERFLOW, GT_ERR_DEVICE = 4, 5, 6
+STATUS_NAMES = {0: "GT_OK", 1: "GT_ERR_INVALID_ARG", 2: "GT_ERR_INVALID_INPUT",
+                3: "GT_ERR_OUT_OF_MEMORY", 4: "GT_ERR_CAPACITY", 5: "GT_ERR_RESULT_OVERFLOW",
+                6: "GT_ERR_DEVICE"}
+GT_F32, GT_F16, GT_BF16 = 0, 1, 2
+POOL_F32, POOL_BF16, POOL_FP8 = 1, 2, 4
+POOLS = {"f32": POOL_F32, "bf16": POOL_BF16, "fp8": POOL_FP8}
+GT_MAX_LEVELS = 40
+
+EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_exhaustive", "gt_get_stats",
+           "gt_read_pools", "gt_set_option", "gt_destroy", "gt_last_error"]
+
+
+class GTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class GTStats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("capacity", ctypes.c_int64),
+        ("d", ctypes.c_int32), ("d_pad", ctypes.c_int32),
+        ("depth", ctypes.c_int32), ("head_level", ctypes.c_int32),
+        ("pool_formats", ctypes.c_uint32),
+        ("m_min", ctypes.c_double), ("epoch", ctypes.c_uint64),
+        ("bytes_device", ctypes.c_int64),
+        ("last_nq", ctypes.c_int32), ("last_tiles", ctypes.c_int32), ("last_format", ctypes.c_int32),
+        ("entries", ctypes.c_int64 * GT_MAX_LEVELS), ("pairs", ctypes.c_int64 * GT_MAX_LEVELS),
+        ("leaf_pairs", ctypes.c_int64), ("candidates", ctypes.c_int64),
+        ("rechecked", ctypes.c_int64), ("results", ctypes.c_int64),
+        ("ms_prep", ctypes.c_double), ("ms_frontier", ctypes.c_double),
+        ("ms_leaf", ctypes.c_double), ("ms_recheck", ctypes.c_double),
+        ("ms_compact", ctypes.c_double), ("ms_gemm", ctypes.c_double),
+        ("ms_total", ctypes.c_double), ("frontier_launches", ctypes.c_int32),
+        ("fp8_exp", ctypes.c_int32 * GT_MAX_LEVELS),
+        ("unique_rows", ctypes.c_int64 * GT_MAX_LEVELS),
+    ]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2311_02573_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+    st = ctypes.c_int
+    lib.gt_build_tree.restype = st
+    lib.gt_build_tree.argtypes = [vp, i64, i32, ctypes.c_int, i64, u32, vp, ctypes.POINTER(vp)]
+    lib.gt_insert.restype = st
+    lib.gt_insert.argtypes = [vp, vp, i64, vp, ctypes.POINTER(i64)]
+    lib.gt_query_batch.restype = st
+    lib.gt_query_batch.argtypes = [vp, vp, i32, vp, ctypes.c_int, i64, vp, vp, vp,
+                                   ctypes.POINTER(i64), vp]
+    lib.gt_exhaustive.restype = st
+    lib.gt_exhaustive.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp]
+    lib.gt_get_stats.restype = st
+    lib.gt_get_stats.argtypes = [vp, ctypes.POINTER(GTStats)]
+    lib.gt_read_pools.restype = st
+    lib.gt_read_pools.argtypes = [vp, i32, i64, i64, ctypes.c_int, vp]
+    lib.gt_set_option.restype = st
+    lib.gt_set_option.argtypes = [vp, ctypes.c_char_p, i64]
+    lib.gt_destroy.restype = None
+    lib.gt_destroy.argtypes = [vp]
+    lib.gt_last_error.restype = ctypes.c_char_p
+    lib.gt_last_error.argtypes = []
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _check(status: int):
+    if status != GT_OK:
+        raise GTError(status, lib().gt_last_error().decode())
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+_DTYPES = {torch.float32: GT_F32, torch.float16: GT_F16, torch.bfloat16: GT_BF16}
+
+
+class Results:
+    """CSR results on the device: query b has ids[offsets[b]:offsets[b+1]]."""
+
+    def __init__(self, offsets, ids, sims, total):
+        self.offsets, self.ids, self.sims, self.total = offsets, ids, sims, total
+
+    def to_lists(self):
+        off = self.offsets.cpu().numpy()
+        ids = self.ids[: self.total].cpu().numpy()
+        sims = self.sims[: self.total].cpu().numpy()
+        return [(ids[off[b]:off[b + 1]], sims[off[b]:off[b + 1]]) for b in range(len(off) - 1)]
+
+
+class GTIndex:
+    """Owns one gt_index.  `feats` is a [n, d] CUDA tensor (float32/16, bfloat16)."""
+
+    def __init__(self, feats: torch.Tensor, capacity: int = 0, pools=("f32", "bf16", "fp8"),
+                 stream=None):
+        if not feats.is_cuda:
+            raise ValueError("features must be a device tensor")
+        if feats.dtype not in _DTYPES:
+            raise ValueError(f"unsupported dtype {feats.dtype}")
+        feats = feats.contiguous()
+        self.dtype = feats.dtype
+        self.d = feats.shape[1]
+        mask = 0
+        for p in pools:
+            mask |= POOLS[p]
+        h = ctypes.c_void_p()
+        _check(lib().gt_build_tree(ctypes.c_void_p(feats.data_ptr()), feats.shape[0], self.d,
+                                   _DTYPES[feats.dtype], capacity, mask, _stream_ptr(stream),
+                                   ctypes.byref(h)))
+        self._h = h
+        self._max_results = 1 << 16
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def insert(self, feats: torch.Tensor, stream=None) -> int:
+        if feats.dtype != self.dtype or feats.shape[1] != self.d:
+            raise ValueError("inserted rows must match the index dtype and dimension")
+        feats = feats.contiguous()
+        first = ctypes.c_int64(-1)
+        _check(lib().gt_insert(self._h, ctypes.c_void_p(feats.data_ptr()), feats.shape[0],
+                               _stream_ptr(stream), ctypes.byref(first)))
+        return first.value
+
+    def _run(self, fn, q, rho, max_results, stream, *extra):
+        q = q.contiguous()
+        if q.dtype != torch.float32 or not q.is_cuda:
+            raise ValueError("queries must be a float32 device tensor")
+        nq = q.shape[0]
+        rho_np = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, dtype=np.float64), (nq,)))
+        rho_arr = ctypes.c_void_p(rho_np.ctypes.data)
+        dev = q.device
+        offsets = torch.empty(nq + 1, dtype=torch.int64, device=dev)
+        cap = max_results if max_results is not None else self._max_results
+        total = ctypes.c_int64(0)
+        while True:
+            ids = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+            sims = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+            st = fn(self._h, ctypes.c_void_p(q.data_ptr()), nq, rho_arr, *extra, cap,
+                    ctypes.c_void_p(offsets.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                    ctypes.c_void_p(sims.data_ptr()), ctypes.byref(total), _stream_ptr(stream))
+            if st == GT_ERR_RESULT_OVERFLOW and max_results is None:
+                cap = total.value
+                self._max_results = max(self._max_results, cap)
+                continue
+            _check(st)
+            return Results(offsets, ids, sims, total.value)
+
+    def query(self, q: torch.Tensor, rho, pool: str = "bf16", max_results=None, stream=None):
+        """Level-wise group-testing walk.  rho: float or per-query sequence."""
+        return self._run(lambda h, qp, nq, r, fmt, *rest: lib().gt_query_batch(h, qp, nq, r, fmt, *rest),
+                         q, rho, max_results, stream, POOLS[pool])
+
+    def exhaustive(self, q: torch.Tensor, rho, max_results=None, stream=None):
+        return self._run(lambda h, qp, nq, r, *rest: lib().gt_exhaustive(h, qp, nq, r, *rest),
+                         q, rho, max_results, stream)
+
+    def stats(self) -> dict:
+        s = GTStats()
+        _check(lib().gt_get_stats(self._h, ctypes.byref(s)))
+        out = {}
+        for name, _ in GTStats._fields_:
+            v = getattr(s, name)
+            out[name] = list(v) if name in ("entries", "pairs", "fp8_exp", "unique_rows") else v
+        return out
+
+    def read_pools(self, level: int, first: int = 0, count: int | None = None, pool: str = "f32"):
+        """Stored pool rows of one level as a numpy array [count, d_pad]."""
+        st = self.stats()
+        if count is None:
+            count = (1 << level) - first
+        dt = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}[pool]
+        out = np.empty((count, st["d_pad"]), dtype=dt)
+        _check(lib().gt_read_pools(self._h, level, first, count, POOLS[pool],
+                                   ctypes.c_void_p(out.ctypes.data)))
+        return out
+
+    def set_option(self, key: str, value: int):
+        _check(lib().gt_set_option(self._h, key.encode(), int(value)))
