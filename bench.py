@@ -125,6 +125,11 @@ def main():
     uniq_leaves = int(su["unique_rows"][su["depth"]])
     pool_bytes = uniq_pools * dp * esz
     leaf_bytes = uniq_leaves * dp * 4
+    h, D = su["head_level"], su["depth"]
+    entries = list(su["entries"])
+    entries[h] = (1 << h) * su["last_tiles"]
+    raw_pool = sum(entries[l] for l in range(h, D - 1)) * 2 * dp * esz
+    raw_leaf = entries[D - 1] * 2 * dp * 4
     achieved = pool_bytes / (ms_front * 1e-3) / 1e9 if ms_front > 0 else None
     roofline = {
         "kernel": f"k_walk_level<{args.pool}>",
@@ -135,9 +140,13 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": None,
         "algorithmic_bytes_per_batch": pool_bytes,
+        "raw_bytes_per_batch": raw_pool,
+        "raw_GBps": round(raw_pool / (ms_front * 1e-3) / 1e9, 1) if ms_front > 0 else None,
+        "entries_per_level": {l: entries[l] for l in range(h, D)},
+        "unique_rows_per_level": {l: su["unique_rows"][l] for l in range(h + 1, D + 1)},
         "launches_per_batch": launches,
         "avg_launch_ms": ms_front / max(1, launches),
-        "leaf_kernel": {"bytes": leaf_bytes, "ms": ms_leaf,
+        "leaf_kernel": {"bytes": leaf_bytes, "raw_bytes": raw_leaf, "ms": ms_leaf,
                         "GBps": round(leaf_bytes / (ms_leaf * 1e-3) / 1e9, 1) if ms_leaf > 0 else None},
     }
 

@@ -118,6 +118,7 @@ void free_all(Index* ix) {
   dfree(ix, &ix->qcursor, nqa);
   dfree(ix, &ix->offs, nqa + 1);
   dfree(ix, &ix->hits, (size_t)ix->hit_cap);
+  dfree(ix, &ix->band_idx, (size_t)ix->hit_cap);
   dfree(ix, &ix->cand, (size_t)ix->cand_cap);
   dfree(ix, &ix->out_id, (size_t)ix->out_cap);
   dfree(ix, &ix->out_sim, (size_t)ix->out_cap);
@@ -220,15 +221,19 @@ gt_status ensure_query_buffers(Index* ix, int nq_pad, int nt) {
   if (!ix->hits) {
     ix->hit_cap = int64_t(1) << 20;
     TRY(dalloc(ix, &ix->hits, (size_t)ix->hit_cap));
+    TRY(dalloc(ix, &ix->band_idx, (size_t)ix->hit_cap));
   }
   return GT_OK;
 }
 
 gt_status grow_hits(Index* ix, int64_t need) {
   dfree(ix, &ix->hits, (size_t)ix->hit_cap);
+  dfree(ix, &ix->band_idx, (size_t)ix->hit_cap);
   ix->hit_cap = 0;
   const int64_t cap = need + need / 4 + 1024;
+  if (cap >= (int64_t(1) << 32)) return fail(GT_ERR_OUT_OF_MEMORY, "more than 2^32 candidates");
   TRY(dalloc(ix, &ix->hits, (size_t)cap));
+  TRY(dalloc(ix, &ix->band_idx, (size_t)cap));
   ix->hit_cap = cap;
   return GT_OK;
 }
@@ -321,9 +326,9 @@ gt_status finish_query(Index* ix, int nq, int nq_pad, int64_t max_results, int64
                        int64_t* ids, float* sims, int64_t* total_out, hipStream_t s, Timer& tm,
                        Rerun rerun, bool* cand_overflow = nullptr) {
   for (int attempt = 0;; ++attempt) {
-    HIPCHK(gt::launch_recheck(ix->hits, &ix->ctr->nhits, (unsigned long long)ix->hit_cap, ix->qf,
-                              ix->leaves, ix->d, ix->dp, ix->qq, ix->ff, ix->rho, ix->qcount,
-                              ix->ctr, s));
+    HIPCHK(gt::launch_recheck(ix->hits, ix->band_idx, &ix->ctr->nband,
+                              (unsigned long long)ix->hit_cap, ix->qf, ix->leaves, ix->d, ix->dp,
+                              ix->qq, ix->ff, ix->rho, ix->qcount, ix->ctr, s));
     tm.mark(4);
     HIPCHK(gt::launch_scan_offsets(ix->qcount, nq, ix->offs, offsets, ix->ctr, s));
     HIPCHK(hipMemcpyAsync(ix->h_ctr, ix->ctr, sizeof(gt::DevCounters), hipMemcpyDeviceToHost, s));
@@ -342,6 +347,7 @@ gt_status finish_query(Index* ix, int nq, int nq_pad, int64_t max_results, int64
     TRY(zero_dev(&ix->ctr->nhits, 8, s));
     TRY(zero_dev(&ix->ctr->leaf_pairs, 8, s));
     TRY(zero_dev(&ix->ctr->rechecked, 8, s));
+    TRY(zero_dev(&ix->ctr->nband, 8, s));
     TRY(rerun());
   }
   const int64_t total = (int64_t)ix->h_ctr->total;
@@ -656,6 +662,7 @@ gt_status gt_query_batch(gt_index* ix, const float* q_dev, int32_t nq, const dou
   la.bit_base = level_row(D);
   auto run_leaf = [&]() -> gt_status {
     la.hits = ix->hits;
+    la.band_idx = ix->band_idx;
     la.hit_cap = (unsigned long long)ix->hit_cap;
     if (ix->n > 0) HIPCHK(gt::launch_leaf(la, ix->n_cu * 4, s));
     return GT_OK;
@@ -715,8 +722,8 @@ gt_status gt_exhaustive(gt_index* ix, const float* q_dev, int32_t nq, const doub
     tm.mark(2);
     HIPCHK(gt::launch_pair_check(ix->cand, &ix->ctr->ncand, (unsigned long long)ix->cand_cap,
                                  ix->qf, ix->leaves, ix->invn_q, ix->invn, ix->rho, ix->dp,
-                                 ix->hits, (unsigned long long)ix->hit_cap, ix->qcount, ix->ctr,
-                                 ix->n_cu * 4, s));
+                                 ix->hits, (unsigned long long)ix->hit_cap, ix->band_idx,
+                                 ix->qcount, ix->ctr, ix->n_cu * 4, s));
     tm.mark(3);
     return GT_OK;
   };

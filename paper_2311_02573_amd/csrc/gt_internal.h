@@ -14,6 +14,7 @@ constexpr int kQueriesPerTile16 = 64; // queries per tile for 16/8-bit pools
 constexpr int kQueriesPerTileF32 = 32;
 constexpr int kMaxTiles = 1024;       // tiles per call (64K queries)
 constexpr int kGroupEntries = 16;     // frontier entries per wave step (32 child rows)
+constexpr int kHitStage = 192;        // per-wave LDS staging of candidate hits
 
 // Largest padded dimension each walk format supports (query tile in LDS).
 constexpr int kMaxDpBf16 = 1152, kMaxDpFp8 = 2304, kMaxDpF32 = 1152;
@@ -33,6 +34,7 @@ struct DevCounters {
   unsigned long long total;         // results after the recheck
   unsigned long long leaf_pairs;
   unsigned long long rechecked;
+  unsigned long long nband;         // candidates within the recheck band
   unsigned int err;                 // invalid query input seen
   unsigned int pad;
   unsigned long long pairs[GT_MAX_LEVELS];
@@ -73,6 +75,7 @@ struct LeafArgs {
   int64_t n_epoch;
   Hit* hits;
   unsigned long long hit_cap;
+  uint32_t* band_idx;       // [hit_cap] indices of band candidates in hits
   unsigned int* qcount;     // [nt * tq] accepted results per query
   DevCounters* ctr;
   uint32_t* bitmap;         // optional: one bit per tree row read
@@ -130,6 +133,7 @@ struct Index {
   unsigned int* qcursor = nullptr;
   int64_t* offs = nullptr;   // [nq + 1] internal offsets
   Hit* hits = nullptr;
+  uint32_t* band_idx = nullptr;
   int64_t hit_cap = 0;
   uint2* cand = nullptr;     // exhaustive candidates
   int64_t cand_cap = 0;
@@ -167,10 +171,10 @@ hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, cons
                              uint64_t* tile_mask, unsigned int* err, int nq_pad, hipStream_t s);
 hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s);
-hipError_t launch_recheck(Hit* hits, const unsigned long long* nhits, unsigned long long cap,
-                          const float* qf, const float* leaves, int d, int dp, const double* qq,
-                          const double* ff, const double* rho, unsigned int* qcount,
-                          DevCounters* ctr, hipStream_t s);
+hipError_t launch_recheck(Hit* hits, const uint32_t* band_idx, const unsigned long long* nband,
+                          unsigned long long cap, const float* qf, const float* leaves, int d,
+                          int dp, const double* qq, const double* ff, const double* rho,
+                          unsigned int* qcount, DevCounters* ctr, hipStream_t s);
 hipError_t launch_scan_offsets(const unsigned int* qcount, int nq, int64_t* offs_internal,
                                int64_t* offs_out, DevCounters* ctr, hipStream_t s);
 hipError_t launch_scatter(const Hit* hits, const unsigned long long* nhits, unsigned long long cap,
@@ -186,8 +190,8 @@ hipError_t launch_exhaustive_gemm(const float* qf, int nq_pad, const float* leav
 hipError_t launch_pair_check(const uint2* cand, const unsigned long long* ncand,
                              unsigned long long cap, const float* qf, const float* leaves,
                              const float* invn_q, const float* invn_f, const double* rho, int dp,
-                             Hit* hits, unsigned long long hit_cap, unsigned int* qcount,
-                             DevCounters* ctr, int grid, hipStream_t s);
+                             Hit* hits, unsigned long long hit_cap, uint32_t* band_idx,
+                             unsigned int* qcount, DevCounters* ctr, int grid, hipStream_t s);
 hipError_t launch_insert_paths(float* master, const float* leaves, int depth, int dp, int64_t lo,
                                int64_t hi, uint16_t* pbf16, uint8_t* pfp8, const int* lexp,
                                unsigned int* flags, hipStream_t s);

@@ -113,6 +113,59 @@ __device__ __forceinline__ float wave_dot_f32(const float* __restrict__ a,
   return acc;
 }
 
+// Pairwise sum of the 16 products a[base + j] * b[base + j] (zero past dp) --
+// the in-lane part of wave_dot_f32.
+__device__ __forceinline__ float lane_partial16(const float* __restrict__ a,
+                                                const float* __restrict__ b, int base, int dp) {
+  float p[16];
+  if (base < dp) {
+    const float4* a4 = reinterpret_cast<const float4*>(a + base);
+    const float4* b4 = reinterpret_cast<const float4*>(b + base);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float4 x = a4[v], y = b4[v];
+      p[4 * v + 0] = __fmul_rn(x.x, y.x);
+      p[4 * v + 1] = __fmul_rn(x.y, y.y);
+      p[4 * v + 2] = __fmul_rn(x.z, y.z);
+      p[4 * v + 3] = __fmul_rn(x.w, y.w);
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) p[v] = 0.0f;
+  }
+#pragma unroll
+  for (int w = 1; w < 16; w *= 2)
+#pragma unroll
+    for (int i = 0; i < 16; i += 2 * w) p[i] = __fadd_rn(p[i], p[i + w]);
+  return p[0];
+}
+
+// Sums eight per-lane values over the 64 lanes with the same pairing as the
+// butterfly of wave_dot_f32 (partners at lane distance 32, 16, 8, 4, 2, 1),
+// so each sum is bit-identical to it, but with 10 shuffles instead of 48.
+// Lanes 8v .. 8v+7 receive the sum of value v.
+__device__ __forceinline__ float wave_reduce8(const float (&a)[8], int lane) {
+  const bool h = (lane >> 5) & 1, g = (lane >> 4) & 1, f = (lane >> 3) & 1;
+  float b[4], c[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float send = h ? a[j] : a[j + 4];
+    const float keep = h ? a[j + 4] : a[j];
+    b[j] = __fadd_rn(keep, __shfl_xor(send, 32, 64));
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float send = g ? b[j] : b[j + 2];
+    const float keep = g ? b[j + 2] : b[j];
+    c[j] = __fadd_rn(keep, __shfl_xor(send, 16, 64));
+  }
+  float dsum = __fadd_rn(f ? c[1] : c[0], __shfl_xor(f ? c[0] : c[1], 8, 64));
+  dsum = __fadd_rn(dsum, __shfl_xor(dsum, 4, 64));
+  dsum = __fadd_rn(dsum, __shfl_xor(dsum, 2, 64));
+  dsum = __fadd_rn(dsum, __shfl_xor(dsum, 1, 64));
+  return dsum;
+}
+
 // Canonical float64 cosine: sequential sums over k, then
 // dot / (sqrt(qq) * sqrt(ff)).  Products of float32 values are exact in
 // float64, so fused or separate multiply-add give the same value.

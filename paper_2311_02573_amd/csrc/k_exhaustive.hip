@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "gt_internal.h"
+#include "gt_device.h"
 #include "gt_numerics.h"
 
 namespace gt {
@@ -131,44 +132,60 @@ __global__ __launch_bounds__(256) void k_gemm_threshold(const float* __restrict_
     }
 }
 
-// Exact test of explicit (query, vector) pairs: one wave per pair, the same
-// float32 dot product and classification as the leaf test of the walk.
+// Exact test of explicit (query, vector) pairs: the same float32 dot product
+// (in-lane pairwise sums, then the lane reduction) and classification as the
+// leaf test of the walk, four pairs per wave at a time.
 __global__ __launch_bounds__(256) void k_pair_check(const uint2* cand, const unsigned long long* ncand,
                                                     unsigned long long cap, const float* qf,
                                                     const float* leaves, const float* invn_q,
                                                     const float* invn_f, const double* rho, int dp,
                                                     Hit* hits, unsigned long long hit_cap,
-                                                    unsigned int* qcount, DevCounters* ctr) {
-  const int lane = threadIdx.x & 63;
+                                                    uint32_t* band_idx, unsigned int* qcount,
+                                                    DevCounters* ctr) {
+  __shared__ Hit hstage[4][kHitStage];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const unsigned long long n = *ncand < cap ? *ncand : cap;
   const unsigned long long nw = blockDim.x >> 6;
+  Hit* buf = hstage[w];
+  int cnt = 0;
   unsigned long long npairs = 0;
-  for (unsigned long long p = blockIdx.x * nw + (threadIdx.x >> 6); p < n; p += gridDim.x * nw) {
-    const uint2 qr = cand[p];
-    const float invf = invn_f[qr.y];
-    const float dot = wave_dot_f32(qf + (size_t)qr.x * dp, leaves + (size_t)qr.y * dp, dp, lane);
-    const float cs = __fmul_rn(__fmul_rn(dot, invn_q[qr.x]), invf);
-    ++npairs;
-    if (lane == 0 && invf != 0.0f) {
-      const double r = rho[qr.x];
-      const double c64 = (double)cs;
-      uint32_t flag = 0;
-      if (c64 >= r + 1e-5) flag = HIT_ACCEPT;
-      else if (c64 > r - 1e-5) flag = HIT_BAND;
-      if (flag) {
-        const unsigned long long slot = atomicAdd(&ctr->nhits, 1ull);
-        if (slot < hit_cap) {
-          Hit h;
-          h.q = qr.x;
-          h.id = qr.y;
-          h.sim = cs;
-          h.flag = flag;
-          hits[slot] = h;
-        }
-        if (flag == HIT_ACCEPT) atomicAdd(&qcount[qr.x], 1u);
+  for (unsigned long long b0 = (blockIdx.x * nw + w) * 4ull; b0 < n; b0 += gridDim.x * nw * 4ull) {
+    uint2 pr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pr[k] = cand[b0 + k < n ? b0 + k : b0];
+    float acc[8];
+    for (int c = 0; c * 1024 < dp; ++c) {
+      const int base = c * 1024 + 16 * lane;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float v = lane_partial16(qf + (size_t)pr[k].x * dp, leaves + (size_t)pr[k].y * dp,
+                                       base, dp);
+        acc[k] = c == 0 ? v : __fadd_rn(acc[k], v);
+        acc[k + 4] = 0.0f;
       }
     }
+    const float dot = wave_reduce8(acc, lane);
+    const int v = lane >> 3;
+    const bool mine = (lane & 7) == 0 && v < 4 && b0 + v < n;
+    Hit h;
+    uint32_t flag = 0;
+    if (mine) {
+      const uint2 x = pr[v];
+      const float invf = invn_f[x.y];
+      const float cs = __fmul_rn(__fmul_rn(dot, invn_q[x.x]), invf);
+      flag = invf != 0.0f ? classify(cs, rho[x.x]) : 0u;
+      h.q = x.x;
+      h.id = x.y;
+      h.sim = cs;
+      h.flag = flag;
+      if (flag == HIT_ACCEPT) atomicAdd(&qcount[x.x], 1u);
+      ++npairs;
+    }
+    stage_hits(buf, cnt, flag != 0u, h, false, ctr, hits, hit_cap, band_idx, lane);
   }
+  Hit none;
+  stage_hits(buf, cnt, false, none, true, ctr, hits, hit_cap, band_idx, lane);
+  for (int o = 32; o >= 1; o >>= 1) npairs += __shfl_xor(npairs, o, 64);
   if (lane == 0 && npairs) atomicAdd(&ctr->leaf_pairs, npairs);
 }
 
@@ -189,10 +206,10 @@ hipError_t launch_exhaustive_gemm(const float* qf, int nq_pad, const float* leav
 hipError_t launch_pair_check(const uint2* cand, const unsigned long long* ncand,
                              unsigned long long cap, const float* qf, const float* leaves,
                              const float* invn_q, const float* invn_f, const double* rho, int dp,
-                             Hit* hits, unsigned long long hit_cap, unsigned int* qcount,
-                             DevCounters* ctr, int grid, hipStream_t s) {
+                             Hit* hits, unsigned long long hit_cap, uint32_t* band_idx,
+                             unsigned int* qcount, DevCounters* ctr, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_pair_check, dim3(grid), dim3(256), 0, s, cand, ncand, cap, qf, leaves, invn_q,
-                     invn_f, rho, dp, hits, hit_cap, qcount, ctr);
+                     invn_f, rho, dp, hits, hit_cap, band_idx, qcount, ctr);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include "gt_internal.h"
+#include "gt_device.h"
 #include "gt_numerics.h"
 
 namespace gt {
@@ -181,12 +182,11 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
       const uint64_t tmask = a.tile_mask[t];
       const size_t tbase = (size_t)t * a.cap;
 
-      for (uint32_t gg = g + wave; gg < send; gg += nwaves) {
+      // entry (pool, mask) of this lane's row in group gg of the tile
+      auto fetch = [&](uint32_t gg, uint32_t& p, uint64_t& pm) {
         const uint32_t gl = gg - gpre[t];
         const uint32_t e = gl * kGroupEntries + (r >> 1);
         const bool valid = e < count;
-        uint32_t p;
-        uint64_t pm;
         if (a.dense) {
           p = valid ? e : gl * kGroupEntries;
           pm = valid ? tmask : 0ull;
@@ -195,14 +195,35 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
           p = a.in_node[tbase + ee];
           pm = valid ? a.in_mask[tbase + ee] : 0ull;
         }
+      };
+      uint32_t np = 0;
+      uint64_t npm = 0ull;
+      if (g + wave < send) fetch(g + wave, np, npm);
+      // survivors of the previous group, written once their slots are known
+      bool pend = false;
+      uint32_t pend_child = 0;
+      uint64_t pend_mask = 0ull, pend_bal = 0ull;
+
+      for (uint32_t gg = g + wave; gg < send; gg += nwaves) {
+        const uint32_t p = np;
+        const uint64_t pm = npm;
         const uint32_t child = 2u * p + (uint32_t)(r & 1);
+        const unsigned char* arow = reinterpret_cast<const unsigned char*>(a.child_rows) +
+                                    (size_t)child * rowbytes + 16 * half;
+        const unsigned char* brow = qlds + r * rs + 16 * half;
+        uint4 bufA[kPipe], bufB[kPipe];
+#pragma unroll
+        for (int u = 0; u < kPipe; ++u)
+          if (u < nslices) bufA[u] = ld_global16(arow + 32 * u);
+        if (gg + nwaves < send) fetch(gg + nwaves, np, npm);
+        // reserve output slots for the previous group; the reply is awaited
+        // only after this group's matrix work
+        uint32_t pend_base = 0;
+        if (pend && lane == 0) pend_base = atomicAdd(&a.out_count[t], (uint32_t)__popcll(pend_bal));
         if (a.bitmap && lane < 32 && pm) {
           const uint64_t row = (uint64_t)a.bit_base + child;
           atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
         }
-        const unsigned char* arow = reinterpret_cast<const unsigned char*>(a.child_rows) +
-                                    (size_t)child * rowbytes + 16 * half;
-        const unsigned char* brow = qlds + r * rs + 16 * half;
 
         f32x16 acc[NB];
 #pragma unroll
@@ -210,10 +231,6 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
 #pragma unroll
           for (int i = 0; i < 16; ++i) acc[j][i] = 0.0f;
 
-        uint4 bufA[kPipe], bufB[kPipe];
-#pragma unroll
-        for (int u = 0; u < kPipe; ++u)
-          if (u < nslices) bufA[u] = ld_global16(arow + 32 * u);
         for (int s0 = 0; s0 < nslices; s0 += 2 * kPipe) {
 #pragma unroll
           for (int u = 0; u < kPipe; ++u)
@@ -237,6 +254,15 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
             }
         }
 
+        if (pend) {
+          pend_base = __shfl(pend_base, 0, 64);
+          if (lane < 32 && pend_mask) {
+            const uint32_t pos = pend_base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
+            a.out_node[tbase + pos] = pend_child;
+            a.out_mask[tbase + pos] = pend_mask;
+          }
+        }
+
         // 32x32 accumulator layout: register i of lane l holds
         // row 8*(i/4) + 4*(l/32) + (i%4), column l%32.
         uint64_t mine = 0ull;
@@ -258,18 +284,19 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
         }
         mine &= pm;  // lane r < 32 holds child row r, whose parent mask is pm
         if (lane < 32) pairs += (unsigned long long)__popcll(pm);
-        const bool emit = lane < 32 && mine != 0ull;
-        const uint64_t eb = __ballot(emit);
-        if (eb) {
-          const uint32_t cnt = (uint32_t)__popcll(eb);
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(&a.out_count[t], cnt);
-          base = __shfl(base, 0, 64);
-          if (emit) {
-            const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
-            a.out_node[tbase + pos] = child;
-            a.out_mask[tbase + pos] = mine;
-          }
+        pend_bal = __ballot(lane < 32 && mine != 0ull);
+        pend = pend_bal != 0ull;
+        pend_child = child;
+        pend_mask = lane < 32 ? mine : 0ull;
+      }
+      if (pend) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&a.out_count[t], (uint32_t)__popcll(pend_bal));
+        base = __shfl(base, 0, 64);
+        if (lane < 32 && pend_mask) {
+          const uint32_t pos = base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
+          a.out_node[tbase + pos] = pend_child;
+          a.out_mask[tbase + pos] = pend_mask;
         }
       }
       g = send;
@@ -282,16 +309,21 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
   }
 }
 
-// Exact leaf test: entries (pool p at level depth-1, mask) -> vectors 2p, 2p+1
-// for every query of the mask.  One wave per entry.
+// Exact leaf test: entries (pool p at level depth-1, mask) -> vectors 2p and
+// 2p+1 for every query of the mask.  One wave per entry; the queries of up to
+// four mask bits are fetched together and the eight dot products (2 vectors x
+// 4 queries) are reduced at once.
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
   __shared__ uint32_t epre[kMaxTiles + 1];
-  const int lane = threadIdx.x & 63;
+  __shared__ Hit hstage[4][kHitStage];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   tile_prefix(epre, a.nt, a.dense, a.level, a.tile_mask, a.in_count, 1);
   const uint32_t etot = epre[a.nt];
   const uint32_t nw = blockDim.x >> 6;
+  Hit* buf = hstage[w];
+  int cnt = 0;
   unsigned long long npairs = 0;
-  for (uint32_t idx = blockIdx.x * nw + (threadIdx.x >> 6); idx < etot; idx += gridDim.x * nw) {
+  for (uint32_t idx = blockIdx.x * nw + w; idx < etot; idx += gridDim.x * nw) {
     const int t = find_tile(epre, a.nt, idx);
     const uint32_t e = idx - epre[t];
     uint32_t p;
@@ -303,72 +335,120 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
       p = a.in_node[(size_t)t * a.cap + e];
       pm = a.in_mask[(size_t)t * a.cap + e];
     }
-#pragma unroll 1
-    for (int c = 0; c < 2; ++c) {
-      const int64_t i = 2 * (int64_t)p + c;
-      if (i >= a.n_epoch) continue;
-      const float invf = a.invn_f[i];
-      if (invf == 0.0f) continue;  // zero vector: cosine undefined, never a member
-      const float* frow = a.leaves + i * a.dp;
-      if (a.bitmap && lane == 0 && pm) {
-        const uint64_t row = (uint64_t)a.bit_base + (uint64_t)i;
-        atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
-      }
-      uint64_t m = pm;
-      while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1ull;
-        const int qg = t * a.tq + b;
-        const float dot = wave_dot_f32(a.qf + (size_t)qg * a.dp, frow, a.dp, lane);
-        const float cs = __fmul_rn(__fmul_rn(dot, a.invn_q[qg]), invf);
-        ++npairs;
-        if (lane == 0) {
-          const double rho = a.rho[qg];
-          const double c64 = (double)cs;
-          uint32_t flag = 0;
-          if (c64 >= rho + 1e-5) flag = HIT_ACCEPT;
-          else if (c64 > rho - 1e-5) flag = HIT_BAND;
-          if (flag) {
-            const unsigned long long slot = atomicAdd(&a.ctr->nhits, 1ull);
-            if (slot < a.hit_cap) {
-              Hit h;
-              h.q = (uint32_t)qg;
-              h.id = (uint32_t)i;
-              h.sim = cs;
-              h.flag = flag;
-              a.hits[slot] = h;
-            }
-            if (flag == HIT_ACCEPT) atomicAdd(&a.qcount[qg], 1u);
-          }
+    const int64_t i0 = 2 * (int64_t)p, i1 = i0 + 1;
+    const float inv0 = i0 < a.n_epoch ? a.invn_f[i0] : 0.0f;
+    const float inv1 = i1 < a.n_epoch ? a.invn_f[i1] : 0.0f;
+    // a zero vector has no cosine and is never a member
+    if ((inv0 == 0.0f && inv1 == 0.0f) || pm == 0ull) continue;
+    if (a.bitmap && lane == 0) {
+      if (inv0 != 0.0f) atomicOr(&a.bitmap[(a.bit_base + i0) >> 5], 1u << ((a.bit_base + i0) & 31));
+      if (inv1 != 0.0f) atomicOr(&a.bitmap[(a.bit_base + i1) >> 5], 1u << ((a.bit_base + i1) & 31));
+    }
+    const float* f0 = a.leaves + i0 * a.dp;
+    const float* f1 = a.leaves + i1 * a.dp;
+    uint64_t m = pm;
+    while (m) {
+      int qs[4];
+      int nb = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (m) {
+          qs[k] = t * a.tq + (__ffsll((unsigned long long)m) - 1);
+          m &= m - 1ull;
+          ++nb;
+        } else {
+          qs[k] = qs[0];
         }
       }
+      float acc[8];
+      for (int c = 0; c * 1024 < a.dp; ++c) {
+        const int base = c * 1024 + 16 * lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float* qrow = a.qf + (size_t)qs[k] * a.dp;
+          const float v0 = lane_partial16(qrow, f0, base, a.dp);
+          const float v1 = lane_partial16(qrow, f1, base, a.dp);
+          acc[2 * k] = c == 0 ? v0 : __fadd_rn(acc[2 * k], v0);
+          acc[2 * k + 1] = c == 0 ? v1 : __fadd_rn(acc[2 * k + 1], v1);
+        }
+      }
+      const float dot = wave_reduce8(acc, lane);
+      const int v = lane >> 3, k = v >> 1, leaf = v & 1;
+      const float invf = leaf ? inv1 : inv0;
+      const bool mine = (lane & 7) == 0 && k < nb && invf != 0.0f;
+      Hit h;
+      uint32_t flag = 0;
+      if (mine) {
+        const int qg = qs[k];
+        const float cs = __fmul_rn(__fmul_rn(dot, a.invn_q[qg]), invf);
+        flag = classify(cs, a.rho[qg]);
+        h.q = (uint32_t)qg;
+        h.id = (uint32_t)(leaf ? i1 : i0);
+        h.sim = cs;
+        h.flag = flag;
+        if (flag == HIT_ACCEPT) atomicAdd(&a.qcount[qg], 1u);
+        ++npairs;
+      }
+      stage_hits(buf, cnt, flag != 0u, h, false, a.ctr, a.hits, a.hit_cap, a.band_idx, lane);
     }
   }
+  Hit none;
+  stage_hits(buf, cnt, false, none, true, a.ctr, a.hits, a.hit_cap, a.band_idx, lane);
+  for (int o = 32; o >= 1; o >>= 1) npairs += __shfl_xor(npairs, o, 64);
   if (lane == 0 && npairs) atomicAdd(&a.ctr->leaf_pairs, npairs);
 }
 
-// Band candidates (|cos32 - rho| < 1e-5) are re-decided with the canonical
-// float64 cosine; one thread per candidate.
-__global__ void k_recheck(Hit* hits, const unsigned long long* nhits, unsigned long long cap,
-                          const float* __restrict__ qf, const float* __restrict__ leaves, int d,
-                          int dp, const double* __restrict__ qq, const double* __restrict__ ff,
-                          const double* __restrict__ rho, unsigned int* qcount, DevCounters* ctr) {
-  const unsigned long long n = *nhits < cap ? *nhits : cap;
-  for (unsigned long long h = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; h < n;
-       h += (unsigned long long)gridDim.x * blockDim.x) {
-    Hit x = hits[h];
-    if (x.flag != HIT_BAND) continue;
-    const double c = canonical_cos(qf + (size_t)x.q * dp, leaves + (size_t)x.id * dp, d, qq[x.q],
-                                   ff[x.id]);
-    atomicAdd(&ctr->rechecked, 1ull);
-    if (c >= rho[x.q]) {
-      x.flag = HIT_ACCEPT;
-      x.sim = (float)c;
-      atomicAdd(&qcount[x.q], 1u);
-    } else {
-      x.flag = HIT_REJECT;
+// Candidates within 1e-5 of rho are re-decided with the canonical float64
+// cosine, bit-identical to the oracle: the sum runs sequentially over k, lane
+// by lane (lane l holds elements [16 l, 16 l + 16) of each 1024-chunk, so lane
+// order is k order), one wave per candidate.
+__global__ __launch_bounds__(256) void k_recheck(Hit* hits, const uint32_t* band_idx,
+                                                 const unsigned long long* nband,
+                                                 unsigned long long cap,
+                                                 const float* __restrict__ qf,
+                                                 const float* __restrict__ leaves, int d, int dp,
+                                                 const double* __restrict__ qq,
+                                                 const double* __restrict__ ff,
+                                                 const double* __restrict__ rho,
+                                                 unsigned int* qcount, DevCounters* ctr) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long n = *nband < cap ? *nband : cap;
+  const unsigned long long nw = blockDim.x >> 6;
+  for (unsigned long long b = blockIdx.x * nw + (threadIdx.x >> 6); b < n; b += gridDim.x * nw) {
+    const uint32_t hi = band_idx[b];
+    Hit x = hits[hi];
+    const float* q = qf + (size_t)x.q * dp;
+    const float* f = leaves + (size_t)x.id * dp;
+    double s = 0.0;
+    for (int c = 0; c * 1024 < dp; ++c) {
+      const int base = c * 1024 + 16 * lane;
+      float qv[16], fv[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        qv[j] = base + j < d ? q[base + j] : 0.0f;
+        fv[j] = base + j < d ? f[base + j] : 0.0f;
+      }
+      for (int L = 0; L < 64; ++L) {
+        if (lane == L) {
+#pragma unroll
+          for (int j = 0; j < 16; ++j)
+            if (base + j < d) s = __fma_rn((double)qv[j], (double)fv[j], s);
+        }
+        s = __shfl(s, L, 64);
+      }
     }
-    hits[h] = x;
+    if (lane == 0) {
+      const double cs = __ddiv_rn(s, __dmul_rn(__dsqrt_rn(qq[x.q]), __dsqrt_rn(ff[x.id])));
+      atomicAdd(&ctr->rechecked, 1ull);
+      if (cs >= rho[x.q]) {
+        x.flag = HIT_ACCEPT;
+        x.sim = (float)cs;
+        atomicAdd(&qcount[x.q], 1u);
+      } else {
+        x.flag = HIT_REJECT;
+      }
+      hits[hi] = x;
+    }
   }
 }
 
@@ -546,12 +626,12 @@ hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_recheck(Hit* hits, const unsigned long long* nhits, unsigned long long cap,
-                          const float* qf, const float* leaves, int d, int dp, const double* qq,
-                          const double* ff, const double* rho, unsigned int* qcount,
-                          DevCounters* ctr, hipStream_t s) {
-  hipLaunchKernelGGL(k_recheck, dim3(256), dim3(256), 0, s, hits, nhits, cap, qf, leaves, d, dp, qq,
-                     ff, rho, qcount, ctr);
+hipError_t launch_recheck(Hit* hits, const uint32_t* band_idx, const unsigned long long* nband,
+                          unsigned long long cap, const float* qf, const float* leaves, int d,
+                          int dp, const double* qq, const double* ff, const double* rho,
+                          unsigned int* qcount, DevCounters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_recheck, dim3(64), dim3(256), 0, s, hits, band_idx, nband, cap, qf, leaves, d,
+                     dp, qq, ff, rho, qcount, ctr);
   return hipGetLastError();
 }
 
