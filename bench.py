@@ -47,6 +47,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="end with a 1 GiB device-to-device copy (reference for memory counters)")
+    ap.add_argument("--sweep-dense", action="store_true",
+                    help="also time the walk for several dense/sparse split levels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU (this build has no multi-GPU path); use --gpus 1",
@@ -110,45 +114,67 @@ def main():
         idx.query(q, args.rho, pool=args.pool)
         prof.append(idx.stats())
     idx.set_option("profile", 0)
-    ms_front = float(np.median([p["ms_frontier"] for p in prof]))
-    ms_leaf = float(np.median([p["ms_leaf"] for p in prof]))
-    launches = prof[-1]["frontier_launches"]
+    med = lambda k: float(np.median([p[k] for p in prof]))
+    ms_dense, ms_sparse, ms_leaf = med("ms_dense"), med("ms_frontier"), med("ms_leaf")
+    n_dense, n_sparse = prof[-1]["dense_launches"], prof[-1]["frontier_launches"]
 
-    # ---- algorithmic bytes of the walk: each distinct pool row read once
+    # ---- algorithmic bytes: each distinct row a kernel must read, once
     idx.set_option("count_unique", 1)
     idx.query(q, args.rho, pool=args.pool)
     su = idx.stats()
     idx.set_option("count_unique", 0)
     esz = {"bf16": 2, "fp8": 1, "f32": 4}[args.pool]
     dp = su["d_pad"]
-    uniq_pools = int(sum(su["unique_rows"][:su["depth"]]))
-    uniq_leaves = int(su["unique_rows"][su["depth"]])
-    pool_bytes = uniq_pools * dp * esz
-    leaf_bytes = uniq_leaves * dp * 4
     h, D = su["head_level"], su["depth"]
+    first_sparse = h + n_dense          # dense steps test levels h+1 .. h+n_dense
+    uniq = su["unique_rows"]
+    dense_bytes = sum(uniq[l] for l in range(h + 1, first_sparse + 1)) * dp * esz
+    sparse_bytes = sum(uniq[l] for l in range(first_sparse + 1, D)) * dp * esz
+    leaf_bytes = uniq[D] * dp * 4
     entries = list(su["entries"])
-    entries[h] = (1 << h) * su["last_tiles"]
-    raw_pool = sum(entries[l] for l in range(h, D - 1)) * 2 * dp * esz
+    raw_sparse = sum(entries[l] for l in range(first_sparse, D - 1)) * 2 * dp * esz
+    if n_dense == 0:
+        raw_sparse += ((1 << h) * su["last_tiles"] - entries[h]) * 2 * dp * esz
     raw_leaf = entries[D - 1] * 2 * dp * 4
-    achieved = pool_bytes / (ms_front * 1e-3) / 1e9 if ms_front > 0 else None
+    groups = {
+        f"k_dense_level<{args.pool}>": (dense_bytes, ms_dense, n_dense),
+        f"k_walk_level<{args.pool}>": (sparse_bytes, ms_sparse, n_sparse),
+        "k_leaf": (leaf_bytes, ms_leaf, 1),
+    }
+    gbps = lambda b, ms: round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
+    dom = max(groups, key=lambda k: groups[k][1])
+    b, ms, nl = groups[dom]
+    achieved = gbps(b, ms)
     roofline = {
-        "kernel": f"k_walk_level<{args.pool}>",
+        "kernel": dom,
         "bound": "hbm",
-        "achieved": round(achieved, 1) if achieved else None,
+        "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
         "traffic": None,
-        "algorithmic_bytes_per_batch": pool_bytes,
-        "raw_bytes_per_batch": raw_pool,
-        "raw_GBps": round(raw_pool / (ms_front * 1e-3) / 1e9, 1) if ms_front > 0 else None,
-        "entries_per_level": {l: entries[l] for l in range(h, D)},
-        "unique_rows_per_level": {l: su["unique_rows"][l] for l in range(h + 1, D + 1)},
-        "launches_per_batch": launches,
-        "avg_launch_ms": ms_front / max(1, launches),
-        "leaf_kernel": {"bytes": leaf_bytes, "raw_bytes": raw_leaf, "ms": ms_leaf,
-                        "GBps": round(leaf_bytes / (ms_leaf * 1e-3) / 1e9, 1) if ms_leaf > 0 else None},
+        "algorithmic_bytes_per_launch": b / max(1, nl),
+        "launches_per_batch": nl,
+        "avg_launch_ms": ms / max(1, nl),
+        "kernels": {k: {"bytes": v[0], "ms": round(v[1], 4), "launches": v[2], "GBps": gbps(v[0], v[1])}
+                    for k, v in groups.items()},
+        "walk_all_levels": {"bytes": dense_bytes + sparse_bytes, "ms": round(ms_dense + ms_sparse, 4),
+                            "GBps": gbps(dense_bytes + sparse_bytes, ms_dense + ms_sparse)},
+        "sparse_raw_bytes": raw_sparse,
+        "leaf_raw_bytes": raw_leaf,
+        "entries_per_level": {l: entries[l] for l in range(h + 1, D)},
+        "unique_rows_per_level": {l: uniq[l] for l in range(h + 1, D + 1)},
     }
+
+    sweep = None
+    if args.sweep_dense:
+        sweep = {}
+        for dl in [-1] + list(range(max(h + 1, D - 7), D)):
+            idx.set_option("dense_last", dl)
+            _, wl, _ = run(args.pool, 5, 1)
+            sweep[dl] = round(wl / 5 * 1e3, 3)
+        idx.set_option("dense_last", -2)
+        log(f"dense_last sweep (ms/batch): {sweep}")
 
     # ---- comparators and recall against the exhaustive GEMM
     comparators = {}
@@ -227,8 +253,17 @@ def main():
         "comparators": comparators,
         "cpu_baseline": cpu,
     }
+    if sweep is not None:
+        out["dense_last_sweep_ms"] = sweep
     print(json.dumps(out), flush=True)
     idx.close()
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy reference: 1 GiB read + 1 GiB written")
 
 
 if __name__ == "__main__":

@@ -34,6 +34,7 @@ extern "C" {
 #endif
 
 typedef struct gt_index gt_index; /* opaque, owned by the library */
+typedef struct gt_batch gt_batch; /* opaque per-call device workspace */
 
 typedef enum {
   GT_OK = 0,
@@ -82,6 +83,8 @@ typedef struct {
   /* distinct rows of each level read by the last gt_query_batch (level depth =
    * leaves); filled only while option "count_unique" is on */
   int64_t unique_rows[GT_MAX_LEVELS];
+  int32_t dense_launches;  /* dense level steps of the last gt_query_batch */
+  double ms_dense;         /* their device time (profiling on) */
 } gt_stats;
 
 /* Build the index (paper Sec. 2: pools of the binary-splitting tree, created
@@ -139,6 +142,36 @@ gt_status gt_exhaustive(gt_index* index, const float* q_dev, int32_t nq, const d
                         int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
                         float* sims_dev, int64_t* total_out, void* stream);
 
+/* Device workspace for one query call at a time, so that several calls can
+ * be in flight on different streams (continuous batching: a server admits
+ * newly arrived requests into a free workspace while others are still on the
+ * device, and their kernels overlap).  gt_query_batch uses the index's own
+ * workspace; these use a caller-made one.
+ *   gt_batch_create  max_queries = the largest call (1 .. 32768); allocates
+ *                    the workspace (frontiers sized for the index depth).
+ *   gt_batch_submit  enqueues the whole walk of gt_query_batch on `stream`
+ *                    and returns without waiting; arguments as there.  The
+ *                    call sees the vectors indexed at submit time (ids below
+ *                    gt_stats.n then).  Errors: INVALID_ARG (a call already in
+ *                    flight on this workspace, format), CAPACITY (nq above
+ *                    max_queries), DEVICE.
+ *   gt_batch_poll    *done_out = 1 once the device has reached the result
+ *                    count of the call in flight (non-blocking).
+ *   gt_batch_finish  completes the call as gt_query_batch does (waits,
+ *                    writes offsets, ids, sims; same errors and overflow
+ *                    contract) and frees the workspace for the next call.
+ * Inserts may run between submit and finish: the call keeps its epoch, and
+ * float32 / bfloat16 pools only grow, which keeps its pruning sound; with
+ * float8 pools built, gt_insert first waits for the device.  One host thread
+ * drives the index and its workspaces. */
+gt_status gt_batch_create(gt_index* index, int32_t max_queries, gt_batch** out);
+gt_status gt_batch_submit(gt_batch* batch, const float* q_dev, int32_t nq, const double* rho_host,
+                          gt_pool fmt, void* stream);
+gt_status gt_batch_poll(gt_batch* batch, int32_t* done_out);
+gt_status gt_batch_finish(gt_batch* batch, int64_t max_results, int64_t* offsets_dev,
+                          int64_t* ids_dev, float* sims_dev, int64_t* total_out);
+void gt_batch_destroy(gt_batch* batch);
+
 /* Counters of the index and of its last query call.  Synchronises the device
  * stream of the last call.  Errors: INVALID_ARG. */
 gt_status gt_get_stats(const gt_index* index, gt_stats* out);
@@ -158,6 +191,8 @@ gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int
  *   "profile"     0/1: time kernel groups with HIP events (gt_stats.ms_*)
  *   "head_level"  first tested level, 0..depth-1 (-1 = automatic)
  *   "grid"        workgroups of the persistent walk kernels (0 = one per CU)
+ *   "dense_last"  last level tested with dense steps, every pool against every
+ *                 query (-2 = automatic, -1 = none; bf16 and fp8 pools only)
  *   "count_unique" 0/1: count distinct rows read per level (gt_stats.unique_rows);
  *                 adds atomics to the walk, for measurement runs only
  * Errors: INVALID_ARG for an unknown key or a value out of range. */

@@ -1,5 +1,5 @@
-// Host runtime behind the C interface of gt.h: the index object, device buffer
-// management and the launch sequence of each call.
+// Host runtime behind the C interface of gt.h: the index object, per-call
+// device workspaces, and the launch sequence of each call.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string.h>
@@ -11,9 +11,11 @@
 #include "gt.h"
 #include "gt_internal.h"
 
+using gt::Batch;
 using gt::Index;
 
 struct gt_index : Index {};
+struct gt_batch : Batch {};
 
 namespace {
 
@@ -30,6 +32,12 @@ gt_status fail(gt_status s, const std::string& msg) {
     if (e_ != hipSuccess)                                                              \
       return fail(e_ == hipErrorOutOfMemory ? GT_ERR_OUT_OF_MEMORY : GT_ERR_DEVICE,    \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+#define TRY(expr)                  \
+  do {                             \
+    gt_status s_ = (expr);         \
+    if (s_ != GT_OK) return s_;    \
   } while (0)
 
 template <class T>
@@ -56,15 +64,7 @@ void dfree(Index* ix, T** p, size_t count) {
   *p = nullptr;
 }
 
-#define TRY(expr)                  \
-  do {                             \
-    gt_status s_ = (expr);         \
-    if (s_ != GT_OK) return s_;    \
-  } while (0)
-
 inline int64_t level_row(int level) { return (int64_t(1) << level) - 1; }
-
-inline size_t bitmap_words(const Index* ix) { return (size_t)((int64_t(2) << ix->depth) / 32 + 1); }
 
 int default_head(int depth) {
   // Pools near the root hold thousands of vectors and essentially never fall
@@ -79,57 +79,23 @@ int head_of(const Index* ix) {
   return default_head(ix->depth);
 }
 
+// Last level walked with dense steps (every pool against every query).  Near
+// the root nearly every pool is live for every query tile, so a dense matrix
+// product reads each pool row once per workgroup column instead of once per
+// tile; a few levels above the leaves the frontier is sparse enough that the
+// per-tile walk reads less.  Float32 pools stay on the sparse walk (float32
+// matrix cores are 16x slower than bfloat16 ones).
+int dense_last_of(const Index* ix, int fmt, int h) {
+  if (fmt == GT_POOL_F32 || ix->dense_last == -1) return -1;
+  int dl = ix->dense_last >= 0 ? ix->dense_last : ix->depth - 5;
+  dl = std::min(dl, ix->depth - 1);
+  return dl > h ? dl : -1;
+}
+
 int tq_of(int fmt) { return fmt == GT_POOL_F32 ? gt::kQueriesPerTileF32 : gt::kQueriesPerTile16; }
 
 int maxdp_of(int fmt) {
   return fmt == GT_POOL_F32 ? gt::kMaxDpF32 : fmt == GT_POOL_BF16 ? gt::kMaxDpBf16 : gt::kMaxDpFp8;
-}
-
-void free_all(Index* ix) {
-  const size_t cap = (size_t)ix->cap, dp = (size_t)ix->dp, tree = (cap - 1) * dp;
-  dfree(ix, &ix->leaves, cap * dp);
-  dfree(ix, &ix->invn, cap);
-  dfree(ix, &ix->ff, cap);
-  dfree(ix, &ix->nf, cap);
-  dfree(ix, &ix->d_mmin, 2);
-  dfree(ix, &ix->master, tree);
-  dfree(ix, &ix->pbf16, tree);
-  dfree(ix, &ix->pfp8, tree);
-  dfree(ix, &ix->d_lexp, GT_MAX_LEVELS);
-  dfree(ix, &ix->d_levelmax, GT_MAX_LEVELS);
-  dfree(ix, &ix->d_flags, GT_MAX_LEVELS);
-  for (int b = 0; b < 2; ++b) {
-    dfree(ix, &ix->fr_node[b], (size_t)ix->nt_alloc * ix->fr_cap);
-    dfree(ix, &ix->fr_mask[b], (size_t)ix->nt_alloc * ix->fr_cap);
-  }
-  const size_t nqa = (size_t)ix->nq_alloc;
-  dfree(ix, &ix->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles);
-  dfree(ix, &ix->tile_mask, gt::kMaxTiles);
-  dfree(ix, &ix->qf, nqa * dp);
-  dfree(ix, &ix->qbf, nqa * dp);
-  dfree(ix, &ix->q8, nqa * dp);
-  dfree(ix, &ix->qexp, nqa);
-  dfree(ix, &ix->invn_q, nqa);
-  dfree(ix, &ix->qq, nqa);
-  dfree(ix, &ix->rho, nqa);
-  dfree(ix, &ix->thr, nqa);
-  dfree(ix, &ix->thr_gemm, nqa);
-  dfree(ix, &ix->qcount, nqa);
-  dfree(ix, &ix->qcursor, nqa);
-  dfree(ix, &ix->offs, nqa + 1);
-  dfree(ix, &ix->hits, (size_t)ix->hit_cap);
-  dfree(ix, &ix->band_idx, (size_t)ix->hit_cap);
-  dfree(ix, &ix->cand, (size_t)ix->cand_cap);
-  dfree(ix, &ix->out_id, (size_t)ix->out_cap);
-  dfree(ix, &ix->out_sim, (size_t)ix->out_cap);
-  dfree(ix, &ix->tmp_id, (size_t)ix->out_cap);
-  dfree(ix, &ix->tmp_sim, (size_t)ix->out_cap);
-  dfree(ix, &ix->ctr, 1);
-  dfree(ix, &ix->bitmap, bitmap_words(ix));
-  if (ix->h_ctr) (void)hipHostFree(ix->h_ctr);
-  if (ix->h_rho) (void)hipHostFree(ix->h_rho);
-  ix->h_ctr = nullptr;
-  ix->h_rho = nullptr;
 }
 
 gt_status zero_dev(void* p, size_t bytes, hipStream_t s) {
@@ -164,210 +130,501 @@ gt_status quantize_fp8_level(Index* ix, int level, hipStream_t s, bool recompute
   return GT_OK;
 }
 
-gt_status ensure_query_buffers(Index* ix, int nq_pad, int nt) {
-  const size_t dp = (size_t)ix->dp;
-  if (!ix->ctr) {
-    TRY(dalloc(ix, &ix->ctr, 1));
-    HIPCHK(hipHostMalloc((void**)&ix->h_ctr, sizeof(gt::DevCounters), hipHostMallocDefault));
-    TRY(dalloc(ix, &ix->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles));
-    TRY(dalloc(ix, &ix->tile_mask, gt::kMaxTiles));
+// ------------------------------------------------------------------ workspaces
+void free_query_arrays(Batch* b) {
+  Index* ix = b->ix;
+  const size_t o = (size_t)b->nq_alloc, dp = (size_t)ix->dp;
+  dfree(ix, &b->qf, o * dp);
+  dfree(ix, &b->qbf, o * dp);
+  dfree(ix, &b->q8, o * dp);
+  dfree(ix, &b->qexp, o);
+  dfree(ix, &b->invn_q, o);
+  dfree(ix, &b->qq, o);
+  dfree(ix, &b->rho, o);
+  dfree(ix, &b->thr, o);
+  dfree(ix, &b->thr_gemm, o);
+  dfree(ix, &b->qcount, o);
+  dfree(ix, &b->qcursor, o);
+  dfree(ix, &b->offs, o + 1);
+  if (b->h_rho) (void)hipHostFree(b->h_rho);
+  b->h_rho = nullptr;
+  b->nq_alloc = 0;
+}
+
+void free_frontier(Batch* b) {
+  for (int k = 0; k < 2; ++k) {
+    dfree(b->ix, &b->fr_node[k], (size_t)b->nt_alloc * b->fr_cap);
+    dfree(b->ix, &b->fr_mask[k], (size_t)b->nt_alloc * b->fr_cap);
   }
-  if (nq_pad > ix->nq_alloc) {
-    const size_t o = (size_t)ix->nq_alloc, nqa = (size_t)nq_pad;
-    dfree(ix, &ix->qf, o * dp);
-    dfree(ix, &ix->qbf, o * dp);
-    dfree(ix, &ix->q8, o * dp);
-    dfree(ix, &ix->qexp, o);
-    dfree(ix, &ix->invn_q, o);
-    dfree(ix, &ix->qq, o);
-    dfree(ix, &ix->rho, o);
-    dfree(ix, &ix->thr, o);
-    dfree(ix, &ix->thr_gemm, o);
-    dfree(ix, &ix->qcount, o);
-    dfree(ix, &ix->qcursor, o);
-    dfree(ix, &ix->offs, o + 1);
-    if (ix->h_rho) (void)hipHostFree(ix->h_rho);
-    ix->h_rho = nullptr;
-    ix->nq_alloc = 0;
-    TRY(dalloc(ix, &ix->qf, nqa * dp));
-    TRY(dalloc(ix, &ix->qbf, nqa * dp));
-    TRY(dalloc(ix, &ix->q8, nqa * dp));
-    TRY(dalloc(ix, &ix->qexp, nqa));
-    TRY(dalloc(ix, &ix->invn_q, nqa));
-    TRY(dalloc(ix, &ix->qq, nqa));
-    TRY(dalloc(ix, &ix->rho, nqa));
-    TRY(dalloc(ix, &ix->thr, nqa));
-    TRY(dalloc(ix, &ix->thr_gemm, nqa));
-    TRY(dalloc(ix, &ix->qcount, nqa));
-    TRY(dalloc(ix, &ix->qcursor, nqa));
-    TRY(dalloc(ix, &ix->offs, nqa + 1));
-    HIPCHK(hipHostMalloc((void**)&ix->h_rho, nqa * sizeof(double), hipHostMallocDefault));
-    ix->nq_alloc = nq_pad;
+  b->nt_alloc = 0;
+}
+
+void free_batch(Batch* b) {
+  if (!b) return;
+  Index* ix = b->ix;
+  free_query_arrays(b);
+  free_frontier(b);
+  dfree(ix, &b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles);
+  dfree(ix, &b->tile_mask, gt::kMaxTiles);
+  dfree(ix, &b->hits, (size_t)b->hit_cap);
+  dfree(ix, &b->band_idx, (size_t)b->hit_cap);
+  dfree(ix, &b->cand, (size_t)b->cand_cap);
+  dfree(ix, &b->out_id, (size_t)b->out_cap);
+  dfree(ix, &b->out_sim, (size_t)b->out_cap);
+  dfree(ix, &b->tmp_id, (size_t)b->out_cap);
+  dfree(ix, &b->tmp_sim, (size_t)b->out_cap);
+  dfree(ix, &b->dmask[0], (size_t)b->dmask_len);
+  dfree(ix, &b->dmask[1], (size_t)b->dmask_len);
+  dfree(ix, &b->bitmap, (size_t)b->bitmap_words);
+  dfree(ix, &b->ctr, 1);
+  if (b->h_ctr) (void)hipHostFree(b->h_ctr);
+  b->h_ctr = nullptr;
+  if (b->done) (void)hipEventDestroy(b->done);
+  b->done = nullptr;
+  if (b->events) {
+    for (auto& e : b->ev) (void)hipEventDestroy(e);
+    for (auto& e : b->evw) (void)hipEventDestroy(e);
+    b->events = false;
+  }
+}
+
+void free_tree(Index* ix) {
+  const size_t cap = (size_t)ix->cap, dp = (size_t)ix->dp, tree = (cap - 1) * dp;
+  dfree(ix, &ix->leaves, cap * dp);
+  dfree(ix, &ix->invn, cap);
+  dfree(ix, &ix->ff, cap);
+  dfree(ix, &ix->nf, cap);
+  dfree(ix, &ix->d_mmin, 2);
+  dfree(ix, &ix->master, tree);
+  dfree(ix, &ix->pbf16, tree);
+  dfree(ix, &ix->pfp8, tree);
+  dfree(ix, &ix->d_lexp, GT_MAX_LEVELS);
+  dfree(ix, &ix->d_levelmax, GT_MAX_LEVELS);
+  dfree(ix, &ix->d_flags, GT_MAX_LEVELS);
+}
+
+gt_status batch_init(Batch* b) {
+  Index* ix = b->ix;
+  TRY(dalloc(ix, &b->ctr, 1));
+  HIPCHK(hipHostMalloc((void**)&b->h_ctr, sizeof(gt::DevCounters), hipHostMallocDefault));
+  TRY(dalloc(ix, &b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles));
+  TRY(dalloc(ix, &b->tile_mask, gt::kMaxTiles));
+  b->hit_cap = int64_t(1) << 20;
+  TRY(dalloc(ix, &b->hits, (size_t)b->hit_cap));
+  TRY(dalloc(ix, &b->band_idx, (size_t)b->hit_cap));
+  HIPCHK(hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+  return GT_OK;
+}
+
+// Query arrays for nq_pad queries and frontiers for nt tiles.
+gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
+  Index* ix = b->ix;
+  const size_t dp = (size_t)ix->dp;
+  if (nq_pad > b->nq_alloc) {
+    free_query_arrays(b);
+    const size_t nqa = (size_t)nq_pad;
+    TRY(dalloc(ix, &b->qf, nqa * dp));
+    TRY(dalloc(ix, &b->qbf, nqa * dp));
+    TRY(dalloc(ix, &b->q8, nqa * dp));
+    TRY(dalloc(ix, &b->qexp, nqa));
+    TRY(dalloc(ix, &b->invn_q, nqa));
+    TRY(dalloc(ix, &b->qq, nqa));
+    TRY(dalloc(ix, &b->rho, nqa));
+    TRY(dalloc(ix, &b->thr, nqa));
+    TRY(dalloc(ix, &b->thr_gemm, nqa));
+    TRY(dalloc(ix, &b->qcount, nqa));
+    TRY(dalloc(ix, &b->qcursor, nqa));
+    TRY(dalloc(ix, &b->offs, nqa + 1));
+    HIPCHK(hipHostMalloc((void**)&b->h_rho, nqa * sizeof(double), hipHostMallocDefault));
+    b->nq_alloc = nq_pad;
   }
   const int64_t fr_cap = int64_t(1) << std::max(0, ix->depth - 1);
-  if (nt > ix->nt_alloc || fr_cap != ix->fr_cap) {
-    for (int b = 0; b < 2; ++b) {
-      dfree(ix, &ix->fr_node[b], (size_t)ix->nt_alloc * ix->fr_cap);
-      dfree(ix, &ix->fr_mask[b], (size_t)ix->nt_alloc * ix->fr_cap);
+  if (nt > b->nt_alloc || fr_cap != b->fr_cap) {
+    free_frontier(b);
+    for (int k = 0; k < 2; ++k) {
+      TRY(dalloc(ix, &b->fr_node[k], (size_t)nt * fr_cap));
+      TRY(dalloc(ix, &b->fr_mask[k], (size_t)nt * fr_cap));
     }
-    ix->nt_alloc = 0;
-    for (int b = 0; b < 2; ++b) {
-      TRY(dalloc(ix, &ix->fr_node[b], (size_t)nt * fr_cap));
-      TRY(dalloc(ix, &ix->fr_mask[b], (size_t)nt * fr_cap));
-    }
-    ix->nt_alloc = nt;
-    ix->fr_cap = fr_cap;
-  }
-  if (!ix->hits) {
-    ix->hit_cap = int64_t(1) << 20;
-    TRY(dalloc(ix, &ix->hits, (size_t)ix->hit_cap));
-    TRY(dalloc(ix, &ix->band_idx, (size_t)ix->hit_cap));
+    b->nt_alloc = nt;
+    b->fr_cap = fr_cap;
   }
   return GT_OK;
 }
 
-gt_status grow_hits(Index* ix, int64_t need) {
-  dfree(ix, &ix->hits, (size_t)ix->hit_cap);
-  dfree(ix, &ix->band_idx, (size_t)ix->hit_cap);
-  ix->hit_cap = 0;
+gt_status grow_hits(Batch* b, int64_t need) {
+  Index* ix = b->ix;
+  dfree(ix, &b->hits, (size_t)b->hit_cap);
+  dfree(ix, &b->band_idx, (size_t)b->hit_cap);
+  b->hit_cap = 0;
   const int64_t cap = need + need / 4 + 1024;
   if (cap >= (int64_t(1) << 32)) return fail(GT_ERR_OUT_OF_MEMORY, "more than 2^32 candidates");
-  TRY(dalloc(ix, &ix->hits, (size_t)cap));
-  TRY(dalloc(ix, &ix->band_idx, (size_t)cap));
-  ix->hit_cap = cap;
+  TRY(dalloc(ix, &b->hits, (size_t)cap));
+  TRY(dalloc(ix, &b->band_idx, (size_t)cap));
+  b->hit_cap = cap;
   return GT_OK;
 }
 
-gt_status ensure_out(Index* ix, int64_t need) {
-  if (need <= ix->out_cap && ix->out_id) return GT_OK;
-  const size_t o = (size_t)ix->out_cap;
-  dfree(ix, &ix->out_id, o);
-  dfree(ix, &ix->out_sim, o);
-  dfree(ix, &ix->tmp_id, o);
-  dfree(ix, &ix->tmp_sim, o);
-  ix->out_cap = 0;
+gt_status ensure_out(Batch* b, int64_t need) {
+  if (need <= b->out_cap && b->out_id) return GT_OK;
+  Index* ix = b->ix;
+  const size_t o = (size_t)b->out_cap;
+  dfree(ix, &b->out_id, o);
+  dfree(ix, &b->out_sim, o);
+  dfree(ix, &b->tmp_id, o);
+  dfree(ix, &b->tmp_sim, o);
+  b->out_cap = 0;
   const int64_t cap = std::max<int64_t>(need + need / 4, int64_t(1) << 16);
-  TRY(dalloc(ix, &ix->out_id, (size_t)cap));
-  TRY(dalloc(ix, &ix->out_sim, (size_t)cap));
-  TRY(dalloc(ix, &ix->tmp_id, (size_t)cap));
-  TRY(dalloc(ix, &ix->tmp_sim, (size_t)cap));
-  ix->out_cap = cap;
+  TRY(dalloc(ix, &b->out_id, (size_t)cap));
+  TRY(dalloc(ix, &b->out_sim, (size_t)cap));
+  TRY(dalloc(ix, &b->tmp_id, (size_t)cap));
+  TRY(dalloc(ix, &b->tmp_sim, (size_t)cap));
+  b->out_cap = cap;
   return GT_OK;
 }
 
-struct Timer {
-  Index* ix;
-  hipStream_t s;
-  hipEvent_t ev[8] = {};
-  hipEvent_t evw[2 * GT_MAX_LEVELS] = {};
-  int nw = 0;
-  bool on;
-  Timer(Index* i, hipStream_t st) : ix(i), s(st), on(i->profile) {
-    if (on) {
-      for (auto& e : ev) (void)hipEventCreate(&e);
-      for (auto& e : evw) (void)hipEventCreate(&e);
-    }
+// --------------------------------------------------------------- event timing
+void ev_mark(Batch* b, int k) {
+  if (b->profile) (void)hipEventRecord(b->ev[k], b->stream);
+}
+void ev_launch_begin(Batch* b) {
+  if (b->profile && b->nw < GT_MAX_LEVELS) (void)hipEventRecord(b->evw[2 * b->nw], b->stream);
+}
+void ev_launch_end(Batch* b, bool dense) {
+  if (b->profile && b->nw < GT_MAX_LEVELS) {
+    (void)hipEventRecord(b->evw[2 * b->nw + 1], b->stream);
+    b->evw_dense[b->nw] = dense;
+    ++b->nw;
   }
-  ~Timer() {
-    if (on) {
-      for (auto& e : ev) (void)hipEventDestroy(e);
-      for (auto& e : evw) (void)hipEventDestroy(e);
-    }
-  }
-  void mark(int k) {
-    if (on) (void)hipEventRecord(ev[k], s);
-  }
-  // events bracketing each walk-level launch
-  void launch_begin() {
-    if (on && nw < GT_MAX_LEVELS) (void)hipEventRecord(evw[2 * nw], s);
-  }
-  void launch_end() {
-    if (on && nw < GT_MAX_LEVELS) (void)hipEventRecord(evw[2 * nw + 1], s), ++nw;
-  }
-  float walk_ms() {
-    float t = 0.0f;
-    for (int i = 0; on && i < nw; ++i) {
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, evw[2 * i], evw[2 * i + 1]);
-      t += ms;
-    }
-    return t;
-  }
-  float between(int a, int b) {
+}
+float ev_between(Batch* b, int x, int y) {
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, b->ev[x], b->ev[y]);
+  return ms;
+}
+float ev_walk(Batch* b, bool dense) {
+  float t = 0.0f;
+  for (int i = 0; i < b->nw; ++i) {
+    if (b->evw_dense[i] != dense) continue;
     float ms = 0.0f;
-    if (on) (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
-    return ms;
+    (void)hipEventElapsedTime(&ms, b->evw[2 * i], b->evw[2 * i + 1]);
+    t += ms;
   }
-};
+  return t;
+}
 
-// Validation shared by the two query entry points.
-gt_status check_query_args(const Index* ix, const float* q, int nq, const double* rho,
-                           int64_t max_results, int64_t* offsets, int64_t* ids, float* sims,
-                           int64_t* total_out, int tq) {
+// ------------------------------------------------------------- launch stages
+gt_status enqueue_walk(Index* ix, Batch* b) {
+  hipStream_t s = b->stream;
+  const int f = b->fmt, nt = b->nt, D = ix->depth, h = b->head, dl = b->dense_last;
+  const int grid = ix->grid > 0 ? ix->grid : ix->n_cu;
+  const size_t dp = (size_t)ix->dp;
+  const void* qtile = f == GT_POOL_F32 ? (const void*)b->qf
+                      : f == GT_POOL_BF16 ? (const void*)b->qbf : (const void*)b->q8;
+  const size_t esz = f == GT_POOL_F32 ? 4 : f == GT_POOL_BF16 ? 2 : 1;
+  const unsigned char* pool_base = f == GT_POOL_F32 ? (const unsigned char*)ix->master
+                                   : f == GT_POOL_BF16 ? (const unsigned char*)ix->pbf16
+                                                       : (const unsigned char*)ix->pfp8;
+  uint32_t* bitmap = b->counted ? b->bitmap : nullptr;
+  b->frontier_launches = 0;
+  b->dense_launches = 0;
+  if (dl >= 0) {
+    const size_t need = ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt;
+    if ((int64_t)need > b->dmask_len) {
+      dfree(ix, &b->dmask[0], (size_t)b->dmask_len);
+      dfree(ix, &b->dmask[1], (size_t)b->dmask_len);
+      b->dmask_len = 0;
+      TRY(dalloc(ix, &b->dmask[0], need));
+      TRY(dalloc(ix, &b->dmask[1], need));
+      b->dmask_len = (int64_t)need;
+    }
+    for (int L = h + 1; L <= dl; ++L) {
+      gt::DenseLevelArgs a{};
+      a.level = L;
+      a.nt = nt;
+      a.dp = ix->dp;
+      a.cap = (int)b->fr_cap;
+      a.child_rows = pool_base + (size_t)level_row(L) * dp * esz;
+      a.qtile = qtile;
+      a.thr = b->thr;
+      a.qexp = b->qexp;
+      a.lexp = ix->lexp[L];
+      a.parent = L == h + 1 ? nullptr : b->dmask[(L - 1) & 1];
+      a.tile_mask = b->tile_mask;
+      a.out_dense = L < dl ? b->dmask[L & 1] : nullptr;
+      a.out_node = b->fr_node[L & 1];
+      a.out_mask = b->fr_mask[L & 1];
+      a.out_count = b->lvl_count + (size_t)L * gt::kMaxTiles;
+      a.stat_pairs = &b->ctr->pairs[L];
+      a.bitmap = bitmap;
+      a.bit_base = level_row(L);
+      ev_launch_begin(b);
+      HIPCHK(gt::launch_dense_level(f, a, s));
+      ev_launch_end(b, true);
+      b->dense_launches++;
+    }
+  }
+  const int sparse_from = dl >= 0 ? dl : h;
+  for (int l = sparse_from; l <= D - 2; ++l) {
+    gt::WalkLevelArgs a{};
+    a.level = l;
+    a.dense = (l == h);
+    a.nt = nt;
+    a.dp = ix->dp;
+    a.cap = (int)b->fr_cap;
+    a.child_rows = pool_base + (size_t)level_row(l + 1) * dp * esz;
+    a.in_node = b->fr_node[l & 1];
+    a.in_mask = b->fr_mask[l & 1];
+    a.in_count = b->lvl_count + (size_t)l * gt::kMaxTiles;
+    a.out_node = b->fr_node[(l + 1) & 1];
+    a.out_mask = b->fr_mask[(l + 1) & 1];
+    a.out_count = b->lvl_count + (size_t)(l + 1) * gt::kMaxTiles;
+    a.tile_mask = b->tile_mask;
+    a.qtile = qtile;
+    a.thr = b->thr;
+    a.qexp = b->qexp;
+    a.lexp = ix->lexp[l + 1];
+    a.stat_pairs = &b->ctr->pairs[l + 1];
+    a.bitmap = bitmap;
+    a.bit_base = level_row(l + 1);
+    ev_launch_begin(b);
+    HIPCHK(gt::launch_walk_level(f, a, grid, s));
+    ev_launch_end(b, false);
+    b->frontier_launches++;
+  }
+  return GT_OK;
+}
+
+gt_status enqueue_leaf(Index* ix, Batch* b) {
+  const int D = ix->depth;
+  const int sparse_from = b->dense_last >= 0 ? b->dense_last : b->head;
+  gt::LeafArgs la{};
+  la.level = D - 1;
+  la.dense = (sparse_from == D - 1) && b->dense_last < 0;
+  la.nt = b->nt;
+  la.dp = ix->dp;
+  la.cap = (int)b->fr_cap;
+  la.tq = b->tq;
+  la.in_node = b->fr_node[(D - 1) & 1];
+  la.in_mask = b->fr_mask[(D - 1) & 1];
+  la.in_count = b->lvl_count + (size_t)(D - 1) * gt::kMaxTiles;
+  la.tile_mask = b->tile_mask;
+  la.leaves = ix->leaves;
+  la.invn_f = ix->invn;
+  la.qf = b->qf;
+  la.invn_q = b->invn_q;
+  la.rho = b->rho;
+  la.n_epoch = b->n_epoch;
+  la.hits = b->hits;
+  la.band_idx = b->band_idx;
+  la.hit_cap = (unsigned long long)b->hit_cap;
+  la.qcount = b->qcount;
+  la.ctr = b->ctr;
+  la.bitmap = b->counted ? b->bitmap : nullptr;
+  la.bit_base = level_row(D);
+  HIPCHK(gt::launch_leaf(la, ix->n_cu * 4, b->stream));
+  return GT_OK;
+}
+
+gt_status enqueue_exhaustive(Index* ix, Batch* b) {
+  if (!b->cand) {
+    b->cand_cap = int64_t(1) << 20;
+    TRY(dalloc(ix, &b->cand, (size_t)b->cand_cap));
+  }
+  ev_launch_begin(b);
+  HIPCHK(gt::launch_exhaustive_gemm(b->qf, b->nq_pad, ix->leaves, b->n_epoch, ix->dp, b->thr_gemm,
+                                    ix->nf, b->cand, (unsigned long long)b->cand_cap, b->ctr,
+                                    b->nq, b->stream));
+  ev_launch_end(b, true);
+  return GT_OK;
+}
+
+gt_status enqueue_pair_check(Index* ix, Batch* b) {
+  HIPCHK(gt::launch_pair_check(b->cand, &b->ctr->ncand, (unsigned long long)b->cand_cap, b->qf,
+                               ix->leaves, b->invn_q, ix->invn, b->rho, ix->dp, b->hits,
+                               (unsigned long long)b->hit_cap, b->band_idx, b->qcount, b->ctr,
+                               ix->n_cu * 4, b->stream));
+  return GT_OK;
+}
+
+// recheck, offsets and the copy of the counters the host needs
+gt_status enqueue_tail(Index* ix, Batch* b) {
+  hipStream_t s = b->stream;
+  HIPCHK(gt::launch_recheck(b->hits, b->band_idx, &b->ctr->nband, (unsigned long long)b->hit_cap,
+                            b->qf, ix->leaves, ix->d, ix->dp, b->qq, ix->ff, b->rho, b->qcount,
+                            b->ctr, s));
+  ev_mark(b, 4);
+  HIPCHK(gt::launch_scan_offsets(b->qcount, b->nq, b->offs, nullptr, b->ctr, s));
+  HIPCHK(hipMemcpyAsync(b->h_ctr, b->ctr, sizeof(gt::DevCounters), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipEventRecord(b->done, s));
+  ev_mark(b, 5);
+  return GT_OK;
+}
+
+// candidate stage again after the candidate buffers grew
+gt_status redo_candidates(Index* ix, Batch* b) {
+  hipStream_t s = b->stream;
+  TRY(zero_dev(b->qcount, (size_t)b->nq_pad * 4, s));
+  TRY(zero_dev(&b->ctr->nhits, 8, s));
+  TRY(zero_dev(&b->ctr->leaf_pairs, 8, s));
+  TRY(zero_dev(&b->ctr->rechecked, 8, s));
+  TRY(zero_dev(&b->ctr->nband, 8, s));
+  if (b->kind == 1) {
+    TRY(enqueue_leaf(ix, b));
+  } else {
+    TRY(zero_dev(&b->ctr->ncand, 8, s));
+    TRY(enqueue_exhaustive(ix, b));
+    TRY(enqueue_pair_check(ix, b));
+  }
+  return enqueue_tail(ix, b);
+}
+
+gt_status check_query_args(const Index* ix, const float* q, int nq, const double* rho, int tq) {
   if (!ix) return fail(GT_ERR_INVALID_ARG, "index is NULL");
-  if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
   if (nq < 0) return fail(GT_ERR_INVALID_ARG, "nq < 0");
   if ((int64_t)nq > (int64_t)gt::kMaxTiles * tq)
     return fail(GT_ERR_INVALID_ARG, "nq exceeds " + std::to_string(gt::kMaxTiles * tq) +
                                         " queries per call for this format");
-  if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
-  if (nq > 0 && (!q || !rho || !offsets)) return fail(GT_ERR_INVALID_ARG, "NULL query argument");
-  if (max_results > 0 && (!ids || !sims)) return fail(GT_ERR_INVALID_ARG, "NULL output buffer");
+  if (nq > 0 && (!q || !rho)) return fail(GT_ERR_INVALID_ARG, "NULL query argument");
   for (int i = 0; i < nq; ++i)
     if (isnan(rho[i])) return fail(GT_ERR_INVALID_ARG, "rho is NaN");
   return GT_OK;
 }
 
-// Shared tail: recheck, offsets, one host synchronisation, overflow handling,
-// scatter and sort.  `rerun` relaunches the candidate-producing stage after
-// the hit buffer has grown.
-template <class Rerun>
-gt_status finish_query(Index* ix, int nq, int nq_pad, int64_t max_results, int64_t* offsets,
-                       int64_t* ids, float* sims, int64_t* total_out, hipStream_t s, Timer& tm,
-                       Rerun rerun, bool* cand_overflow = nullptr) {
-  for (int attempt = 0;; ++attempt) {
-    HIPCHK(gt::launch_recheck(ix->hits, ix->band_idx, &ix->ctr->nband,
-                              (unsigned long long)ix->hit_cap, ix->qf, ix->leaves, ix->d, ix->dp,
-                              ix->qq, ix->ff, ix->rho, ix->qcount, ix->ctr, s));
-    tm.mark(4);
-    HIPCHK(gt::launch_scan_offsets(ix->qcount, nq, ix->offs, offsets, ix->ctr, s));
-    HIPCHK(hipMemcpyAsync(ix->h_ctr, ix->ctr, sizeof(gt::DevCounters), hipMemcpyDeviceToHost, s));
-    tm.mark(5);
-    HIPCHK(hipStreamSynchronize(s));
-    const gt::DevCounters& c = *ix->h_ctr;
-    if (c.err) return fail(GT_ERR_INVALID_INPUT, "query contains a NaN, infinite or negative value");
-    if (cand_overflow && (int64_t)c.ncand > ix->cand_cap) {
-      *cand_overflow = true;  // the caller regrows the candidate list and starts over
-      return GT_OK;
-    }
-    if ((int64_t)c.nhits <= ix->hit_cap) break;
-    if (attempt > 2) return fail(GT_ERR_DEVICE, "candidate buffer did not converge");
-    TRY(grow_hits(ix, (int64_t)c.nhits));
-    TRY(zero_dev(ix->qcount, (size_t)nq_pad * 4, s));
-    TRY(zero_dev(&ix->ctr->nhits, 8, s));
-    TRY(zero_dev(&ix->ctr->leaf_pairs, 8, s));
-    TRY(zero_dev(&ix->ctr->rechecked, 8, s));
-    TRY(zero_dev(&ix->ctr->nband, 8, s));
-    TRY(rerun());
+// Enqueues a whole call up to the counter readback.  kind 1: walk, 2: exhaustive.
+gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const double* rho,
+                 int fmt, hipStream_t s) {
+  if (b->pending) return fail(GT_ERR_INVALID_ARG, "the workspace has a call in flight");
+  const int tq = kind == 1 ? tq_of(fmt) : gt::kQueriesPerTile16;
+  if (kind == 1) {
+    if (fmt != GT_POOL_F32 && fmt != GT_POOL_BF16 && fmt != GT_POOL_FP8E4M3)
+      return fail(GT_ERR_INVALID_ARG, "unknown pool format");
+    if (!(ix->formats & (uint32_t)fmt)) return fail(GT_ERR_INVALID_ARG, "pool format was not built");
+    if (ix->dp > maxdp_of(fmt))
+      return fail(GT_ERR_INVALID_ARG, "d too large for this pool format (padded d <= " +
+                                          std::to_string(maxdp_of(fmt)) + ")");
   }
-  const int64_t total = (int64_t)ix->h_ctr->total;
+  TRY(check_query_args(ix, q, nq, rho, tq));
+  const int nt = (nq + tq - 1) / tq;
+  const int nq_pad = std::max(128, (nq + 127) / 128 * 128);
+  if (b->max_queries > 0 && nq > b->max_queries)
+    return fail(GT_ERR_CAPACITY, "batch of " + std::to_string(nq) +
+                                     " queries exceeds the workspace's " +
+                                     std::to_string(b->max_queries));
+  TRY(batch_reserve(b, nq_pad, std::max(nt, 1)));
+  b->kind = kind;
+  b->stream = s;
+  b->fmt = fmt;
+  b->nq = nq;
+  b->nq_pad = nq_pad;
+  b->nt = nt;
+  b->tq = tq;
+  b->n_epoch = ix->n;
+  b->head = head_of(ix);
+  b->dense_last = kind == 1 ? dense_last_of(ix, fmt, b->head) : -1;
+  b->profile = ix->profile;
+  b->nw = 0;
+  if (b->profile && !b->events) {
+    for (auto& e : b->ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : b->evw) HIPCHK(hipEventCreate(&e));
+    b->events = true;
+  }
+  ev_mark(b, 0);
+  TRY(zero_dev(b->ctr, sizeof(gt::DevCounters), s));
+  TRY(zero_dev(b->qcount, (size_t)nq_pad * 4, s));
+  TRY(zero_dev(b->tile_mask, (size_t)gt::kMaxTiles * 8, s));
+  if (kind == 1) TRY(zero_dev(b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles * 4, s));
+  b->counted = ix->count_unique && kind == 1;
+  if (b->counted) {
+    const int64_t words = (int64_t(2) << ix->depth) / 32 + 1;
+    if (!b->bitmap) {
+      TRY(dalloc(ix, &b->bitmap, (size_t)words));
+      b->bitmap_words = words;
+    }
+    TRY(zero_dev(b->bitmap, (size_t)words * 4, s));
+  }
+  if (nq > 0) {
+    memcpy(b->h_rho, rho, (size_t)nq * 8);
+    HIPCHK(hipMemcpyAsync(b->rho, b->h_rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    HIPCHK(gt::launch_query_prep(q, nq, ix->d, ix->dp, tq, b->rho, ix->d_mmin, b->qf, b->qbf,
+                                 b->q8, b->qexp, b->invn_q, b->qq, b->thr, b->thr_gemm,
+                                 b->tile_mask, &b->ctr->err, nq_pad, s));
+  }
+  ev_mark(b, 1);
+  if (nq > 0 && ix->n > 0) {
+    if (kind == 1) {
+      TRY(enqueue_walk(ix, b));
+      ev_mark(b, 2);
+      TRY(enqueue_leaf(ix, b));
+    } else {
+      TRY(enqueue_exhaustive(ix, b));
+      ev_mark(b, 2);
+      TRY(enqueue_pair_check(ix, b));
+    }
+  } else {
+    ev_mark(b, 2);
+  }
+  ev_mark(b, 3);
+  TRY(enqueue_tail(ix, b));
+  b->pending = true;
+  b->last_nq = nq;
+  b->last_nt = nt;
+  b->last_fmt = kind == 1 ? fmt : 0;
+  return GT_OK;
+}
+
+// Waits for the counters, handles buffer overflow, writes offsets, ids and sims.
+gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int64_t* ids,
+                 float* sims, int64_t* total_out) {
+  if (!b->pending) return fail(GT_ERR_INVALID_ARG, "no call in flight on this workspace");
+  b->pending = false;
+  if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
+  if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
+  if (!offsets) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
+  if (max_results > 0 && (!ids || !sims)) return fail(GT_ERR_INVALID_ARG, "NULL output buffer");
+  hipStream_t s = b->stream;
+  *total_out = 0;
+  for (int attempt = 0;; ++attempt) {
+    HIPCHK(hipEventSynchronize(b->done));
+    const gt::DevCounters& c = *b->h_ctr;
+    if (c.err) return fail(GT_ERR_INVALID_INPUT, "query contains a NaN, infinite or negative value");
+    const bool cand_over = b->kind == 2 && (int64_t)c.ncand > b->cand_cap;
+    const bool hit_over = (int64_t)c.nhits > b->hit_cap;
+    if (!cand_over && !hit_over) break;
+    if (attempt > 3) return fail(GT_ERR_DEVICE, "candidate buffers did not converge");
+    if (cand_over) {
+      const int64_t need = (int64_t)c.ncand;
+      dfree(ix, &b->cand, (size_t)b->cand_cap);
+      b->cand_cap = 0;
+      TRY(dalloc(ix, &b->cand, (size_t)(need + need / 4 + 1024)));
+      b->cand_cap = need + need / 4 + 1024;
+    }
+    if (hit_over) TRY(grow_hits(b, (int64_t)c.nhits));
+    TRY(redo_candidates(ix, b));
+  }
+  const int64_t total = (int64_t)b->h_ctr->total;
   *total_out = total;
+  HIPCHK(hipMemcpyAsync(offsets, b->offs, (size_t)(b->nq + 1) * 8, hipMemcpyDeviceToDevice, s));
   if (total > max_results)
     return fail(GT_ERR_RESULT_OVERFLOW, "need max_results >= " + std::to_string(total));
   if (total > 0) {
-    TRY(ensure_out(ix, total));
-    TRY(zero_dev(ix->qcursor, (size_t)nq_pad * 4, s));
-    HIPCHK(gt::launch_scatter(ix->hits, &ix->ctr->nhits, (unsigned long long)ix->hit_cap, ix->offs,
-                              ix->qcursor, ix->out_id, ix->out_sim, s));
-    HIPCHK(gt::launch_sort_segments(ix->offs, nq, ix->out_id, ix->out_sim, ix->tmp_id,
-                                    ix->tmp_sim, ids, sims, s));
+    TRY(ensure_out(b, total));
+    TRY(zero_dev(b->qcursor, (size_t)b->nq_pad * 4, s));
+    HIPCHK(gt::launch_scatter(b->hits, &b->ctr->nhits, (unsigned long long)b->hit_cap, b->offs,
+                              b->qcursor, b->out_id, b->out_sim, s));
+    HIPCHK(gt::launch_sort_segments(b->offs, b->nq, b->out_id, b->out_sim, b->tmp_id, b->tmp_sim,
+                                    ids, sims, s));
   }
-  tm.mark(6);
-  if (tm.on) {
+  ev_mark(b, 6);
+  if (b->profile) {
     HIPCHK(hipStreamSynchronize(s));
-    ix->ms[3] = tm.between(3, 4);
-    ix->ms[4] = tm.between(4, 5) + tm.between(5, 6);
-    ix->ms[6] = tm.between(0, 6);
+    b->ms[0] = ev_between(b, 0, 1);                          // query prep
+    b->ms[1] = b->kind == 1 ? ev_walk(b, false) : 0.0;       // sparse walk levels
+    b->ms[2] = ev_between(b, 2, 3);                          // leaf / pair test
+    b->ms[3] = ev_between(b, 3, 4);                          // float64 recheck
+    b->ms[4] = ev_between(b, 4, 5) + ev_between(b, 5, 6);    // offsets, compaction
+    b->ms[5] = b->kind == 2 ? ev_walk(b, true) : 0.0;        // exhaustive GEMM
+    b->ms[6] = ev_between(b, 0, 6);
+    b->ms[7] = b->kind == 1 ? ev_walk(b, true) : 0.0;        // dense levels
   }
   return GT_OK;
 }
@@ -400,9 +657,32 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
 
   hipStream_t s = (hipStream_t)stream;
   gt_index* ix = new gt_index();
-  HIPCHK(hipGetDevice(&ix->device));
+  auto bail = [&](gt_status st) {
+    std::string keep = g_err;
+    if (ix->def) {
+      free_batch(ix->def);
+      delete static_cast<gt_batch*>(ix->def);
+    }
+    free_tree(ix);
+    delete ix;
+    g_err = keep;
+    return st;
+  };
+#define BTRY(expr)                    \
+  do {                                \
+    gt_status s_ = (expr);            \
+    if (s_ != GT_OK) return bail(s_); \
+  } while (0)
+#define BHIP(expr)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return bail(fail(GT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
+  } while (0)
+
+  BHIP(hipGetDevice(&ix->device));
   hipDeviceProp_t prop;
-  HIPCHK(hipGetDeviceProperties(&prop, ix->device));
+  BHIP(hipGetDeviceProperties(&prop, ix->device));
   ix->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   ix->d = d;
   ix->dp = (d + 127) / 128 * 128;
@@ -411,25 +691,6 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   while ((int64_t(1) << ix->depth) < capacity) ++ix->depth;
   ix->dtype = dtype;
   ix->formats = pool_formats | GT_POOL_F32;
-
-  auto bail = [&](gt_status st) {
-    std::string keep = g_err;
-    free_all(ix);
-    delete ix;
-    g_err = keep;
-    return st;
-  };
-#define BTRY(expr)                 \
-  do {                             \
-    gt_status s_ = (expr);         \
-    if (s_ != GT_OK) return bail(s_); \
-  } while (0)
-#define BHIP(expr)                                                                    \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess)                                                             \
-      return bail(fail(GT_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_))); \
-  } while (0)
 
   const size_t cap = (size_t)capacity, dp = (size_t)ix->dp, tree = (cap - 1) * dp;
   BTRY(dalloc(ix, &ix->leaves, cap * dp));
@@ -458,7 +719,8 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   unsigned int herr = 0;
   BHIP(hipMemcpyAsync(&herr, derr, 4, hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));
-  if (herr) return bail(fail(GT_ERR_INVALID_INPUT, "features contain a NaN, infinite or negative value"));
+  if (herr)
+    return bail(fail(GT_ERR_INVALID_INPUT, "features contain a NaN, infinite or negative value"));
   ix->n = n;
 
   // pools, bottom-up; only pools covering some of the first n leaves are non-zero
@@ -483,6 +745,10 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   }
   BHIP(hipMemcpyAsync(&ix->m_min, ix->d_mmin, 8, hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));
+  gt_batch* def = new gt_batch();
+  def->ix = ix;
+  ix->def = def;
+  BTRY(batch_init(def));
 #undef BTRY
 #undef BHIP
   *out = ix;
@@ -524,6 +790,11 @@ gt_status gt_insert(gt_index* ix, const void* feats_dev, int64_t n_new, void* st
     HIPCHK(hipStreamSynchronize(s));
     return fail(GT_ERR_INVALID_INPUT, "inserted rows contain a NaN, infinite or negative value");
   }
+  // A float8 level that must be rescaled is rewritten whole; calls in flight
+  // on other streams must not read it meanwhile, so the device is drained
+  // first when float8 pools exist.  Float32 and bfloat16 pools only grow
+  // (upward-rounded sums of non-negative rows), which in-flight calls tolerate.
+  if (ix->pfp8) HIPCHK(hipDeviceSynchronize());
   // pools on the root-to-leaf paths of the new rows, re-derived bottom-up
   for (int l = ix->depth - 1; l >= 0; --l) {
     const int sh = ix->depth - l;
@@ -562,206 +833,84 @@ gt_status gt_query_batch(gt_index* ix, const float* q_dev, int32_t nq, const dou
                          gt_pool fmt, int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
                          float* sims_dev, int64_t* total_out, void* stream) {
   g_err.clear();
-  const int f = (int)fmt;
-  if (f != GT_POOL_F32 && f != GT_POOL_BF16 && f != GT_POOL_FP8E4M3)
-    return fail(GT_ERR_INVALID_ARG, "unknown pool format");
-  const int tq = tq_of(f);
-  TRY(check_query_args(ix, q_dev, nq, rho_host, max_results, offsets_dev, ids_dev, sims_dev,
-                       total_out, tq));
-  if (!(ix->formats & (uint32_t)f)) return fail(GT_ERR_INVALID_ARG, "pool format was not built");
-  if (ix->dp > maxdp_of(f))
-    return fail(GT_ERR_INVALID_ARG, "d too large for this pool format (padded d <= " +
-                                        std::to_string(maxdp_of(f)) + ")");
-  hipStream_t s = (hipStream_t)stream;
-  *total_out = 0;
-  const int nt = (nq + tq - 1) / tq;
-  const int nq_pad = std::max(128, (nq + 127) / 128 * 128);
-  TRY(ensure_query_buffers(ix, nq_pad, std::max(nt, 1)));
-  if (nq == 0) {
-    if (offsets_dev) TRY(zero_dev(offsets_dev, 8, s));
-    return GT_OK;
-  }
-  Timer tm(ix, s);
-  tm.mark(0);
-  TRY(zero_dev(ix->ctr, sizeof(gt::DevCounters), s));
-  TRY(zero_dev(ix->qcount, (size_t)nq_pad * 4, s));
-  TRY(zero_dev(ix->tile_mask, (size_t)gt::kMaxTiles * 8, s));
-  TRY(zero_dev(ix->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles * 4, s));
-  if (ix->count_unique) {
-    if (!ix->bitmap) TRY(dalloc(ix, &ix->bitmap, bitmap_words(ix)));
-    TRY(zero_dev(ix->bitmap, bitmap_words(ix) * 4, s));
-  }
-  ix->counted = ix->count_unique;
-  memcpy(ix->h_rho, rho_host, (size_t)nq * 8);
-  HIPCHK(hipMemcpyAsync(ix->rho, ix->h_rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(gt::launch_query_prep(q_dev, nq, ix->d, ix->dp, tq, ix->rho, ix->d_mmin, ix->qf, ix->qbf,
-                               ix->q8, ix->qexp, ix->invn_q, ix->qq, ix->thr, ix->thr_gemm,
-                               ix->tile_mask, &ix->ctr->err, nq_pad, s));
-  tm.mark(1);
-
-  const int D = ix->depth, h = head_of(ix);
-  const int grid = ix->grid > 0 ? ix->grid : ix->n_cu;
-  const size_t dp = (size_t)ix->dp;
-  const void* qtile = f == GT_POOL_F32 ? (const void*)ix->qf
-                      : f == GT_POOL_BF16 ? (const void*)ix->qbf : (const void*)ix->q8;
-  const size_t esz = f == GT_POOL_F32 ? 4 : f == GT_POOL_BF16 ? 2 : 1;
-  const unsigned char* pool_base = f == GT_POOL_F32 ? (const unsigned char*)ix->master
-                                   : f == GT_POOL_BF16 ? (const unsigned char*)ix->pbf16
-                                                       : (const unsigned char*)ix->pfp8;
-  ix->frontier_launches = 0;
-  if (ix->n > 0) {
-    for (int l = h; l <= D - 2; ++l) {
-      gt::WalkLevelArgs a{};
-      a.level = l;
-      a.dense = (l == h);
-      a.nt = nt;
-      a.dp = ix->dp;
-      a.cap = (int)ix->fr_cap;
-      a.child_rows = pool_base + (size_t)level_row(l + 1) * dp * esz;
-      a.in_node = ix->fr_node[l & 1];
-      a.in_mask = ix->fr_mask[l & 1];
-      a.in_count = ix->lvl_count + (size_t)l * gt::kMaxTiles;
-      a.out_node = ix->fr_node[(l + 1) & 1];
-      a.out_mask = ix->fr_mask[(l + 1) & 1];
-      a.out_count = ix->lvl_count + (size_t)(l + 1) * gt::kMaxTiles;
-      a.tile_mask = ix->tile_mask;
-      a.qtile = qtile;
-      a.thr = ix->thr;
-      a.qexp = ix->qexp;
-      a.lexp = ix->lexp[l + 1];
-      a.stat_pairs = &ix->ctr->pairs[l + 1];
-      a.bitmap = ix->count_unique ? ix->bitmap : nullptr;
-      a.bit_base = level_row(l + 1);
-      tm.launch_begin();
-      HIPCHK(gt::launch_walk_level(f, a, grid, s));
-      tm.launch_end();
-      ix->frontier_launches++;
-    }
-  }
-  tm.mark(2);
-  gt::LeafArgs la{};
-  la.level = D - 1;
-  la.dense = (h == D - 1);
-  la.nt = nt;
-  la.dp = ix->dp;
-  la.cap = (int)ix->fr_cap;
-  la.tq = tq;
-  la.in_node = ix->fr_node[(D - 1) & 1];
-  la.in_mask = ix->fr_mask[(D - 1) & 1];
-  la.in_count = ix->lvl_count + (size_t)(D - 1) * gt::kMaxTiles;
-  la.tile_mask = ix->tile_mask;
-  la.leaves = ix->leaves;
-  la.invn_f = ix->invn;
-  la.qf = ix->qf;
-  la.invn_q = ix->invn_q;
-  la.rho = ix->rho;
-  la.n_epoch = ix->n;
-  la.qcount = ix->qcount;
-  la.ctr = ix->ctr;
-  la.bitmap = ix->count_unique ? ix->bitmap : nullptr;
-  la.bit_base = level_row(D);
-  auto run_leaf = [&]() -> gt_status {
-    la.hits = ix->hits;
-    la.band_idx = ix->band_idx;
-    la.hit_cap = (unsigned long long)ix->hit_cap;
-    if (ix->n > 0) HIPCHK(gt::launch_leaf(la, ix->n_cu * 4, s));
-    return GT_OK;
-  };
-  TRY(run_leaf());
-  tm.mark(3);
-  ix->last_nq = nq;
-  ix->last_nt = nt;
-  ix->last_fmt = f;
-  ix->last_head = h;
-  gt_status st = finish_query(ix, nq, nq_pad, max_results, offsets_dev, ids_dev, sims_dev,
-                              total_out, s, tm, run_leaf);
-  if (tm.on) {
-    ix->ms[0] = tm.between(0, 1);
-    ix->ms[1] = tm.walk_ms();
-    ix->ms[2] = tm.between(2, 3);
-    ix->ms[5] = 0.0;
-  }
-  return st;
+  if (!ix) return fail(GT_ERR_INVALID_ARG, "index is NULL");
+  if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
+  if (!offsets_dev) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
+  if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
+  TRY(submit(ix, ix->def, 1, q_dev, nq, rho_host, (int)fmt, (hipStream_t)stream));
+  return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out);
 }
 
 gt_status gt_exhaustive(gt_index* ix, const float* q_dev, int32_t nq, const double* rho_host,
                         int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
                         float* sims_dev, int64_t* total_out, void* stream) {
   g_err.clear();
-  TRY(check_query_args(ix, q_dev, nq, rho_host, max_results, offsets_dev, ids_dev, sims_dev,
-                       total_out, gt::kQueriesPerTile16));
-  hipStream_t s = (hipStream_t)stream;
-  *total_out = 0;
-  const int tq = gt::kQueriesPerTile16;
-  const int nt = (nq + tq - 1) / tq;
-  const int nq_pad = std::max(128, (nq + 127) / 128 * 128);
-  TRY(ensure_query_buffers(ix, nq_pad, std::max(nt, 1)));
-  if (!ix->cand) {
-    ix->cand_cap = int64_t(1) << 20;
-    TRY(dalloc(ix, &ix->cand, (size_t)ix->cand_cap));
+  if (!ix) return fail(GT_ERR_INVALID_ARG, "index is NULL");
+  if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
+  if (!offsets_dev) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
+  if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
+  TRY(submit(ix, ix->def, 2, q_dev, nq, rho_host, 0, (hipStream_t)stream));
+  return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out);
+}
+
+gt_status gt_batch_create(gt_index* ix, int32_t max_queries, gt_batch** out) {
+  g_err.clear();
+  if (!ix || !out) return fail(GT_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (max_queries < 1 || max_queries > gt::kMaxTiles * gt::kQueriesPerTileF32)
+    return fail(GT_ERR_INVALID_ARG, "max_queries out of range");
+  gt_batch* b = new gt_batch();
+  b->ix = ix;
+  b->max_queries = max_queries;
+  gt_status st = batch_init(b);
+  const int nq_pad = (max_queries + 127) / 128 * 128;
+  const int nt = (max_queries + gt::kQueriesPerTileF32 - 1) / gt::kQueriesPerTileF32;
+  if (st == GT_OK) st = batch_reserve(b, nq_pad, nt);
+  if (st != GT_OK) {
+    std::string keep = g_err;
+    free_batch(b);
+    delete b;
+    g_err = keep;
+    return st;
   }
-  if (nq == 0) {
-    if (offsets_dev) TRY(zero_dev(offsets_dev, 8, s));
-    return GT_OK;
-  }
-  Timer tm(ix, s);
-  tm.mark(0);
-  TRY(zero_dev(ix->ctr, sizeof(gt::DevCounters), s));
-  TRY(zero_dev(ix->qcount, (size_t)nq_pad * 4, s));
-  TRY(zero_dev(ix->tile_mask, (size_t)gt::kMaxTiles * 8, s));
-  memcpy(ix->h_rho, rho_host, (size_t)nq * 8);
-  HIPCHK(hipMemcpyAsync(ix->rho, ix->h_rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
-  HIPCHK(gt::launch_query_prep(q_dev, nq, ix->d, ix->dp, tq, ix->rho, ix->d_mmin, ix->qf, ix->qbf,
-                               ix->q8, ix->qexp, ix->invn_q, ix->qq, ix->thr, ix->thr_gemm,
-                               ix->tile_mask, &ix->ctr->err, nq_pad, s));
-  tm.mark(1);
-  auto run_gemm_and_check = [&]() -> gt_status {
-    HIPCHK(gt::launch_exhaustive_gemm(ix->qf, nq_pad, ix->leaves, ix->n, ix->dp, ix->thr_gemm,
-                                      ix->nf, ix->cand, (unsigned long long)ix->cand_cap, ix->ctr,
-                                      nq, s));
-    tm.mark(2);
-    HIPCHK(gt::launch_pair_check(ix->cand, &ix->ctr->ncand, (unsigned long long)ix->cand_cap,
-                                 ix->qf, ix->leaves, ix->invn_q, ix->invn, ix->rho, ix->dp,
-                                 ix->hits, (unsigned long long)ix->hit_cap, ix->band_idx,
-                                 ix->qcount, ix->ctr, ix->n_cu * 4, s));
-    tm.mark(3);
-    return GT_OK;
-  };
-  TRY(run_gemm_and_check());
-  ix->last_nq = nq;
-  ix->last_nt = nt;
-  ix->last_fmt = 0;
-  ix->frontier_launches = 0;
-  for (int attempt = 0;; ++attempt) {
-    bool cand_over = false;
-    gt_status st = finish_query(ix, nq, nq_pad, max_results, offsets_dev, ids_dev, sims_dev,
-                                total_out, s, tm, [&]() -> gt_status {
-                                  TRY(zero_dev(&ix->ctr->ncand, 8, s));
-                                  return run_gemm_and_check();
-                                }, &cand_over);
-    if (st != GT_OK) return st;
-    if (!cand_over) break;
-    // the candidate list overflowed: grow it and redo the whole pass
-    if (attempt > 2) return fail(GT_ERR_DEVICE, "candidate list did not converge");
-    const int64_t need = (int64_t)ix->h_ctr->ncand;
-    dfree(ix, &ix->cand, (size_t)ix->cand_cap);
-    ix->cand_cap = 0;
-    TRY(dalloc(ix, &ix->cand, (size_t)(need + need / 4 + 1024)));
-    ix->cand_cap = need + need / 4 + 1024;
-    TRY(zero_dev(ix->ctr, sizeof(gt::DevCounters), s));
-    TRY(zero_dev(ix->qcount, (size_t)nq_pad * 4, s));
-    HIPCHK(gt::launch_query_prep(q_dev, nq, ix->d, ix->dp, tq, ix->rho, ix->d_mmin, ix->qf, ix->qbf,
-                                 ix->q8, ix->qexp, ix->invn_q, ix->qq, ix->thr, ix->thr_gemm,
-                                 ix->tile_mask, &ix->ctr->err, nq_pad, s));
-    TRY(run_gemm_and_check());
-  }
-  if (tm.on) {
-    ix->ms[0] = tm.between(0, 1);
-    ix->ms[5] = tm.between(1, 2);
-    ix->ms[2] = tm.between(2, 3);
-    ix->ms[1] = 0.0;
+  *out = b;
+  return GT_OK;
+}
+
+gt_status gt_batch_submit(gt_batch* b, const float* q_dev, int32_t nq, const double* rho_host,
+                          gt_pool fmt, void* stream) {
+  g_err.clear();
+  if (!b) return fail(GT_ERR_INVALID_ARG, "batch is NULL");
+  return submit(b->ix, b, 1, q_dev, nq, rho_host, (int)fmt, (hipStream_t)stream);
+}
+
+gt_status gt_batch_poll(gt_batch* b, int32_t* done_out) {
+  g_err.clear();
+  if (!b || !done_out) return fail(GT_ERR_INVALID_ARG, "NULL argument");
+  if (!b->pending) return fail(GT_ERR_INVALID_ARG, "no call in flight on this workspace");
+  const hipError_t e = hipEventQuery(b->done);
+  if (e == hipSuccess) {
+    *done_out = 1;
+  } else if (e == hipErrorNotReady) {
+    *done_out = 0;
+  } else {
+    return fail(GT_ERR_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(e));
   }
   return GT_OK;
+}
+
+gt_status gt_batch_finish(gt_batch* b, int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
+                          float* sims_dev, int64_t* total_out) {
+  g_err.clear();
+  if (!b) return fail(GT_ERR_INVALID_ARG, "batch is NULL");
+  return finish(b->ix, b, max_results, offsets_dev, ids_dev, sims_dev, total_out);
+}
+
+void gt_batch_destroy(gt_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+  delete b;
 }
 
 gt_status gt_get_stats(const gt_index* ix, gt_stats* out) {
@@ -778,18 +927,20 @@ gt_status gt_get_stats(const gt_index* ix, gt_stats* out) {
   out->m_min = ix->m_min;
   out->epoch = ix->epoch;
   out->bytes_device = ix->bytes;
-  out->last_nq = ix->last_nq;
-  out->last_tiles = ix->last_nt;
-  out->last_format = ix->last_fmt;
-  if (ix->ctr && ix->last_nt > 0) {
+  for (int l = 0; l < GT_MAX_LEVELS; ++l) out->fp8_exp[l] = ix->lexp[l];
+  const Batch* b = ix->def;
+  out->last_nq = b->last_nq;
+  out->last_tiles = b->last_nt;
+  out->last_format = b->last_fmt;
+  if (b->ctr && b->last_nt > 0) {
     HIPCHK(hipDeviceSynchronize());
     std::vector<uint32_t> cnt((size_t)GT_MAX_LEVELS * gt::kMaxTiles);
-    HIPCHK(hipMemcpy(cnt.data(), ix->lvl_count, cnt.size() * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cnt.data(), b->lvl_count, cnt.size() * 4, hipMemcpyDeviceToHost));
     gt::DevCounters c;
-    HIPCHK(hipMemcpy(&c, ix->ctr, sizeof(c), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&c, b->ctr, sizeof(c), hipMemcpyDeviceToHost));
     for (int l = 0; l < ix->depth && l < GT_MAX_LEVELS; ++l) {
       int64_t e = 0;
-      for (int t = 0; t < ix->last_nt; ++t) e += cnt[(size_t)l * gt::kMaxTiles + t];
+      for (int t = 0; t < b->last_nt; ++t) e += cnt[(size_t)l * gt::kMaxTiles + t];
       out->entries[l] = e;
       out->pairs[l] = (int64_t)c.pairs[l];
     }
@@ -797,26 +948,26 @@ gt_status gt_get_stats(const gt_index* ix, gt_stats* out) {
     out->candidates = (int64_t)c.nhits;
     out->rechecked = (int64_t)c.rechecked;
     out->results = (int64_t)c.total;
-  }
-  out->ms_prep = ix->ms[0];
-  out->ms_frontier = ix->ms[1];
-  out->ms_leaf = ix->ms[2];
-  out->ms_recheck = ix->ms[3];
-  out->ms_compact = ix->ms[4];
-  out->ms_gemm = ix->ms[5];
-  out->ms_total = ix->ms[6];
-  out->frontier_launches = ix->frontier_launches;
-  for (int l = 0; l < GT_MAX_LEVELS; ++l) out->fp8_exp[l] = ix->lexp[l];
-  if (ix->counted && ix->bitmap) {
-    std::vector<uint32_t> bm(bitmap_words(ix));
-    HIPCHK(hipDeviceSynchronize());
-    HIPCHK(hipMemcpy(bm.data(), ix->bitmap, bm.size() * 4, hipMemcpyDeviceToHost));
-    for (int l = 0; l <= ix->depth && l < GT_MAX_LEVELS; ++l) {
-      int64_t c = 0;
-      for (int64_t r = level_row(l); r < level_row(l + 1); ++r) c += (bm[r >> 5] >> (r & 31)) & 1u;
-      out->unique_rows[l] = c;
+    if (b->counted && b->bitmap) {
+      std::vector<uint32_t> bm((size_t)b->bitmap_words);
+      HIPCHK(hipMemcpy(bm.data(), b->bitmap, bm.size() * 4, hipMemcpyDeviceToHost));
+      for (int l = 0; l <= ix->depth && l < GT_MAX_LEVELS; ++l) {
+        int64_t k = 0;
+        for (int64_t r = level_row(l); r < level_row(l + 1); ++r) k += (bm[r >> 5] >> (r & 31)) & 1u;
+        out->unique_rows[l] = k;
+      }
     }
   }
+  out->ms_prep = b->ms[0];
+  out->ms_frontier = b->ms[1];
+  out->ms_leaf = b->ms[2];
+  out->ms_recheck = b->ms[3];
+  out->ms_compact = b->ms[4];
+  out->ms_gemm = b->ms[5];
+  out->ms_total = b->ms[6];
+  out->ms_dense = b->ms[7];
+  out->frontier_launches = b->frontier_launches;
+  out->dense_launches = b->dense_launches;
   return GT_OK;
 }
 
@@ -851,6 +1002,9 @@ gt_status gt_set_option(gt_index* ix, const char* key, int64_t value) {
   } else if (!strcmp(key, "head_level")) {
     if (value < -1 || value > ix->depth - 1) return fail(GT_ERR_INVALID_ARG, "head_level out of range");
     ix->head_level = (int)value;
+  } else if (!strcmp(key, "dense_last")) {
+    if (value < -2 || value > ix->depth - 1) return fail(GT_ERR_INVALID_ARG, "dense_last out of range");
+    ix->dense_last = (int)value;
   } else if (!strcmp(key, "count_unique")) {
     ix->count_unique = value != 0;
   } else if (!strcmp(key, "grid")) {
@@ -865,7 +1019,11 @@ gt_status gt_set_option(gt_index* ix, const char* key, int64_t value) {
 void gt_destroy(gt_index* ix) {
   if (!ix) return;
   (void)hipDeviceSynchronize();
-  free_all(ix);
+  if (ix->def) {
+    free_batch(ix->def);
+    delete static_cast<gt_batch*>(ix->def);
+  }
+  free_tree(ix);
   delete ix;
 }
 

@@ -61,6 +61,25 @@ struct WalkLevelArgs {
   int64_t bit_base;         // tree row of node 0 of level+1
 };
 
+// Arguments of a dense level step (children at `level`, all 2^level pools).
+struct DenseLevelArgs {
+  int level, nt, dp, cap;
+  const void* child_rows;   // first row of `level` in the pool format
+  const void* qtile;        // [nt * 64 * dp] queries in the pool format
+  const float* thr;
+  const int* qexp;
+  int lexp;                 // float8 scale exponent of `level`
+  const uint64_t* parent;   // [2^(level-1) x nt] survival masks, or NULL: tile masks
+  const uint64_t* tile_mask;
+  uint64_t* out_dense;      // [2^level x nt], or NULL: sparse output below
+  uint32_t* out_node;
+  uint64_t* out_mask;
+  uint32_t* out_count;      // [nt] entries (sparse) or non-empty masks (dense)
+  unsigned long long* stat_pairs;
+  uint32_t* bitmap;
+  int64_t bit_base;
+};
+
 struct LeafArgs {
   int level, dense, nt, dp, cap, tq;
   const uint32_t* in_node;
@@ -82,42 +101,21 @@ struct LeafArgs {
   int64_t bit_base;         // tree row of leaf 0
 };
 
-struct Index {
-  int device = 0;
-  int n_cu = 256;
-  int64_t n = 0, cap = 0;
-  int d = 0, dp = 0, depth = 0;
-  gt_dtype dtype = GT_F32;
-  uint32_t formats = 0;
-  uint64_t epoch = 0;
-  int head_level = -1;       // -1: automatic
-  int grid = 0;              // 0: one workgroup per CU
-  bool profile = false;
-  bool count_unique = false;
-  bool counted = false;      // bitmap holds the last call's rows
-  uint32_t* bitmap = nullptr;
-  double m_min = 0.0;        // host copy
+struct Index;
 
-  // device memory of the tree
-  float* leaves = nullptr;   // [cap x dp]
-  float* invn = nullptr;     // [cap]
-  double* ff = nullptr;      // [cap] canonical squared norms
-  double* d_mmin = nullptr;  // device copy of m_min (as a double)
-  float* master = nullptr;   // levels 0..depth-1, level l at row (2^l - 1)
-  uint16_t* pbf16 = nullptr;
-  uint8_t* pfp8 = nullptr;
-  int* d_lexp = nullptr;     // [depth + 1] float8 scale exponents per level
-  int lexp[GT_MAX_LEVELS] = {0};
-  float* d_levelmax = nullptr;
-  unsigned int* d_flags = nullptr;  // [depth + 1] float8 overflow flags per level
-
-  // per-call work buffers (grown on demand)
+// Device workspace of one query call (query copies, frontiers, counters,
+// candidate and result staging).  The index owns one for the synchronous
+// entry points; gt_batch_create makes more so that calls can be in flight on
+// several streams at once.
+struct Batch {
+  Index* ix = nullptr;
+  int max_queries = 0;       // 0: grows on demand (the index's own workspace)
   int nt_alloc = 0;
   int nq_alloc = 0;
   uint32_t* fr_node[2] = {nullptr, nullptr};
   uint64_t* fr_mask[2] = {nullptr, nullptr};
   int64_t fr_cap = 0;        // entries per tile per buffer
-  uint32_t* lvl_count = nullptr;    // [(depth + 1) x kMaxTiles]
+  uint32_t* lvl_count = nullptr;    // [GT_MAX_LEVELS x kMaxTiles]
   uint64_t* tile_mask = nullptr;    // [kMaxTiles]
   float* qf = nullptr;       // [nq_pad x dp]
   uint16_t* qbf = nullptr;
@@ -128,10 +126,9 @@ struct Index {
   double* rho = nullptr;
   float* thr = nullptr;
   float* thr_gemm = nullptr;
-  float* nf = nullptr;       // [cap] float32 norms rounded down (GEMM epilogue)
   unsigned int* qcount = nullptr;
   unsigned int* qcursor = nullptr;
-  int64_t* offs = nullptr;   // [nq + 1] internal offsets
+  int64_t* offs = nullptr;   // [nq + 1]
   Hit* hits = nullptr;
   uint32_t* band_idx = nullptr;
   int64_t hit_cap = 0;
@@ -142,16 +139,66 @@ struct Index {
   uint32_t* tmp_id = nullptr;
   float* tmp_sim = nullptr;
   int64_t out_cap = 0;
+  uint64_t* dmask[2] = {nullptr, nullptr};  // dense survival masks, ping-pong
+  int64_t dmask_len = 0;
+  uint32_t* bitmap = nullptr;
+  int64_t bitmap_words = 0;
+  bool counted = false;
   DevCounters* ctr = nullptr;
   DevCounters* h_ctr = nullptr;  // pinned
   double* h_rho = nullptr;       // pinned staging for thresholds
-  int h_rho_cap = 0;
+  hipEvent_t done = nullptr;     // counters copied to h_ctr
+  hipEvent_t ev[8] = {};
+  hipEvent_t evw[2 * GT_MAX_LEVELS] = {};
+  bool evw_dense[GT_MAX_LEVELS] = {};
+  int nw = 0;
+  bool events = false;
+
+  // the call in flight (between submit and finish)
+  bool pending = false;
+  int kind = 0;              // 1: walk, 2: exhaustive
+  hipStream_t stream = nullptr;
+  int fmt = 0, nq = 0, nq_pad = 0, nt = 0, tq = 0, head = 0, dense_last = -1;
+  int64_t n_epoch = 0;       // vectors visible to the call (ids below this)
+  bool profile = false;
+
+  // counters of the last finished call
+  int last_nq = 0, last_nt = 0, last_fmt = 0;
+  double ms[8] = {0};
+  int frontier_launches = 0, dense_launches = 0;
+};
+
+struct Index {
+  int device = 0;
+  int n_cu = 256;
+  int64_t n = 0, cap = 0;
+  int d = 0, dp = 0, depth = 0;
+  gt_dtype dtype = GT_F32;
+  uint32_t formats = 0;
+  uint64_t epoch = 0;
+  int head_level = -1;       // -1: automatic
+  int grid = 0;              // 0: one workgroup per CU
+  int dense_last = -2;       // last level walked densely (-2: automatic, -1: none)
+  bool profile = false;
+  bool count_unique = false;
+  double m_min = 0.0;        // host copy
   int64_t bytes = 0;
 
-  // stats of the last call
-  int last_nq = 0, last_nt = 0, last_fmt = 0, last_head = 0;
-  double ms[7] = {0};
-  int frontier_launches = 0;
+  // device memory of the tree
+  float* leaves = nullptr;   // [cap x dp]
+  float* invn = nullptr;     // [cap]
+  double* ff = nullptr;      // [cap] canonical squared norms
+  float* nf = nullptr;       // [cap] float32 norms rounded down (GEMM epilogue)
+  double* d_mmin = nullptr;  // device copy of m_min, and a scratch slot
+  float* master = nullptr;   // levels 0..depth-1, level l at row (2^l - 1)
+  uint16_t* pbf16 = nullptr;
+  uint8_t* pfp8 = nullptr;
+  int* d_lexp = nullptr;     // float8 scale exponents per level
+  int lexp[GT_MAX_LEVELS] = {0};
+  float* d_levelmax = nullptr;
+  unsigned int* d_flags = nullptr;  // float8 overflow flags per level; last: input error
+
+  Batch* def = nullptr;      // workspace of gt_query_batch / gt_exhaustive
 };
 
 // ---- launch wrappers (kernels in k_build.hip, k_walk.hip, k_exhaustive.hip) ----
@@ -171,6 +218,7 @@ hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, cons
                              uint64_t* tile_mask, unsigned int* err, int nq_pad, hipStream_t s);
 hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s);
+hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s);
 hipError_t launch_recheck(Hit* hits, const uint32_t* band_idx, const unsigned long long* nband,
                           unsigned long long cap, const float* qf, const float* leaves, int d,
                           int dp, const double* qq, const double* ff, const double* rho,

@@ -76,62 +76,31 @@ __host__ __device__ __forceinline__ double pool_slack(int K) {
   return (double)(K + 2) * 0x1p-22;
 }
 
-// Fixed-order float32 dot product of two rows, wave-wide (64 lanes).  Lane l
-// owns elements [c*1024 + 16 l, +16) of chunk c; products are summed pairwise
-// within the lane, chunks in order, then a butterfly over lanes.  The result
-// is identical in every lane and depends only on the two rows.
+// In-lane part of a fixed-order float32 dot product of two rows, wave-wide
+// (64 lanes).  In chunk c (1024 elements), lane l owns the 16 elements
+//   c*1024 + 256 v + 4 l + j      (v, j = 0..3),
+// so each of the lane's four 16-byte loads belongs to one contiguous 1 KB
+// piece read by the whole wave.  The 16 products are summed pairwise in
+// (v, j) order; callers add the chunks in order and then sum over the lanes
+// with wave_reduce8.  The result depends only on the two rows.
 // Bound: |error| <= (5 + (chunks - 1) + 6) * 2^-24 * exact sum.
-__device__ __forceinline__ float wave_dot_f32(const float* __restrict__ a,
-                                              const float* __restrict__ b, int dp, int lane) {
-  float acc = 0.0f;
-  for (int c = 0; c * 1024 < dp; ++c) {
-    int base = c * 1024 + lane * 16;
-    float p[16];
-    if (base < dp) {
-      const float4* a4 = reinterpret_cast<const float4*>(a + base);
-      const float4* b4 = reinterpret_cast<const float4*>(b + base);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float4 x = a4[v], y = b4[v];
-        p[4 * v + 0] = __fmul_rn(x.x, y.x);
-        p[4 * v + 1] = __fmul_rn(x.y, y.y);
-        p[4 * v + 2] = __fmul_rn(x.z, y.z);
-        p[4 * v + 3] = __fmul_rn(x.w, y.w);
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) p[v] = 0.0f;
-    }
-#pragma unroll
-    for (int w = 1; w < 16; w *= 2)
-#pragma unroll
-      for (int i = 0; i < 16; i += 2 * w) p[i] = __fadd_rn(p[i], p[i + w]);
-    acc = (c == 0) ? p[0] : __fadd_rn(acc, p[0]);
-  }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) acc = __fadd_rn(acc, __shfl_xor(acc, m, 64));
-  return acc;
-}
-
-// Pairwise sum of the 16 products a[base + j] * b[base + j] (zero past dp) --
-// the in-lane part of wave_dot_f32.
 __device__ __forceinline__ float lane_partial16(const float* __restrict__ a,
-                                                const float* __restrict__ b, int base, int dp) {
+                                                const float* __restrict__ b, int chunk, int dp,
+                                                int lane) {
   float p[16];
-  if (base < dp) {
-    const float4* a4 = reinterpret_cast<const float4*>(a + base);
-    const float4* b4 = reinterpret_cast<const float4*>(b + base);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float4 x = a4[v], y = b4[v];
+  for (int v = 0; v < 4; ++v) {
+    const int e = chunk * 1024 + 256 * v + 4 * lane;
+    if (e < dp) {
+      const float4 x = *reinterpret_cast<const float4*>(a + e);
+      const float4 y = *reinterpret_cast<const float4*>(b + e);
       p[4 * v + 0] = __fmul_rn(x.x, y.x);
       p[4 * v + 1] = __fmul_rn(x.y, y.y);
       p[4 * v + 2] = __fmul_rn(x.z, y.z);
       p[4 * v + 3] = __fmul_rn(x.w, y.w);
+    } else {
+      p[4 * v + 0] = p[4 * v + 1] = p[4 * v + 2] = p[4 * v + 3] = 0.0f;
     }
-  } else {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) p[v] = 0.0f;
   }
 #pragma unroll
   for (int w = 1; w < 16; w *= 2)
@@ -140,10 +109,9 @@ __device__ __forceinline__ float lane_partial16(const float* __restrict__ a,
   return p[0];
 }
 
-// Sums eight per-lane values over the 64 lanes with the same pairing as the
-// butterfly of wave_dot_f32 (partners at lane distance 32, 16, 8, 4, 2, 1),
-// so each sum is bit-identical to it, but with 10 shuffles instead of 48.
-// Lanes 8v .. 8v+7 receive the sum of value v.
+// Sums eight per-lane values over the 64 lanes, each by the same tree
+// (partners at lane distance 32, 16, 8, 4, 2, 1), using 10 shuffles instead
+// of 6 per value.  Lanes 8v .. 8v+7 receive the sum of value v.
 __device__ __forceinline__ float wave_reduce8(const float (&a)[8], int lane) {
   const bool h = (lane >> 5) & 1, g = (lane >> 4) & 1, f = (lane >> 3) & 1;
   float b[4], c[2];

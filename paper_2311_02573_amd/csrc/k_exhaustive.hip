@@ -51,35 +51,49 @@ __global__ __launch_bounds__(256) void k_gemm_threshold(const float* __restrict_
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
-  // global -> register staging: 128 rows x 32 floats per operand, 4 float4 per thread
+  // global -> register staging: 128 rows x 32 floats per operand; thread tid
+  // moves float4 pieces tid + 256 v (v < 4): row = piece / 8 = tid / 8 + 32 v
   const float* qbase = qf + (size_t)qt * GT_ * dp;
   const int64_t r0 = rt * GT_;
-  float4 ra[4], rb[4];
-  auto gload = [&](int k0) {
+  const int prow = tid >> 3, pcol = (tid & 7) * 4;
+  const float* qa = qbase + (size_t)prow * dp + pcol;
+  const float* fb[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int idx = tid + v * 256;       // 0..1023
-      const int row = idx >> 3, col = (idx & 7) * 4;
-      ra[v] = *reinterpret_cast<const float4*>(qbase + (size_t)row * dp + k0 + col);
-      const int64_t rr = r0 + row < n ? r0 + row : n - 1;
-      rb[v] = *reinterpret_cast<const float4*>(rows + (size_t)rr * dp + k0 + col);
-    }
-  };
-  auto sstore = [&]() {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int idx = tid + v * 256;
-      const int row = idx >> 3, col = (idx & 7) * 4;
-      *reinterpret_cast<float4*>(&As[row * LDSW + col]) = ra[v];
-      *reinterpret_cast<float4*>(&Bs[row * LDSW + col]) = rb[v];
-    }
-  };
-  gload(0);
+  for (int v = 0; v < 4; ++v) {
+    const int64_t rr = r0 + prow + 32 * v < n ? r0 + prow + 32 * v : n - 1;
+    fb[v] = rows + (size_t)rr * dp + pcol;
+  }
+  const size_t q32 = (size_t)32 * dp;
+  float4 ra0 = *reinterpret_cast<const float4*>(qa);
+  float4 ra1 = *reinterpret_cast<const float4*>(qa + q32);
+  float4 ra2 = *reinterpret_cast<const float4*>(qa + 2 * q32);
+  float4 ra3 = *reinterpret_cast<const float4*>(qa + 3 * q32);
+  float4 rb0 = *reinterpret_cast<const float4*>(fb[0]);
+  float4 rb1 = *reinterpret_cast<const float4*>(fb[1]);
+  float4 rb2 = *reinterpret_cast<const float4*>(fb[2]);
+  float4 rb3 = *reinterpret_cast<const float4*>(fb[3]);
   for (int k0 = 0; k0 < dp; k0 += KC) {
     __syncthreads();
-    sstore();
+    *reinterpret_cast<float4*>(&As[(prow + 0) * LDSW + pcol]) = ra0;
+    *reinterpret_cast<float4*>(&As[(prow + 32) * LDSW + pcol]) = ra1;
+    *reinterpret_cast<float4*>(&As[(prow + 64) * LDSW + pcol]) = ra2;
+    *reinterpret_cast<float4*>(&As[(prow + 96) * LDSW + pcol]) = ra3;
+    *reinterpret_cast<float4*>(&Bs[(prow + 0) * LDSW + pcol]) = rb0;
+    *reinterpret_cast<float4*>(&Bs[(prow + 32) * LDSW + pcol]) = rb1;
+    *reinterpret_cast<float4*>(&Bs[(prow + 64) * LDSW + pcol]) = rb2;
+    *reinterpret_cast<float4*>(&Bs[(prow + 96) * LDSW + pcol]) = rb3;
     __syncthreads();
-    if (k0 + KC < dp) gload(k0 + KC);
+    if (k0 + KC < dp) {
+      const int kn = k0 + KC;
+      ra0 = *reinterpret_cast<const float4*>(qa + kn);
+      ra1 = *reinterpret_cast<const float4*>(qa + q32 + kn);
+      ra2 = *reinterpret_cast<const float4*>(qa + 2 * q32 + kn);
+      ra3 = *reinterpret_cast<const float4*>(qa + 3 * q32 + kn);
+      rb0 = *reinterpret_cast<const float4*>(fb[0] + kn);
+      rb1 = *reinterpret_cast<const float4*>(fb[1] + kn);
+      rb2 = *reinterpret_cast<const float4*>(fb[2] + kn);
+      rb3 = *reinterpret_cast<const float4*>(fb[3] + kn);
+    }
 #pragma unroll
     for (int t = 0; t < KC / 8; ++t) {
       float4 fa[2], fb[2];
@@ -155,11 +169,10 @@ __global__ __launch_bounds__(256) void k_pair_check(const uint2* cand, const uns
     for (int k = 0; k < 4; ++k) pr[k] = cand[b0 + k < n ? b0 + k : b0];
     float acc[8];
     for (int c = 0; c * 1024 < dp; ++c) {
-      const int base = c * 1024 + 16 * lane;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const float v = lane_partial16(qf + (size_t)pr[k].x * dp, leaves + (size_t)pr[k].y * dp,
-                                       base, dp);
+                                       c, dp, lane);
         acc[k] = c == 0 ? v : __fadd_rn(acc[k], v);
         acc[k + 4] = 0.0f;
       }

@@ -309,10 +309,202 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
   }
 }
 
+// Dense level step: every pool of a level against every query, as a matrix
+// product with a masked epilogue.  Used where almost every (pool, query tile)
+// pair is live (the first levels below the head), so reading each pool row
+// once per workgroup column and keeping the queries in LDS beats a per-tile
+// frontier, which would read each row once per tile.  A workgroup (4 waves)
+// computes 128 pools x 128 queries (2 tiles); each wave owns 64 pools x one
+// 64-query tile.  K is staged through LDS 128 bytes per row at a time with a
+// register prefetch of the next stage; several workgroups share a CU so one
+// computes while another waits for memory.  Child j of level L survives for
+// query b iff its parent's bit b is set and its score reaches tau'_b.  Output:
+// per-(pool, tile) masks for the next dense level, or the tiles' sparse
+// frontiers for the walk that follows.
+constexpr int kDR = 128, kDQ = 128, kDChunk = 128, kDStride = kDChunk + 16;
+
+template <int FMT>
+__global__ __launch_bounds__(256) void k_dense_level(DenseLevelArgs a) {
+  using F = WalkFmt<FMT>;
+  static_assert(F::TQ == 64, "dense steps use 64-query tiles");
+  __shared__ __attribute__((aligned(16))) unsigned char As[kDR * kDStride];
+  __shared__ __attribute__((aligned(16))) unsigned char Bs[kDQ * kDStride];
+  const int64_t rows = int64_t(1) << a.level;
+  const int64_t RB = (rows + kDR - 1) / kDR;
+  const int QB = (a.nt + 1) / 2;
+  const int64_t total = RB * QB;
+  const int64_t per_xcd = (total + 7) / 8;
+  const int64_t wid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (wid >= total) return;
+  const int qb = (int)(wid % QB);
+  const int64_t row0 = (wid / QB) * kDR;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wt = wave & 1;
+  const int t = qb * 2 + wt;
+  const int r = lane & 31, half = lane >> 5;
+  const int rowbytes = a.dp * F::ESZ;
+  const int nqrows = a.nt * 64;
+  const unsigned char* crow = reinterpret_cast<const unsigned char*>(a.child_rows);
+  const unsigned char* qrow = reinterpret_cast<const unsigned char*>(a.qtile);
+
+  // does any of this wave's 32 parents survive for tile t?
+  bool active = false;
+  if (t < a.nt) {
+    const int64_t par = ((row0 + wr * 64) >> 1) + (lane & 31);
+    uint64_t pm = 0ull;
+    if (2 * par < rows) pm = a.parent ? a.parent[par * a.nt + t] : a.tile_mask[t];
+    active = __ballot(pm != 0ull) != 0ull;
+  }
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int x = 0; x < 16; ++x) acc[i][j][x] = 0.0f;
+
+  // staging: thread tid moves the 16-byte pieces of rows tid/8 + 32 v (v < 4),
+  // byte (tid % 8) * 16 of each 128-byte stage, for pools and for queries
+  const int prow = tid >> 3, pc16 = (tid & 7) * 16;
+  const unsigned char* ga[4];
+  const unsigned char* gq[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t gr = row0 + prow + 32 * v < rows ? row0 + prow + 32 * v : rows - 1;
+    ga[v] = crow + (size_t)gr * rowbytes + pc16;
+    gq[v] = qrow + (size_t)min(qb * kDQ + prow + 32 * v, nqrows - 1) * rowbytes + pc16;
+  }
+  uint4 ra0 = *reinterpret_cast<const uint4*>(ga[0]);
+  uint4 ra1 = *reinterpret_cast<const uint4*>(ga[1]);
+  uint4 ra2 = *reinterpret_cast<const uint4*>(ga[2]);
+  uint4 ra3 = *reinterpret_cast<const uint4*>(ga[3]);
+  uint4 rq0 = *reinterpret_cast<const uint4*>(gq[0]);
+  uint4 rq1 = *reinterpret_cast<const uint4*>(gq[1]);
+  uint4 rq2 = *reinterpret_cast<const uint4*>(gq[2]);
+  uint4 rq3 = *reinterpret_cast<const uint4*>(gq[3]);
+  for (int k0 = 0; k0 < rowbytes; k0 += kDChunk) {
+    __syncthreads();
+    *reinterpret_cast<uint4*>(As + (prow + 0) * kDStride + pc16) = ra0;
+    *reinterpret_cast<uint4*>(As + (prow + 32) * kDStride + pc16) = ra1;
+    *reinterpret_cast<uint4*>(As + (prow + 64) * kDStride + pc16) = ra2;
+    *reinterpret_cast<uint4*>(As + (prow + 96) * kDStride + pc16) = ra3;
+    *reinterpret_cast<uint4*>(Bs + (prow + 0) * kDStride + pc16) = rq0;
+    *reinterpret_cast<uint4*>(Bs + (prow + 32) * kDStride + pc16) = rq1;
+    *reinterpret_cast<uint4*>(Bs + (prow + 64) * kDStride + pc16) = rq2;
+    *reinterpret_cast<uint4*>(Bs + (prow + 96) * kDStride + pc16) = rq3;
+    __syncthreads();
+    if (k0 + kDChunk < rowbytes) {
+      const int kn = k0 + kDChunk;
+      ra0 = *reinterpret_cast<const uint4*>(ga[0] + kn);
+      ra1 = *reinterpret_cast<const uint4*>(ga[1] + kn);
+      ra2 = *reinterpret_cast<const uint4*>(ga[2] + kn);
+      ra3 = *reinterpret_cast<const uint4*>(ga[3] + kn);
+      rq0 = *reinterpret_cast<const uint4*>(gq[0] + kn);
+      rq1 = *reinterpret_cast<const uint4*>(gq[1] + kn);
+      rq2 = *reinterpret_cast<const uint4*>(gq[2] + kn);
+      rq3 = *reinterpret_cast<const uint4*>(gq[3] + kn);
+    }
+    if (active) {
+#pragma unroll
+      for (int sl = 0; sl < kDChunk / 32; ++sl) {
+        uint4 b[2], av[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          b[j] = *reinterpret_cast<const uint4*>(Bs + (wt * 64 + j * 32 + r) * kDStride + 32 * sl + 16 * half);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          av[i] = *reinterpret_cast<const uint4*>(As + (wr * 64 + i * 32 + r) * kDStride + 32 * sl + 16 * half);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) mma16<FMT>(av[i], b[j], acc[i][j]);
+      }
+    }
+  }
+  if (t >= a.nt) return;
+
+  float thr[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int qi = t * 64 + 32 * j + r;
+    float th = a.thr[qi];
+    if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+    thr[j] = th;
+  }
+  unsigned long long pairs = 0;
+  const size_t tbase = (size_t)t * a.cap;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t row = row0 + wr * 64 + i * 32 + r;
+    const bool rv = lane < 32 && row < rows;
+    uint64_t pm = 0ull;
+    if (rv) pm = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
+    uint64_t mine = 0ull;
+#pragma unroll
+    for (int x = 0; x < 16; ++x) {
+      const uint64_t b0 = __ballot(acc[i][0][x] >= thr[0]);
+      const uint64_t b1 = __ballot(acc[i][1][x] >= thr[1]);
+      const uint64_t lo = (b0 & 0xffffffffull) | (b1 << 32);
+      const uint64_t hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
+      const int rr = 8 * (x >> 2) + (x & 3);
+      if (lane == rr) mine = lo;
+      if (lane == rr + 4) mine = hi;
+    }
+    mine &= pm;
+    if (rv) pairs += (unsigned long long)__popcll(pm);
+    if (a.bitmap && rv && pm) atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
+    const uint64_t eb = __ballot(rv && mine != 0ull);
+    if (a.out_dense) {
+      if (rv) a.out_dense[row * a.nt + t] = mine;
+      if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
+    } else if (eb) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
+      base = __shfl(base, 0, 64);
+      if (rv && mine) {
+        const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
+        a.out_node[tbase + pos] = (uint32_t)row;
+        a.out_mask[tbase + pos] = mine;
+      }
+    }
+  }
+  if (a.stat_pairs) {
+    for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
+    if (lane == 0 && pairs) atomicAdd(a.stat_pairs, pairs);
+  }
+}
+
 // Exact leaf test: entries (pool p at level depth-1, mask) -> vectors 2p and
-// 2p+1 for every query of the mask.  One wave per entry; the queries of up to
-// four mask bits are fetched together and the eight dot products (2 vectors x
-// 4 queries) are reduced at once.
+// 2p+1 for every query of the mask.  A wave takes two entries at a time and,
+// per round, up to two mask bits of each: 2 entries x 2 queries x 2 vectors =
+// eight dot products whose rows are all fetched together and reduced at once.
+// The next pair of entries is fetched while the current one is computed.
+struct LeafEntry {
+  int t;
+  uint32_t p;
+  uint64_t m;
+};
+
+__device__ __forceinline__ LeafEntry leaf_entry(const LeafArgs& a, const uint32_t* epre,
+                                                uint32_t idx, uint32_t etot) {
+  LeafEntry x;
+  x.t = 0;
+  x.p = 0;
+  x.m = 0ull;
+  if (idx >= etot) return x;
+  x.t = find_tile(epre, a.nt, idx);
+  const uint32_t e = idx - epre[x.t];
+  if (a.dense) {
+    x.p = e;
+    x.m = a.tile_mask[x.t];
+  } else {
+    x.p = a.in_node[(size_t)x.t * a.cap + e];
+    x.m = a.in_mask[(size_t)x.t * a.cap + e];
+  }
+  return x;
+}
+
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
   __shared__ uint32_t epre[kMaxTiles + 1];
   __shared__ Hit hstage[4][kHitStage];
@@ -320,70 +512,86 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
   tile_prefix(epre, a.nt, a.dense, a.level, a.tile_mask, a.in_count, 1);
   const uint32_t etot = epre[a.nt];
   const uint32_t nw = blockDim.x >> 6;
+  const uint32_t stride = 2u * gridDim.x * nw;
   Hit* buf = hstage[w];
   int cnt = 0;
   unsigned long long npairs = 0;
-  for (uint32_t idx = blockIdx.x * nw + w; idx < etot; idx += gridDim.x * nw) {
-    const int t = find_tile(epre, a.nt, idx);
-    const uint32_t e = idx - epre[t];
-    uint32_t p;
-    uint64_t pm;
-    if (a.dense) {
-      p = e;
-      pm = a.tile_mask[t];
-    } else {
-      p = a.in_node[(size_t)t * a.cap + e];
-      pm = a.in_mask[(size_t)t * a.cap + e];
-    }
-    const int64_t i0 = 2 * (int64_t)p, i1 = i0 + 1;
-    const float inv0 = i0 < a.n_epoch ? a.invn_f[i0] : 0.0f;
-    const float inv1 = i1 < a.n_epoch ? a.invn_f[i1] : 0.0f;
-    // a zero vector has no cosine and is never a member
-    if ((inv0 == 0.0f && inv1 == 0.0f) || pm == 0ull) continue;
-    if (a.bitmap && lane == 0) {
-      if (inv0 != 0.0f) atomicOr(&a.bitmap[(a.bit_base + i0) >> 5], 1u << ((a.bit_base + i0) & 31));
-      if (inv1 != 0.0f) atomicOr(&a.bitmap[(a.bit_base + i1) >> 5], 1u << ((a.bit_base + i1) & 31));
-    }
-    const float* f0 = a.leaves + i0 * a.dp;
-    const float* f1 = a.leaves + i1 * a.dp;
-    uint64_t m = pm;
-    while (m) {
-      int qs[4];
-      int nb = 0;
+  const int v = lane >> 3;              // value owned after the reduction
+  const int vs = v >> 2, vk = (v >> 1) & 1, vl = v & 1;
+  uint32_t idx = 2u * (blockIdx.x * nw + w);
+  LeafEntry nx0 = leaf_entry(a, epre, idx, etot), nx1 = leaf_entry(a, epre, idx + 1, etot);
+  for (; idx < etot; idx += stride) {
+    LeafEntry en[2] = {nx0, nx1};
+    nx0 = leaf_entry(a, epre, idx + stride, etot);
+    nx1 = leaf_entry(a, epre, idx + stride + 1, etot);
+    float inv[2][2];
+    const float* frow[2][2];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (m) {
-          qs[k] = t * a.tq + (__ffsll((unsigned long long)m) - 1);
-          m &= m - 1ull;
-          ++nb;
-        } else {
-          qs[k] = qs[0];
-        }
+    for (int s2 = 0; s2 < 2; ++s2) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int64_t i = 2 * (int64_t)en[s2].p + c;
+        inv[s2][c] = (en[s2].m && i < a.n_epoch) ? a.invn_f[i] : 0.0f;
+        frow[s2][c] = a.leaves + i * a.dp;
+        if (a.bitmap && lane == 0 && inv[s2][c] != 0.0f)
+          atomicOr(&a.bitmap[(a.bit_base + i) >> 5], 1u << ((a.bit_base + i) & 31));
       }
+      // a zero vector has no cosine and is never a member
+      if (inv[s2][0] == 0.0f && inv[s2][1] == 0.0f) en[s2].m = 0ull;
+    }
+    while (en[0].m | en[1].m) {
+      int qs[2][2];
+      bool qv[2][2];
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          qv[s2][k] = en[s2].m != 0ull;
+          qs[s2][k] = qv[s2][k] ? en[s2].t * a.tq + (__ffsll((unsigned long long)en[s2].m) - 1) : 0;
+          en[s2].m &= en[s2].m - 1ull;
+        }
       float acc[8];
       for (int c = 0; c * 1024 < a.dp; ++c) {
-        const int base = c * 1024 + 16 * lane;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const float* qrow = a.qf + (size_t)qs[k] * a.dp;
-          const float v0 = lane_partial16(qrow, f0, base, a.dp);
-          const float v1 = lane_partial16(qrow, f1, base, a.dp);
-          acc[2 * k] = c == 0 ? v0 : __fadd_rn(acc[2 * k], v0);
-          acc[2 * k + 1] = c == 0 ? v1 : __fadd_rn(acc[2 * k + 1], v1);
-        }
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const float* qrow = a.qf + (size_t)qs[s2][k] * a.dp;
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+              float val = 0.0f;
+              if (qv[s2][k] && inv[s2][l] != 0.0f) val = lane_partial16(qrow, frow[s2][l], c, a.dp, lane);
+              const int vi = 4 * s2 + 2 * k + l;
+              acc[vi] = c == 0 ? val : __fadd_rn(acc[vi], val);
+            }
+          }
       }
       const float dot = wave_reduce8(acc, lane);
-      const int v = lane >> 3, k = v >> 1, leaf = v & 1;
-      const float invf = leaf ? inv1 : inv0;
-      const bool mine = (lane & 7) == 0 && k < nb && invf != 0.0f;
+      // lane 8v classifies value v = (entry vs, query vk, vector vl)
+      int qg = 0;
+      bool ok = false;
+      float invf = 0.0f;
+      uint32_t id = 0;
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int l = 0; l < 2; ++l)
+            if (vs == s2 && vk == k && vl == l) {
+              qg = qs[s2][k];
+              ok = qv[s2][k] && inv[s2][l] != 0.0f;
+              invf = inv[s2][l];
+              id = 2u * en[s2].p + (uint32_t)l;
+            }
+      const bool mine = (lane & 7) == 0 && ok;
       Hit h;
       uint32_t flag = 0;
       if (mine) {
-        const int qg = qs[k];
         const float cs = __fmul_rn(__fmul_rn(dot, a.invn_q[qg]), invf);
         flag = classify(cs, a.rho[qg]);
         h.q = (uint32_t)qg;
-        h.id = (uint32_t)(leaf ? i1 : i0);
+        h.id = id;
         h.sim = cs;
         h.flag = flag;
         if (flag == HIT_ACCEPT) atomicAdd(&a.qcount[qg], 1u);
@@ -614,6 +822,23 @@ hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStrea
       break;
     case GT_POOL_F32:
       hipLaunchKernelGGL(k_walk_level<GT_POOL_F32>, dim3(grid), dim3(kWalkThreads), 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {
+  const int64_t rows = int64_t(1) << a.level;
+  const int64_t total = ((rows + kDR - 1) / kDR) * ((a.nt + 1) / 2);
+  const int64_t grid = 8 * ((total + 7) / 8);
+  switch (fmt) {
+    case GT_POOL_BF16:
+      hipLaunchKernelGGL(k_dense_level<GT_POOL_BF16>, dim3((unsigned)grid), dim3(256), 0, s, a);
+      break;
+    case GT_POOL_FP8E4M3:
+      hipLaunchKernelGGL(k_dense_level<GT_POOL_FP8E4M3>, dim3((unsigned)grid), dim3(256), 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;

@@ -25,8 +25,9 @@ POOL_F32, POOL_BF16, POOL_FP8 = 1, 2, 4
 POOLS = {"f32": POOL_F32, "bf16": POOL_BF16, "fp8": POOL_FP8}
 GT_MAX_LEVELS = 40
 
-EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_exhaustive", "gt_get_stats",
-           "gt_read_pools", "gt_set_option", "gt_destroy", "gt_last_error"]
+EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_exhaustive", "gt_batch_create",
+           "gt_batch_submit", "gt_batch_poll", "gt_batch_finish", "gt_batch_destroy",
+           "gt_get_stats", "gt_read_pools", "gt_set_option", "gt_destroy", "gt_last_error"]
 
 
 class GTError(RuntimeError):
@@ -53,6 +54,7 @@ class GTStats(ctypes.Structure):
         ("ms_total", ctypes.c_double), ("frontier_launches", ctypes.c_int32),
         ("fp8_exp", ctypes.c_int32 * GT_MAX_LEVELS),
         ("unique_rows", ctypes.c_int64 * GT_MAX_LEVELS),
+        ("dense_launches", ctypes.c_int32), ("ms_dense", ctypes.c_double),
     ]
 
 
@@ -72,6 +74,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(i64), vp]
     lib.gt_exhaustive.restype = st
     lib.gt_exhaustive.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp]
+    lib.gt_batch_create.restype = st
+    lib.gt_batch_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.gt_batch_submit.restype = st
+    lib.gt_batch_submit.argtypes = [vp, vp, i32, vp, ctypes.c_int, vp]
+    lib.gt_batch_poll.restype = st
+    lib.gt_batch_poll.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.gt_batch_finish.restype = st
+    lib.gt_batch_finish.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(i64)]
+    lib.gt_batch_destroy.restype = None
+    lib.gt_batch_destroy.argtypes = [vp]
     lib.gt_get_stats.restype = st
     lib.gt_get_stats.argtypes = [vp, ctypes.POINTER(GTStats)]
     lib.gt_read_pools.restype = st
@@ -142,6 +154,7 @@ class GTIndex:
                                    ctypes.byref(h)))
         self._h = h
         self._max_results = 1 << 16
+        self.n = feats.shape[0]
 
     def close(self):
         if getattr(self, "_h", None):
@@ -165,6 +178,7 @@ class GTIndex:
         first = ctypes.c_int64(-1)
         _check(lib().gt_insert(self._h, ctypes.c_void_p(feats.data_ptr()), feats.shape[0],
                                _stream_ptr(stream), ctypes.byref(first)))
+        self.n = first.value + feats.shape[0]
         return first.value
 
     def _run(self, fn, q, rho, max_results, stream, *extra):
@@ -222,3 +236,73 @@ class GTIndex:
 
     def set_option(self, key: str, value: int):
         _check(lib().gt_set_option(self._h, key.encode(), int(value)))
+
+
+class Workspace:
+    """A gt_batch: one asynchronous query call in flight at a time, on its own
+    stream.  submit() returns at once; poll() says whether the result count is
+    ready; finish() waits and returns Results."""
+
+    def __init__(self, index: "GTIndex", max_queries: int, stream=None):
+        self.index = index
+        self.max_queries = max_queries
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = ctypes.c_void_p()
+        _check(lib().gt_batch_create(index.handle, max_queries, ctypes.byref(h)))
+        self._h = h
+        self._q = None
+        self._rho = None
+        self._max_results = 1 << 16
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, q: torch.Tensor, rho, pool: str = "bf16"):
+        q = q.contiguous()
+        if q.dtype != torch.float32 or not q.is_cuda:
+            raise ValueError("queries must be a float32 device tensor")
+        nq = q.shape[0]
+        self._rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, dtype=np.float64), (nq,)))
+        self._q = q  # kept alive until finish
+        self._pool = pool
+        # the workspace's stream must see the queries written on the caller's stream
+        self.stream.wait_stream(torch.cuda.current_stream())
+        _check(lib().gt_batch_submit(self._h, ctypes.c_void_p(q.data_ptr()), nq,
+                                     ctypes.c_void_p(self._rho.ctypes.data), POOLS[pool],
+                                     ctypes.c_void_p(self.stream.cuda_stream)))
+        self._nq = nq
+
+    def poll(self) -> bool:
+        done = ctypes.c_int32(0)
+        _check(lib().gt_batch_poll(self._h, ctypes.byref(done)))
+        return bool(done.value)
+
+    def finish(self, max_results=None) -> Results:
+        dev = self._q.device
+        with torch.cuda.stream(self.stream):
+            offsets = torch.empty(self._nq + 1, dtype=torch.int64, device=dev)
+            cap = max_results if max_results is not None else self._max_results
+            total = ctypes.c_int64(0)
+            ids = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+            sims = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+            st = lib().gt_batch_finish(self._h, cap, ctypes.c_void_p(offsets.data_ptr()),
+                                       ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(sims.data_ptr()),
+                                       ctypes.byref(total))
+            if st == GT_ERR_RESULT_OVERFLOW and max_results is None:
+                # the call is complete; run it again with room for every result
+                self._max_results = max(self._max_results, total.value)
+                self.submit(self._q, self._rho, self._pool)
+                return self.finish(total.value)
+            _check(st)
+        torch.cuda.current_stream().wait_stream(self.stream)
+        res = Results(offsets, ids, sims, total.value)
+        self._q = None
+        return res

@@ -266,3 +266,21 @@ def test_result_of_a_query_does_not_depend_on_its_batch(gtmod):
         np.testing.assert_array_equal(alone[0], full[perm[0]][0])
         np.testing.assert_array_equal(alone[1], full[perm[0]][1])
     idx.close()
+
+
+@pytest.mark.parametrize("dense_last", [-1, -2, "deepest"])
+def test_dense_and_sparse_level_steps_agree(gtmod, dense_last):
+    """The walk may test the first levels densely (every pool x every query) and
+    the rest with per-tile frontiers; any split gives the oracle's result."""
+    w = synth.workload_small(20000, 300, 200, temp=0.2, seed_offset=17)
+    F = np.asarray(w.feats)
+    idx = gtmod.GTIndex(_dev(F))
+    depth = idx.stats()["depth"]
+    idx.set_option("dense_last", depth - 1 if dense_last == "deepest" else dense_last)
+    q = _dev(w.queries)
+    for rho in (0.6, 0.9):
+        ora = ob.range_search(F, w.queries, rho)
+        for f in FORMATS:
+            say(f"dense_last={dense_last} {f} rho={rho}")
+            assert_same(idx.query(q, rho, pool=f).to_lists(), ora, f"dense_last={dense_last} {f}")
+    idx.close()

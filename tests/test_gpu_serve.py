@@ -1,0 +1,90 @@
+"""Serving on the GPU: continuous batching over several workspaces on their own
+streams.  Every request's result in the mix must equal its result run alone
+(ids identical, similarities within 1e-6; they are in fact bit-identical), and
+with inserts between steps, the oracle's result over the rows indexed when
+the request was admitted."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.brute as ob
+from paper_2311_02573_amd import serve, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def gt():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2311_02573_amd import gt as g
+
+    g.lib()
+    return g
+
+
+def test_mix_equals_alone(gt):
+    w = synth.workload_small(60000, 256, 600, temp=0.2, seed_offset=31)
+    F = np.asarray(w.feats)
+    idx = gt.GTIndex(torch.from_numpy(F).cuda(), pools=("f32", "bf16"))
+    Q = torch.from_numpy(w.queries).cuda()
+    rng = np.random.default_rng(3)
+    srv = serve.Server(serve.GpuBackend(idx), n_workspaces=3, max_queries=192, pool="bf16")
+    reqs, off = [], 0
+    while off < len(w.queries):
+        k = int(min(rng.integers(1, 97), len(w.queries) - off))
+        rho = rng.uniform(0.75, 0.95, size=k)
+        reqs.append(serve.Request(len(reqs), Q[off:off + k], rho, arrival=srv.now()))
+        off += k
+    say(f"{len(reqs)} requests")
+    for r in reqs:
+        srv.submit(r)
+        srv.step()
+    srv.drain(timeout_s=120)
+    assert len(srv.finished) == len(reqs)
+    for r in reqs:
+        alone = idx.query(r.queries, r.rho, pool="bf16").to_lists()
+        for (gi, gs), (ai, as_) in zip(r.results, alone):
+            np.testing.assert_array_equal(gi, ai)
+            assert np.max(np.abs(gs.astype(np.float64) - as_), initial=0.0) <= 1e-6
+    sample = [reqs[0], reqs[len(reqs) // 2], reqs[-1]]
+    for r in sample:
+        ora = ob.range_search(F, r.queries.cpu().numpy(), r.rho)
+        for (gi, _), (oi, _) in zip(r.results, ora):
+            np.testing.assert_array_equal(gi, oi)
+    idx.close()
+
+
+def test_inserts_between_steps(gt):
+    w = synth.workload_small(40000, 128, 240, temp=0.25, seed_offset=32)
+    F = np.asarray(w.feats)
+    n0 = 25000
+    idx = gt.GTIndex(torch.from_numpy(F[:n0]).cuda(), capacity=65536, pools=("f32", "bf16"))
+    Q = torch.from_numpy(w.queries).cuda()
+    srv = serve.Server(serve.GpuBackend(idx), n_workspaces=2, max_queries=64, pool="bf16")
+    reqs = []
+    lo = n0
+    for i in range(12):
+        r = serve.Request(i, Q[20 * i:20 * i + 20], np.full(20, 0.88), arrival=srv.now())
+        srv.submit(r)
+        reqs.append(r)
+        srv.step()
+        if lo < len(F):
+            hi = min(len(F), lo + 1500)
+            idx.insert(torch.from_numpy(F[lo:hi]).cuda())
+            lo = hi
+    srv.drain(timeout_s=120)
+    epochs = sorted({r.epoch_n for r in reqs})
+    assert len(epochs) > 3
+    for r in reqs:
+        say(f"request {r.rid} epoch {r.epoch_n}")
+        ora = ob.range_search(F[:r.epoch_n], r.queries.cpu().numpy(), r.rho)
+        for (gi, gs), (oi, os_) in zip(r.results, ora):
+            np.testing.assert_array_equal(gi, oi)
+            if len(gs):
+                assert np.max(np.abs(gs.astype(np.float64) - os_)) <= 1e-6
+    idx.close()
