@@ -80,33 +80,39 @@ __host__ __device__ __forceinline__ double pool_slack(int K) {
 // (64 lanes).  In chunk c (1024 elements), lane l owns the 16 elements
 //   c*1024 + 256 v + 4 l + j      (v, j = 0..3),
 // so each of the lane's four 16-byte loads belongs to one contiguous 1 KB
-// piece read by the whole wave.  The 16 products are summed pairwise in
-// (v, j) order; callers add the chunks in order and then sum over the lanes
-// with wave_reduce8.  The result depends only on the two rows.
+// piece read by the whole wave.  The 16 products are summed pairwise:
+//   slice v:  (x0 y0 + x1 y1) + (x2 y2 + x3 y3)
+//   chunk:    (slice 0 + slice 1) + (slice 2 + slice 3)
+// Callers add the chunks in order and then sum over the lanes with
+// wave_reduce8; the result depends only on the two rows.  Slices past dp
+// count as zero; their loads are redirected to the last slice of the row so
+// that every load stays in bounds and no branch is needed.
 // Bound: |error| <= (5 + (chunks - 1) + 6) * 2^-24 * exact sum.
+__device__ __forceinline__ int slice_index(int chunk, int v, int lane, int dp, bool& ok) {
+  const int e4 = chunk * 256 + 64 * v + lane;  // float4 index within the row
+  ok = 4 * e4 < dp;
+  return ok ? e4 : (dp >> 2) - 1;
+}
+__device__ __forceinline__ float slice_dot4(const float4& x, const float4& y) {
+  return __fadd_rn(__fadd_rn(__fmul_rn(x.x, y.x), __fmul_rn(x.y, y.y)),
+                   __fadd_rn(__fmul_rn(x.z, y.z), __fmul_rn(x.w, y.w)));
+}
+__device__ __forceinline__ float chunk_sum4(float s0, float s1, float s2, float s3) {
+  return __fadd_rn(__fadd_rn(s0, s1), __fadd_rn(s2, s3));
+}
 __device__ __forceinline__ float lane_partial16(const float* __restrict__ a,
                                                 const float* __restrict__ b, int chunk, int dp,
                                                 int lane) {
-  float p[16];
+  float sv[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int e = chunk * 1024 + 256 * v + 4 * lane;
-    if (e < dp) {
-      const float4 x = *reinterpret_cast<const float4*>(a + e);
-      const float4 y = *reinterpret_cast<const float4*>(b + e);
-      p[4 * v + 0] = __fmul_rn(x.x, y.x);
-      p[4 * v + 1] = __fmul_rn(x.y, y.y);
-      p[4 * v + 2] = __fmul_rn(x.z, y.z);
-      p[4 * v + 3] = __fmul_rn(x.w, y.w);
-    } else {
-      p[4 * v + 0] = p[4 * v + 1] = p[4 * v + 2] = p[4 * v + 3] = 0.0f;
-    }
+    bool ok;
+    const int ec = slice_index(chunk, v, lane, dp, ok);
+    const float4 x = reinterpret_cast<const float4*>(a)[ec];
+    const float4 y = reinterpret_cast<const float4*>(b)[ec];
+    sv[v] = ok ? slice_dot4(x, y) : 0.0f;
   }
-#pragma unroll
-  for (int w = 1; w < 16; w *= 2)
-#pragma unroll
-    for (int i = 0; i < 16; i += 2 * w) p[i] = __fadd_rn(p[i], p[i + w]);
-  return p[0];
+  return chunk_sum4(sv[0], sv[1], sv[2], sv[3]);
 }
 
 // Sums eight per-lane values over the 64 lanes, each by the same tree

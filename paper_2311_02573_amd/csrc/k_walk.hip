@@ -550,22 +550,53 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
           qs[s2][k] = qv[s2][k] ? en[s2].t * a.tq + (__ffsll((unsigned long long)en[s2].m) - 1) : 0;
           en[s2].m &= en[s2].m - 1ull;
         }
+      // all eight rows' slices are loaded before any arithmetic (rows of
+      // unused combinations are valid rows; their sums are dropped below)
+      const float4* q4[2][2];
+      const float4* f4[2][2];
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          q4[s2][k] = reinterpret_cast<const float4*>(a.qf + (size_t)qs[s2][k] * a.dp);
+          f4[s2][k] = reinterpret_cast<const float4*>(frow[s2][k]);
+        }
       float acc[8];
       for (int c = 0; c * 1024 < a.dp; ++c) {
+        float sv[8][4];
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2)
+        for (int v = 0; v < 4; ++v) {
+          bool ok;
+          const int ec = slice_index(c, v, lane, a.dp, ok);
+          float4 qx[2][2], fx[2][2];
 #pragma unroll
-          for (int k = 0; k < 2; ++k) {
-            const float* qrow = a.qf + (size_t)qs[s2][k] * a.dp;
+          for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
-            for (int l = 0; l < 2; ++l) {
-              float val = 0.0f;
-              if (qv[s2][k] && inv[s2][l] != 0.0f) val = lane_partial16(qrow, frow[s2][l], c, a.dp, lane);
-              const int vi = 4 * s2 + 2 * k + l;
-              acc[vi] = c == 0 ? val : __fadd_rn(acc[vi], val);
+            for (int k = 0; k < 2; ++k) {
+              qx[s2][k] = q4[s2][k][ec];
+              fx[s2][k] = f4[s2][k][ec];
             }
-          }
+#pragma unroll
+          for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+              for (int l = 0; l < 2; ++l)
+                sv[4 * s2 + 2 * k + l][v] = ok ? slice_dot4(qx[s2][k], fx[s2][l]) : 0.0f;
+        }
+#pragma unroll
+        for (int vi = 0; vi < 8; ++vi) {
+          const float part = chunk_sum4(sv[vi][0], sv[vi][1], sv[vi][2], sv[vi][3]);
+          acc[vi] = c == 0 ? part : __fadd_rn(acc[vi], part);
+        }
       }
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+          for (int l = 0; l < 2; ++l)
+            if (!(qv[s2][k] && inv[s2][l] != 0.0f)) acc[4 * s2 + 2 * k + l] = 0.0f;
       const float dot = wave_reduce8(acc, lane);
       // lane 8v classifies value v = (entry vs, query vk, vector vl)
       int qg = 0;
