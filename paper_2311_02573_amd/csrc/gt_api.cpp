@@ -87,9 +87,18 @@ int head_of(const Index* ix) {
 // matrix cores are 16x slower than bfloat16 ones).
 int dense_last_of(const Index* ix, int fmt, int h) {
   if (fmt == GT_POOL_F32 || ix->dense_last == -1) return -1;
-  int dl = ix->dense_last >= 0 ? ix->dense_last : ix->depth - 5;
+  int dl = ix->dense_last >= 0 ? ix->dense_last : ix->depth - 6;
   dl = std::min(dl, ix->depth - 1);
   return dl > h ? dl : -1;
+}
+
+// Bucket bits of a call's sparse frontier: subtrees of level nb, at most
+// 2^7 of them and at most kMaxSlots (bucket, tile) slots, never deeper than
+// the level where the sparse frontier starts.
+int bucket_bits_of(int sparse_from, int nt) {
+  int nb = std::min(gt::kMaxBucketBits, std::max(0, sparse_from));
+  while (nb > 0 && ((int64_t)nt << nb) > gt::kMaxSlots) --nb;
+  return nb;
 }
 
 int tq_of(int fmt) { return fmt == GT_POOL_F32 ? gt::kQueriesPerTileF32 : gt::kQueriesPerTile16; }
@@ -164,7 +173,7 @@ void free_batch(Batch* b) {
   Index* ix = b->ix;
   free_query_arrays(b);
   free_frontier(b);
-  dfree(ix, &b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles);
+  dfree(ix, &b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots);
   dfree(ix, &b->tile_mask, gt::kMaxTiles);
   dfree(ix, &b->hits, (size_t)b->hit_cap);
   dfree(ix, &b->band_idx, (size_t)b->hit_cap);
@@ -207,7 +216,7 @@ gt_status batch_init(Batch* b) {
   Index* ix = b->ix;
   TRY(dalloc(ix, &b->ctr, 1));
   HIPCHK(hipHostMalloc((void**)&b->h_ctr, sizeof(gt::DevCounters), hipHostMallocDefault));
-  TRY(dalloc(ix, &b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles));
+  TRY(dalloc(ix, &b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots));
   TRY(dalloc(ix, &b->tile_mask, gt::kMaxTiles));
   b->hit_cap = int64_t(1) << 20;
   TRY(dalloc(ix, &b->hits, (size_t)b->hit_cap));
@@ -342,7 +351,8 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
       a.level = L;
       a.nt = nt;
       a.dp = ix->dp;
-      a.cap = (int)b->fr_cap;
+      a.nb = b->nb;
+      a.bcap = b->fr_cap >> b->nb;
       a.child_rows = pool_base + (size_t)level_row(L) * dp * esz;
       a.qtile = qtile;
       a.thr = b->thr;
@@ -353,7 +363,7 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
       a.out_dense = L < dl ? b->dmask[L & 1] : nullptr;
       a.out_node = b->fr_node[L & 1];
       a.out_mask = b->fr_mask[L & 1];
-      a.out_count = b->lvl_count + (size_t)L * gt::kMaxTiles;
+      a.out_count = b->lvl_count + (size_t)L * gt::kMaxSlots;
       a.stat_pairs = &b->ctr->pairs[L];
       a.bitmap = bitmap;
       a.bit_base = level_row(L);
@@ -370,14 +380,15 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
     a.dense = (l == h);
     a.nt = nt;
     a.dp = ix->dp;
-    a.cap = (int)b->fr_cap;
+    a.nb = b->nb;
+    a.bcap = b->fr_cap >> b->nb;
     a.child_rows = pool_base + (size_t)level_row(l + 1) * dp * esz;
     a.in_node = b->fr_node[l & 1];
     a.in_mask = b->fr_mask[l & 1];
-    a.in_count = b->lvl_count + (size_t)l * gt::kMaxTiles;
+    a.in_count = b->lvl_count + (size_t)l * gt::kMaxSlots;
     a.out_node = b->fr_node[(l + 1) & 1];
     a.out_mask = b->fr_mask[(l + 1) & 1];
-    a.out_count = b->lvl_count + (size_t)(l + 1) * gt::kMaxTiles;
+    a.out_count = b->lvl_count + (size_t)(l + 1) * gt::kMaxSlots;
     a.tile_mask = b->tile_mask;
     a.qtile = qtile;
     a.thr = b->thr;
@@ -402,11 +413,12 @@ gt_status enqueue_leaf(Index* ix, Batch* b) {
   la.dense = (sparse_from == D - 1) && b->dense_last < 0;
   la.nt = b->nt;
   la.dp = ix->dp;
-  la.cap = (int)b->fr_cap;
+  la.nb = b->nb;
+  la.bcap = b->fr_cap >> b->nb;
   la.tq = b->tq;
   la.in_node = b->fr_node[(D - 1) & 1];
   la.in_mask = b->fr_mask[(D - 1) & 1];
-  la.in_count = b->lvl_count + (size_t)(D - 1) * gt::kMaxTiles;
+  la.in_count = b->lvl_count + (size_t)(D - 1) * gt::kMaxSlots;
   la.tile_mask = b->tile_mask;
   la.leaves = ix->leaves;
   la.invn_f = ix->invn;
@@ -521,6 +533,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   b->n_epoch = ix->n;
   b->head = head_of(ix);
   b->dense_last = kind == 1 ? dense_last_of(ix, fmt, b->head) : -1;
+  b->nb = bucket_bits_of(b->dense_last >= 0 ? b->dense_last : b->head, nt);
   b->profile = ix->profile;
   b->nw = 0;
   if (b->profile && !b->events) {
@@ -532,7 +545,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   TRY(zero_dev(b->ctr, sizeof(gt::DevCounters), s));
   TRY(zero_dev(b->qcount, (size_t)nq_pad * 4, s));
   TRY(zero_dev(b->tile_mask, (size_t)gt::kMaxTiles * 8, s));
-  if (kind == 1) TRY(zero_dev(b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxTiles * 4, s));
+  if (kind == 1) TRY(zero_dev(b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots * 4, s));
   b->counted = ix->count_unique && kind == 1;
   if (b->counted) {
     const int64_t words = (int64_t(2) << ix->depth) / 32 + 1;
@@ -934,13 +947,13 @@ gt_status gt_get_stats(const gt_index* ix, gt_stats* out) {
   out->last_format = b->last_fmt;
   if (b->ctr && b->last_nt > 0) {
     HIPCHK(hipDeviceSynchronize());
-    std::vector<uint32_t> cnt((size_t)GT_MAX_LEVELS * gt::kMaxTiles);
+    std::vector<uint32_t> cnt((size_t)GT_MAX_LEVELS * gt::kMaxSlots);
     HIPCHK(hipMemcpy(cnt.data(), b->lvl_count, cnt.size() * 4, hipMemcpyDeviceToHost));
     gt::DevCounters c;
     HIPCHK(hipMemcpy(&c, b->ctr, sizeof(c), hipMemcpyDeviceToHost));
     for (int l = 0; l < ix->depth && l < GT_MAX_LEVELS; ++l) {
       int64_t e = 0;
-      for (int t = 0; t < b->last_nt; ++t) e += cnt[(size_t)l * gt::kMaxTiles + t];
+      for (int k = 0; k < gt::kMaxSlots; ++k) e += cnt[(size_t)l * gt::kMaxSlots + k];
       out->entries[l] = e;
       out->pairs[l] = (int64_t)c.pairs[l];
     }

@@ -16,6 +16,19 @@ constexpr int kMaxTiles = 1024;       // tiles per call (64K queries)
 constexpr int kGroupEntries = 16;     // frontier entries per wave step (32 child rows)
 constexpr int kHitStage = 192;        // per-wave LDS staging of candidate hits
 
+// Frontier buckets.  A sparse frontier entry (pool p of level l, mask) lives
+// in bucket p >> (l - nb): the subtree of node p's ancestor at level nb, so a
+// child stays in its parent's bucket.  Bucket b of tile t is the slot
+// b * nt + t; its entries are stored at slot * (fr_cap >> nb).  Buckets are
+// dealt to the chip's 8 XCDs in contiguous ranges, so each subtree's pool
+// rows are only read through one XCD's L2, where the copies needed by the
+// different query tiles meet.
+constexpr int kXcds = 8;
+constexpr int kMaxBucketBits = 7;
+constexpr int kMaxSlots = 8192;       // nt << nb
+constexpr int kMaxSlotsPerXcd = kMaxSlots / kXcds;
+constexpr int kMaxBucketsPerXcd = (1 << kMaxBucketBits) / kXcds;
+
 // Largest padded dimension each walk format supports (query tile in LDS).
 constexpr int kMaxDpBf16 = 1152, kMaxDpFp8 = 2304, kMaxDpF32 = 1152;
 
@@ -43,14 +56,16 @@ struct DevCounters {
 // Arguments of one level step of the frontier walk (parents at `level`,
 // children at `level + 1`).
 struct WalkLevelArgs {
-  int level, dense, nt, dp, cap;
+  int level, dense, nt, dp;
+  int nb;                   // bucket bits
+  int64_t bcap;             // entries per bucket slot
   const void* child_rows;   // first row of level+1 in the pool format
   const uint32_t* in_node;
   const uint64_t* in_mask;
-  const uint32_t* in_count;
+  const uint32_t* in_count;  // [slots]
   uint32_t* out_node;
   uint64_t* out_mask;
-  uint32_t* out_count;
+  uint32_t* out_count;      // [slots]
   const uint64_t* tile_mask;
   const void* qtile;        // [nt * TQ * dp] queries in the pool format
   const float* thr;         // [nt * TQ] lowered thresholds tau'
@@ -63,7 +78,9 @@ struct WalkLevelArgs {
 
 // Arguments of a dense level step (children at `level`, all 2^level pools).
 struct DenseLevelArgs {
-  int level, nt, dp, cap;
+  int level, nt, dp;
+  int nb;                   // bucket bits of the sparse output
+  int64_t bcap;
   const void* child_rows;   // first row of `level` in the pool format
   const void* qtile;        // [nt * 64 * dp] queries in the pool format
   const float* thr;
@@ -74,14 +91,16 @@ struct DenseLevelArgs {
   uint64_t* out_dense;      // [2^level x nt], or NULL: sparse output below
   uint32_t* out_node;
   uint64_t* out_mask;
-  uint32_t* out_count;      // [nt] entries (sparse) or non-empty masks (dense)
+  uint32_t* out_count;      // [slots] entries (sparse), or [nt] non-empty masks (dense)
   unsigned long long* stat_pairs;
   uint32_t* bitmap;
   int64_t bit_base;
 };
 
 struct LeafArgs {
-  int level, dense, nt, dp, cap, tq;
+  int level, dense, nt, dp, tq;
+  int nb;
+  int64_t bcap;
   const uint32_t* in_node;
   const uint64_t* in_mask;
   const uint32_t* in_count;
@@ -115,7 +134,7 @@ struct Batch {
   uint32_t* fr_node[2] = {nullptr, nullptr};
   uint64_t* fr_mask[2] = {nullptr, nullptr};
   int64_t fr_cap = 0;        // entries per tile per buffer
-  uint32_t* lvl_count = nullptr;    // [GT_MAX_LEVELS x kMaxTiles]
+  uint32_t* lvl_count = nullptr;    // [GT_MAX_LEVELS x kMaxSlots]
   uint64_t* tile_mask = nullptr;    // [kMaxTiles]
   float* qf = nullptr;       // [nq_pad x dp]
   uint16_t* qbf = nullptr;
@@ -158,7 +177,7 @@ struct Batch {
   bool pending = false;
   int kind = 0;              // 1: walk, 2: exhaustive
   hipStream_t stream = nullptr;
-  int fmt = 0, nq = 0, nq_pad = 0, nt = 0, tq = 0, head = 0, dense_last = -1;
+  int fmt = 0, nq = 0, nq_pad = 0, nt = 0, tq = 0, head = 0, dense_last = -1, nb = 0;
   int64_t n_epoch = 0;       // vectors visible to the call (ids below this)
   bool profile = false;
 

@@ -69,24 +69,25 @@ __device__ __forceinline__ void mma16<GT_POOL_F32>(const uint4& a, const uint4& 
   acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
 }
 
-// Exclusive prefix over tiles of ceil(count / per) (per = 1: entry counts),
-// computed by wave 0 into pre[0..nt]; nt <= 1024.
-__device__ __forceinline__ void tile_prefix(uint32_t* pre, int nt, int dense, int level,
-                                            const uint64_t* tile_mask, const uint32_t* in_count,
-                                            uint32_t per) {
+// Exclusive prefix pre[0..n] of the entry counts of bucket slots
+// slot0 .. slot0 + n - 1 (n <= 1024), computed by wave 0.  Dense input: every
+// pool of the bucket (1 << shift of them) for the tile's queries.
+__device__ __forceinline__ void slot_prefix(uint32_t* pre, int n, int slot0, int nt, int dense,
+                                            int shift, const uint64_t* tile_mask,
+                                            const uint32_t* counts) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    const int per_lane = (nt + 63) / 64;
-    const int t0 = lane * per_lane;
+    const int per_lane = (n + 63) / 64;
+    const int s0 = lane * per_lane;
     uint32_t loc[16];
     uint32_t sum = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int t = t0 + i;
+      const int sl = s0 + i;
       uint32_t c = 0;
-      if (i < per_lane && t < nt) {
-        c = dense ? (tile_mask[t] ? (1u << level) : 0u) : in_count[t];
-        c = (c + per - 1) / per;
+      if (i < per_lane && sl < n) {
+        const int gs = slot0 + sl;
+        c = dense ? (tile_mask[gs % nt] ? (1u << shift) : 0u) : counts[gs];
       }
       loc[i] = sum;
       sum += c;
@@ -100,22 +101,12 @@ __device__ __forceinline__ void tile_prefix(uint32_t* pre, int nt, int dense, in
     const uint32_t excl = incl - sum;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int t = t0 + i;
-      if (i < per_lane && t < nt) pre[t] = excl + loc[i];
+      const int sl = s0 + i;
+      if (i < per_lane && sl < n) pre[sl] = excl + loc[i];
     }
-    if (lane == 63) pre[nt] = incl;
+    if (lane == 63) pre[n] = incl;
   }
   __syncthreads();
-}
-
-// Index t of the tile with pre[t] <= g < pre[t + 1] (pre ascending).
-__device__ __forceinline__ int find_tile(const uint32_t* pre, int nt, uint32_t g) {
-  int lo = 0, hi = nt;  // invariant pre[lo] <= g < pre[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (pre[mid] <= g) lo = mid; else hi = mid;
-  }
-  return lo;
 }
 
 __device__ __forceinline__ uint4 ld_global16(const unsigned char* p) {
@@ -125,182 +116,287 @@ __device__ __forceinline__ uint4 ld_lds16(const unsigned char* p) {
   return *reinterpret_cast<const uint4*>(p);
 }
 
-constexpr int kPipe = 8;  // 16-byte slices per lane fetched ahead
+// 16x16 forms: one 16-byte slice per lane, 64 bytes of each of 16 rows per
+// wave instruction.  Lane l holds row (l % 16) and slice (l / 16) of a 64-byte
+// step; the A and B lanes of the same index hold the same dimensions.
+// Accumulator: register i of lane l is row 4 (l / 16) + i, column l % 16.
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+template <int FMT>
+__device__ __forceinline__ void mma16x16(const uint4& a, const uint4& b, f32x4& acc);
+template <>
+__device__ __forceinline__ void mma16x16<GT_POOL_BF16>(const uint4& a, const uint4& b, f32x4& acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void mma16x16<GT_POOL_FP8E4M3>(const uint4& a, const uint4& b,
+                                                          f32x4& acc) {
+  const long a0 = (long)(((unsigned long)a.y << 32) | a.x);
+  const long a1 = (long)(((unsigned long)a.w << 32) | a.z);
+  const long b0 = (long)(((unsigned long)b.y << 32) | b.x);
+  const long b1 = (long)(((unsigned long)b.w << 32) | b.z);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, acc, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ void mma16x16<GT_POOL_F32>(const uint4& a, const uint4& b, f32x4& acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+}
 
+// Index i with pre[i] <= g < pre[i + 1] (pre ascending, n + 1 values).
+__device__ __forceinline__ int find_slot(const uint32_t* pre, int n, uint32_t g) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= g) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+constexpr int kPipe = 8;  // 64-byte steps of a lane's two rows fetched ahead
+
+// One level step of the sparse walk.  Workgroup -> XCD x = blockIdx % 8 (the
+// hardware deals workgroups to XCDs round robin), which owns the buckets
+// [x R, x R + R).  Within an XCD the workgroups split the query tiles; when
+// there are fewer tiles than workgroups, the c workgroups of a tile each take
+// part m of every bucket.  Every workgroup goes through its buckets in
+// order, so at any moment the XCD's workgroups read the same subtrees for
+// different tiles and the repeated pool rows are found in L2.
 template <int FMT>
 __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a) {
   using F = WalkFmt<FMT>;
   constexpr int TQ = F::TQ;
-  constexpr int NB = TQ / 32;  // 32-query column blocks
+  constexpr int NQB = TQ / 16;  // 16-query column blocks
   __shared__ __attribute__((aligned(16))) unsigned char qlds[TQ * (F::MAXDP * F::ESZ + 16)];
-  __shared__ uint32_t gpre[kMaxTiles + 1];
+  static_assert(kMaxBucketsPerXcd <= 64, "one bucket per lane of wave 0");
+  __shared__ uint32_t gpre[kMaxBucketsPerXcd + 1];
+  __shared__ uint32_t glo[kMaxBucketsPerXcd], ghi[kMaxBucketsPerXcd];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
   const int rowbytes = a.dp * F::ESZ;
   const int rs = rowbytes + 16;           // LDS row stride (bank spread)
-  const int nslices = rowbytes / 32;      // 16-byte slices per lane half
-  const int r = lane & 31, half = lane >> 5;
+  const int nsteps = rowbytes / 64;
+  const int c16 = lane & 15, g4 = lane >> 4;
 
-  tile_prefix(gpre, a.nt, a.dense, a.level, a.tile_mask, a.in_count, kGroupEntries);
-  const uint32_t gtot = gpre[a.nt];
-  const uint32_t g0 = (uint32_t)(((uint64_t)gtot * blockIdx.x) / gridDim.x);
-  const uint32_t g1 = (uint32_t)(((uint64_t)gtot * (blockIdx.x + 1)) / gridDim.x);
+  const int nbk = 1 << a.nb;
+  const int xs = nbk < kXcds ? nbk : kXcds;
+  const int R = nbk / xs;
+  const int x = blockIdx.x % kXcds;
+  const int W = gridDim.x / kXcds, j = blockIdx.x / kXcds;
+  if (x >= xs) return;
+  int t0, tstep, m, c;
+  if (a.nt <= W) {
+    t0 = j % a.nt;
+    tstep = a.nt;
+    m = j / a.nt;
+    c = (W - 1 - t0) / a.nt + 1;
+  } else {
+    t0 = j;
+    tstep = W;
+    m = 0;
+    c = 1;
+  }
+  const int bshift = a.level - a.nb;  // node -> bucket
   unsigned long long pairs = 0;
-  if (g0 < g1) {
-    int t = find_tile(gpre, a.nt, g0);
-    uint32_t g = g0;
-    while (g < g1) {
-      const uint32_t tend = gpre[t + 1];
-      if (tend <= g) {
-        ++t;
-        continue;
-      }
-      const uint32_t send = tend < g1 ? tend : g1;
-      // stage the tile's queries in LDS
-      __syncthreads();
-      {
-        const unsigned char* src =
-            reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)t * TQ * rowbytes;
-        const int vec_per_row = rowbytes / 16;
-        for (int v = tid; v < TQ * vec_per_row; v += blockDim.x) {
-          const int row = v / vec_per_row, col = v - row * vec_per_row;
-          *reinterpret_cast<uint4*>(qlds + row * rs + col * 16) =
-              *reinterpret_cast<const uint4*>(src + (size_t)row * rowbytes + col * 16);
-        }
-      }
-      __syncthreads();
-      float thr[NB];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        const int qi = t * TQ + 32 * j + r;
-        float th = a.thr[qi];
-        if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
-        thr[j] = th;
-      }
-      const uint32_t count = a.dense ? (1u << a.level) : a.in_count[t];
-      const uint64_t tmask = a.tile_mask[t];
-      const size_t tbase = (size_t)t * a.cap;
 
-      // entry (pool, mask) of this lane's row in group gg of the tile
-      auto fetch = [&](uint32_t gg, uint32_t& p, uint64_t& pm) {
-        const uint32_t gl = gg - gpre[t];
-        const uint32_t e = gl * kGroupEntries + (r >> 1);
-        const bool valid = e < count;
-        if (a.dense) {
-          p = valid ? e : gl * kGroupEntries;
-          pm = valid ? tmask : 0ull;
-        } else {
-          const uint32_t ee = valid ? e : gl * kGroupEntries;
-          p = a.in_node[tbase + ee];
-          pm = valid ? a.in_mask[tbase + ee] : 0ull;
-        }
-      };
-      uint32_t np = 0;
-      uint64_t npm = 0ull;
-      if (g + wave < send) fetch(g + wave, np, npm);
-      // survivors of the previous group, written once their slots are known
-      bool pend = false;
-      uint32_t pend_child = 0;
-      uint64_t pend_mask = 0ull, pend_bal = 0ull;
-
-      for (uint32_t gg = g + wave; gg < send; gg += nwaves) {
-        const uint32_t p = np;
-        const uint64_t pm = npm;
-        const uint32_t child = 2u * p + (uint32_t)(r & 1);
-        const unsigned char* arow = reinterpret_cast<const unsigned char*>(a.child_rows) +
-                                    (size_t)child * rowbytes + 16 * half;
-        const unsigned char* brow = qlds + r * rs + 16 * half;
-        uint4 bufA[kPipe], bufB[kPipe];
+  for (int t = t0; t < a.nt; t += tstep) {
+    const uint64_t tmask = a.tile_mask[t];
+    __syncthreads();  // LDS of the previous tile no longer read
+    if (wave == 0) {  // groups of this workgroup's share of each bucket (R <= 16)
+      uint32_t ng = 0, lo = 0, hi = 0;
+      if (lane < R && tmask) {
+        const uint32_t n = a.dense ? (1u << bshift) : a.in_count[(size_t)(x * R + lane) * a.nt + t];
+        lo = (uint32_t)(((uint64_t)n * m) / c);
+        hi = (uint32_t)(((uint64_t)n * (m + 1)) / c);
+        ng = (hi - lo + kGroupEntries - 1) / kGroupEntries;
+      }
+      uint32_t incl = ng;
 #pragma unroll
-        for (int u = 0; u < kPipe; ++u)
-          if (u < nslices) bufA[u] = ld_global16(arow + 32 * u);
-        if (gg + nwaves < send) fetch(gg + nwaves, np, npm);
-        // reserve output slots for the previous group; the reply is awaited
-        // only after this group's matrix work
-        uint32_t pend_base = 0;
-        if (pend && lane == 0) pend_base = atomicAdd(&a.out_count[t], (uint32_t)__popcll(pend_bal));
-        if (a.bitmap && lane < 32 && pm) {
-          const uint64_t row = (uint64_t)a.bit_base + child;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+      }
+      if (lane < R) {
+        gpre[lane] = incl - ng;
+        glo[lane] = lo;
+        ghi[lane] = hi;
+      }
+      if (lane == 63) gpre[R] = incl;
+    }
+    __syncthreads();
+    const uint32_t gtot = gpre[R];
+    if (gtot == 0) continue;
+    {
+      const unsigned char* src =
+          reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)t * TQ * rowbytes;
+      const int vec_per_row = rowbytes / 16;
+      for (int v = tid; v < TQ * vec_per_row; v += blockDim.x) {
+        const int row = v / vec_per_row, col = v - row * vec_per_row;
+        *reinterpret_cast<uint4*>(qlds + row * rs + col * 16) =
+            *reinterpret_cast<const uint4*>(src + (size_t)row * rowbytes + col * 16);
+      }
+    }
+    __syncthreads();
+    float thr[NQB];
+#pragma unroll
+    for (int qb = 0; qb < NQB; ++qb) {
+      const int qi = t * TQ + 16 * qb + c16;
+      float th = a.thr[qi];
+      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+      thr[qb] = th;
+    }
+
+    // entries of group gg held by this lane: rows c16 (entry c16 / 2) and
+    // 16 + c16 (entry 8 + c16 / 2) of the group's 32 child rows
+    auto fetch = [&](uint32_t gg, uint32_t& p0, uint64_t& pm0, uint32_t& p1, uint64_t& pm1,
+                     uint32_t& slot) {
+      const int r = find_slot(gpre, R, gg);
+      const uint32_t e0 = glo[r] + (gg - gpre[r]) * kGroupEntries + (c16 >> 1);
+      const uint32_t e1 = e0 + 8;
+      const uint32_t hi = ghi[r];
+      const uint32_t bk = (uint32_t)(x * R + r);
+      slot = bk * (uint32_t)a.nt + (uint32_t)t;
+      if (a.dense) {
+        const uint32_t first = bk << bshift;
+        p0 = first + (e0 < hi ? e0 : e0 - (c16 >> 1));
+        p1 = first + (e1 < hi ? e1 : e0 - (c16 >> 1));
+        pm0 = e0 < hi ? tmask : 0ull;
+        pm1 = e1 < hi ? tmask : 0ull;
+      } else {
+        const size_t base = (size_t)slot * a.bcap;
+        const uint32_t ef = e0 - (c16 >> 1);  // first entry of the group, always valid
+        p0 = a.in_node[base + (e0 < hi ? e0 : ef)];
+        p1 = a.in_node[base + (e1 < hi ? e1 : ef)];
+        pm0 = e0 < hi ? a.in_mask[base + e0] : 0ull;
+        pm1 = e1 < hi ? a.in_mask[base + e1] : 0ull;
+      }
+    };
+    uint32_t np0 = 0, np1 = 0, nslot = 0;
+    uint64_t npm0 = 0ull, npm1 = 0ull;
+    if ((uint32_t)wave < gtot) fetch(wave, np0, npm0, np1, npm1, nslot);
+    bool pend = false;
+    uint32_t pend_child = 0, pend_slot = 0;
+    uint64_t pend_mask = 0ull, pend_bal = 0ull;
+
+    for (uint32_t gg = wave; gg < gtot; gg += nwaves) {
+      const uint32_t p0 = np0, p1 = np1, slot = nslot;
+      const uint64_t pm0 = npm0, pm1 = npm1;
+      const uint32_t child0 = 2u * p0 + (uint32_t)(lane & 1);
+      const uint32_t child1 = 2u * p1 + (uint32_t)(lane & 1);
+      const unsigned char* arow0 = reinterpret_cast<const unsigned char*>(a.child_rows) +
+                                   (size_t)child0 * rowbytes + 16 * g4;
+      const unsigned char* arow1 = reinterpret_cast<const unsigned char*>(a.child_rows) +
+                                   (size_t)child1 * rowbytes + 16 * g4;
+      const unsigned char* brow = qlds + c16 * rs + 16 * g4;
+      uint4 bA0[kPipe], bA1[kPipe], bB0[kPipe], bB1[kPipe];
+#pragma unroll
+      for (int u = 0; u < kPipe; ++u)
+        if (u < nsteps) {
+          bA0[u] = ld_global16(arow0 + 64 * u);
+          bA1[u] = ld_global16(arow1 + 64 * u);
+        }
+      if (gg + nwaves < gtot) fetch(gg + nwaves, np0, npm0, np1, npm1, nslot);
+      // reserve output slots for the previous group; the reply is awaited
+      // only after this group's matrix work
+      uint32_t pend_base = 0;
+      if (pend && lane == 0) pend_base = atomicAdd(&a.out_count[pend_slot], (uint32_t)__popcll(pend_bal));
+      if (a.bitmap && lane < 16) {
+        if (pm0) {
+          const uint64_t row = (uint64_t)a.bit_base + child0;
           atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
         }
-
-        f32x16 acc[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-          for (int i = 0; i < 16; ++i) acc[j][i] = 0.0f;
-
-        for (int s0 = 0; s0 < nslices; s0 += 2 * kPipe) {
-#pragma unroll
-          for (int u = 0; u < kPipe; ++u)
-            if (s0 + kPipe + u < nslices) bufB[u] = ld_global16(arow + 32 * (s0 + kPipe + u));
-#pragma unroll
-          for (int u = 0; u < kPipe; ++u)
-            if (s0 + u < nslices) {
-#pragma unroll
-              for (int j = 0; j < NB; ++j)
-                mma16<FMT>(bufA[u], ld_lds16(brow + j * 32 * rs + 32 * (s0 + u)), acc[j]);
-            }
-#pragma unroll
-          for (int u = 0; u < kPipe; ++u)
-            if (s0 + 2 * kPipe + u < nslices) bufA[u] = ld_global16(arow + 32 * (s0 + 2 * kPipe + u));
-#pragma unroll
-          for (int u = 0; u < kPipe; ++u)
-            if (s0 + kPipe + u < nslices) {
-#pragma unroll
-              for (int j = 0; j < NB; ++j)
-                mma16<FMT>(bufB[u], ld_lds16(brow + j * 32 * rs + 32 * (s0 + kPipe + u)), acc[j]);
-            }
+        if (pm1) {
+          const uint64_t row = (uint64_t)a.bit_base + child1;
+          atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
         }
-
-        if (pend) {
-          pend_base = __shfl(pend_base, 0, 64);
-          if (lane < 32 && pend_mask) {
-            const uint32_t pos = pend_base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
-            a.out_node[tbase + pos] = pend_child;
-            a.out_mask[tbase + pos] = pend_mask;
-          }
-        }
-
-        // 32x32 accumulator layout: register i of lane l holds
-        // row 8*(i/4) + 4*(l/32) + (i%4), column l%32.
-        uint64_t mine = 0ull;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const uint64_t b0 = __ballot(acc[0][i] >= thr[0]);
-          uint64_t lo, hi;
-          if (NB == 2) {
-            const uint64_t b1 = __ballot(acc[NB - 1][i] >= thr[NB - 1]);
-            lo = (b0 & 0xffffffffull) | (b1 << 32);
-            hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
-          } else {
-            lo = b0 & 0xffffffffull;
-            hi = b0 >> 32;
-          }
-          const int row0 = 8 * (i >> 2) + (i & 3);
-          if (lane == row0) mine = lo;
-          if (lane == row0 + 4) mine = hi;
-        }
-        mine &= pm;  // lane r < 32 holds child row r, whose parent mask is pm
-        if (lane < 32) pairs += (unsigned long long)__popcll(pm);
-        pend_bal = __ballot(lane < 32 && mine != 0ull);
-        pend = pend_bal != 0ull;
-        pend_child = child;
-        pend_mask = lane < 32 ? mine : 0ull;
       }
+
+      f32x4 acc[2][NQB];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int qb = 0; qb < NQB; ++qb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[rb][qb][i] = 0.0f;
+
+      auto step = [&](const uint4& x0, const uint4& x1, int s) {
+#pragma unroll
+        for (int qb = 0; qb < NQB; ++qb) {
+          const uint4 bq = ld_lds16(brow + qb * 16 * rs + 64 * s);
+          mma16x16<FMT>(x0, bq, acc[0][qb]);
+          mma16x16<FMT>(x1, bq, acc[1][qb]);
+        }
+      };
+      for (int s0 = 0; s0 < nsteps; s0 += 2 * kPipe) {
+#pragma unroll
+        for (int u = 0; u < kPipe; ++u)
+          if (s0 + kPipe + u < nsteps) {
+            bB0[u] = ld_global16(arow0 + 64 * (s0 + kPipe + u));
+            bB1[u] = ld_global16(arow1 + 64 * (s0 + kPipe + u));
+          }
+#pragma unroll
+        for (int u = 0; u < kPipe; ++u)
+          if (s0 + u < nsteps) step(bA0[u], bA1[u], s0 + u);
+#pragma unroll
+        for (int u = 0; u < kPipe; ++u)
+          if (s0 + 2 * kPipe + u < nsteps) {
+            bA0[u] = ld_global16(arow0 + 64 * (s0 + 2 * kPipe + u));
+            bA1[u] = ld_global16(arow1 + 64 * (s0 + 2 * kPipe + u));
+          }
+#pragma unroll
+        for (int u = 0; u < kPipe; ++u)
+          if (s0 + kPipe + u < nsteps) step(bB0[u], bB1[u], s0 + kPipe + u);
+      }
+
       if (pend) {
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&a.out_count[t], (uint32_t)__popcll(pend_bal));
-        base = __shfl(base, 0, 64);
+        pend_base = __shfl(pend_base, 0, 64);
         if (lane < 32 && pend_mask) {
-          const uint32_t pos = base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
-          a.out_node[tbase + pos] = pend_child;
-          a.out_mask[tbase + pos] = pend_mask;
+          const uint32_t pos = pend_base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
+          const size_t o = (size_t)pend_slot * a.bcap + pos;
+          a.out_node[o] = pend_child;
+          a.out_mask[o] = pend_mask;
         }
       }
-      g = send;
-      ++t;
+
+      // Child row r (lane r < 32): block r / 16, register r % 4, lane group
+      // (r % 16) / 4; column block qb supplies query bits 16 qb .. 16 qb + 15.
+      const int gsel = 16 * ((lane & 15) >> 2);
+      uint64_t mine = 0ull;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          uint64_t part = 0ull;
+#pragma unroll
+          for (int qb = 0; qb < NQB; ++qb) {
+            const uint64_t bal = __ballot(acc[rb][qb][i] >= thr[qb]);
+            part |= ((bal >> gsel) & 0xffffull) << (16 * qb);
+          }
+          if ((lane >> 4) == rb && (lane & 3) == i) mine = part;
+        }
+      const uint64_t pm_own = lane < 16 ? pm0 : pm1;
+      mine = lane < 32 ? (mine & pm_own) : 0ull;
+      if (lane < 32) pairs += (unsigned long long)__popcll(pm_own);
+      pend_bal = __ballot(mine != 0ull);
+      pend = pend_bal != 0ull;
+      pend_child = lane < 16 ? child0 : child1;
+      pend_mask = mine;
+      pend_slot = slot;
+    }
+    if (pend) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(&a.out_count[pend_slot], (uint32_t)__popcll(pend_bal));
+      base = __shfl(base, 0, 64);
+      if (lane < 32 && pend_mask) {
+        const uint32_t pos = base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
+        const size_t o = (size_t)pend_slot * a.bcap + pos;
+        a.out_node[o] = pend_child;
+        a.out_mask[o] = pend_mask;
+      }
     }
   }
   if (a.stat_pairs) {
@@ -433,7 +529,7 @@ __global__ __launch_bounds__(256) void k_dense_level(DenseLevelArgs a) {
     thr[j] = th;
   }
   unsigned long long pairs = 0;
-  const size_t tbase = (size_t)t * a.cap;
+  const int bshift = a.level - a.nb;  // node -> bucket of the sparse output
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int64_t row = row0 + wr * 64 + i * 32 + r;
@@ -458,15 +554,24 @@ __global__ __launch_bounds__(256) void k_dense_level(DenseLevelArgs a) {
     if (a.out_dense) {
       if (rv) a.out_dense[row * a.nt + t] = mine;
       if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
-    } else if (eb) {
+    } else if (eb && bshift >= 5) {
+      // the 32 rows (aligned) share one bucket: one reservation per wave
+      const uint32_t slot = (uint32_t)((row0 + wr * 64 + i * 32) >> bshift) * (uint32_t)a.nt + t;
       uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
+      if (lane == 0) base = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(eb));
       base = __shfl(base, 0, 64);
       if (rv && mine) {
         const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
-        a.out_node[tbase + pos] = (uint32_t)row;
-        a.out_mask[tbase + pos] = mine;
+        const size_t o = (size_t)slot * a.bcap + pos;
+        a.out_node[o] = (uint32_t)row;
+        a.out_mask[o] = mine;
       }
+    } else if (eb && rv && mine) {
+      const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
+      const uint32_t pos = atomicAdd(&a.out_count[slot], 1u);
+      const size_t o = (size_t)slot * a.bcap + pos;
+      a.out_node[o] = (uint32_t)row;
+      a.out_mask[o] = mine;
     }
   }
   if (a.stat_pairs) {
@@ -486,44 +591,58 @@ struct LeafEntry {
   uint64_t m;
 };
 
-__device__ __forceinline__ LeafEntry leaf_entry(const LeafArgs& a, const uint32_t* epre,
-                                                uint32_t idx, uint32_t etot) {
+__device__ __forceinline__ LeafEntry leaf_entry(const LeafArgs& a, const uint32_t* epre, int nsl,
+                                                int slot0, uint32_t idx, uint32_t etot) {
   LeafEntry x;
   x.t = 0;
   x.p = 0;
   x.m = 0ull;
   if (idx >= etot) return x;
-  x.t = find_tile(epre, a.nt, idx);
-  const uint32_t e = idx - epre[x.t];
+  const int sl = find_slot(epre, nsl, idx);
+  const int gs = slot0 + sl;
+  const uint32_t e = idx - epre[sl];
+  x.t = gs % a.nt;
   if (a.dense) {
-    x.p = e;
+    x.p = ((uint32_t)(gs / a.nt) << (a.level - a.nb)) + e;
     x.m = a.tile_mask[x.t];
   } else {
-    x.p = a.in_node[(size_t)x.t * a.cap + e];
-    x.m = a.in_mask[(size_t)x.t * a.cap + e];
+    x.p = a.in_node[(size_t)gs * a.bcap + e];
+    x.m = a.in_mask[(size_t)gs * a.bcap + e];
   }
   return x;
 }
 
+// Workgroup -> XCD x = blockIdx % 8, which owns the bucket slots of buckets
+// [x R, x R + R) (slots are bucket-major, so they are contiguous); the XCD's
+// workgroups sweep its entries in slot order, so the tiles' copies of a leaf
+// pair are tested close together in time and share the XCD's L2.
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
-  __shared__ uint32_t epre[kMaxTiles + 1];
+  __shared__ uint32_t epre[kMaxSlotsPerXcd + 1];
   __shared__ Hit hstage[4][kHitStage];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  tile_prefix(epre, a.nt, a.dense, a.level, a.tile_mask, a.in_count, 1);
-  const uint32_t etot = epre[a.nt];
+  const int nbk = 1 << a.nb;
+  const int xs = nbk < kXcds ? nbk : kXcds;
+  const int x = blockIdx.x % kXcds;
+  if (x >= xs) return;
+  const int nsl = (nbk / xs) * a.nt;
+  const int slot0 = x * nsl;
+  slot_prefix(epre, nsl, slot0, a.nt, a.dense, a.level - a.nb, a.tile_mask, a.in_count);
+  const uint32_t etot = epre[nsl];
   const uint32_t nw = blockDim.x >> 6;
-  const uint32_t stride = 2u * gridDim.x * nw;
+  const uint32_t wgs = gridDim.x / kXcds;
+  const uint32_t stride = 2u * wgs * nw;
   Hit* buf = hstage[w];
   int cnt = 0;
   unsigned long long npairs = 0;
   const int v = lane >> 3;              // value owned after the reduction
   const int vs = v >> 2, vk = (v >> 1) & 1, vl = v & 1;
-  uint32_t idx = 2u * (blockIdx.x * nw + w);
-  LeafEntry nx0 = leaf_entry(a, epre, idx, etot), nx1 = leaf_entry(a, epre, idx + 1, etot);
+  uint32_t idx = 2u * ((blockIdx.x / kXcds) * nw + w);
+  LeafEntry nx0 = leaf_entry(a, epre, nsl, slot0, idx, etot);
+  LeafEntry nx1 = leaf_entry(a, epre, nsl, slot0, idx + 1, etot);
   for (; idx < etot; idx += stride) {
     LeafEntry en[2] = {nx0, nx1};
-    nx0 = leaf_entry(a, epre, idx + stride, etot);
-    nx1 = leaf_entry(a, epre, idx + stride + 1, etot);
+    nx0 = leaf_entry(a, epre, nsl, slot0, idx + stride, etot);
+    nx1 = leaf_entry(a, epre, nsl, slot0, idx + stride + 1, etot);
     float inv[2][2];
     const float* frow[2][2];
 #pragma unroll
@@ -844,6 +963,11 @@ int grid_for(int64_t work, int block) {
 }  // namespace
 
 hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s) {
+  // whole workgroups per XCD; bucket and slot limits of the kernels
+  grid = kXcds * ((grid + kXcds - 1) / kXcds);
+  if (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
+      a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles)
+    return hipErrorInvalidValue;
   switch (fmt) {
     case GT_POOL_BF16:
       hipLaunchKernelGGL(k_walk_level<GT_POOL_BF16>, dim3(grid), dim3(kWalkThreads), 0, s, a);
@@ -861,6 +985,9 @@ hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStrea
 }
 
 hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {
+  if (!a.out_dense &&
+      (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots || a.level < a.nb))
+    return hipErrorInvalidValue;
   const int64_t rows = int64_t(1) << a.level;
   const int64_t total = ((rows + kDR - 1) / kDR) * ((a.nt + 1) / 2);
   const int64_t grid = 8 * ((total + 7) / 8);
@@ -878,6 +1005,10 @@ hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s) {
+  grid = kXcds * ((grid + kXcds - 1) / kXcds);
+  if (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
+      a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_leaf, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
