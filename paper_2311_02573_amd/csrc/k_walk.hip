@@ -165,7 +165,7 @@ constexpr int kPipe = 8;  // 64-byte steps of a lane's two rows fetched ahead
 // part m of every bucket.  Every workgroup goes through its buckets in
 // order, so at any moment the XCD's workgroups read the same subtrees for
 // different tiles and the repeated pool rows are found in L2.
-template <int FMT>
+template <int FMT, int NSTEPS>
 __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a) {
   using F = WalkFmt<FMT>;
   constexpr int TQ = F::TQ;
@@ -174,12 +174,18 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
   static_assert(kMaxBucketsPerXcd <= 64, "one bucket per lane of wave 0");
   __shared__ uint32_t gpre[kMaxBucketsPerXcd + 1];
   __shared__ uint32_t glo[kMaxBucketsPerXcd], ghi[kMaxBucketsPerXcd];
+  // Thresholds of the tile.  Read from LDS in the loop: a value loaded from
+  // global memory before the loop would make the compiler wait for every
+  // load in flight at its first use in each iteration.
+  __shared__ float thr_lds[TQ];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
   const int rowbytes = a.dp * F::ESZ;
   const int rs = rowbytes + 16;           // LDS row stride (bank spread)
-  const int nsteps = rowbytes / 64;
+  // 64-byte steps per row; a compile-time count (the common padded widths)
+  // unrolls the stage loop completely
+  const int nsteps = NSTEPS > 0 ? NSTEPS : rowbytes / 64;
   const int c16 = lane & 15, g4 = lane >> 4;
 
   const int nbk = 1 << a.nb;
@@ -233,22 +239,36 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
     {
       const unsigned char* src =
           reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)t * TQ * rowbytes;
+      // 8 loads in flight per thread before their LDS stores (a plain
+      // load-store loop would pay one memory latency per 16 bytes)
       const int vec_per_row = rowbytes / 16;
-      for (int v = tid; v < TQ * vec_per_row; v += blockDim.x) {
-        const int row = v / vec_per_row, col = v - row * vec_per_row;
-        *reinterpret_cast<uint4*>(qlds + row * rs + col * 16) =
-            *reinterpret_cast<const uint4*>(src + (size_t)row * rowbytes + col * 16);
+      const int nvec = TQ * vec_per_row;
+      for (int v0 = 0; v0 < nvec; v0 += 8 * kWalkThreads) {
+        uint4 buf[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int v = v0 + k * kWalkThreads + tid;
+          const int vv = v < nvec ? v : nvec - 1;
+          const int row = vv / vec_per_row, col = vv - row * vec_per_row;
+          buf[k] = *reinterpret_cast<const uint4*>(src + (size_t)row * rowbytes + col * 16);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int v = v0 + k * kWalkThreads + tid;
+          if (v < nvec) {
+            const int row = v / vec_per_row, col = v - row * vec_per_row;
+            *reinterpret_cast<uint4*>(qlds + row * rs + col * 16) = buf[k];
+          }
+        }
       }
     }
-    __syncthreads();
-    float thr[NQB];
-#pragma unroll
-    for (int qb = 0; qb < NQB; ++qb) {
-      const int qi = t * TQ + 16 * qb + c16;
+    if (tid < TQ) {
+      const int qi = t * TQ + tid;
       float th = a.thr[qi];
       if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
-      thr[qb] = th;
+      thr_lds[tid] = th;
     }
+    __syncthreads();
 
     // entries of group gg held by this lane: rows c16 (entry c16 / 2) and
     // 16 + c16 (entry 8 + c16 / 2) of the group's 32 child rows
@@ -260,24 +280,47 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
       const uint32_t hi = ghi[r];
       const uint32_t bk = (uint32_t)(x * R + r);
       slot = bk * (uint32_t)a.nt + (uint32_t)t;
-      if (a.dense) {
-        const uint32_t first = bk << bshift;
-        p0 = first + (e0 < hi ? e0 : e0 - (c16 >> 1));
-        p1 = first + (e1 < hi ? e1 : e0 - (c16 >> 1));
-        pm0 = e0 < hi ? tmask : 0ull;
-        pm1 = e1 < hi ? tmask : 0ull;
-      } else {
-        const size_t base = (size_t)slot * a.bcap;
-        const uint32_t ef = e0 - (c16 >> 1);  // first entry of the group, always valid
-        p0 = a.in_node[base + (e0 < hi ? e0 : ef)];
-        p1 = a.in_node[base + (e1 < hi ? e1 : ef)];
-        pm0 = e0 < hi ? a.in_mask[base + e0] : 0ull;
-        pm1 = e1 < hi ? a.in_mask[base + e1] : 0ull;
-      }
+      // Loads are issued in both input modes and for padding lanes (at the
+      // group's first entry, always valid) so that no branch separates them
+      // from their use; dense input (every pool of the bucket) ignores them.
+      const size_t base = (size_t)slot * a.bcap;
+      const uint32_t ef = e0 - (c16 >> 1);
+      const uint32_t i0 = e0 < hi ? e0 : ef, i1 = e1 < hi ? e1 : ef;
+      const uint32_t ld0 = a.in_node[base + i0], ld1 = a.in_node[base + i1];
+      const uint64_t lm0 = a.in_mask[base + i0], lm1 = a.in_mask[base + i1];
+      const uint32_t first = bk << bshift;
+      p0 = a.dense ? first + i0 : ld0;
+      p1 = a.dense ? first + i1 : ld1;
+      pm0 = e0 < hi ? (a.dense ? tmask : lm0) : 0ull;
+      pm1 = e1 < hi ? (a.dense ? tmask : lm1) : 0ull;
     };
+    // Rows of a group's child pools for this lane (row c16 and 16 + c16).
+    auto rows_of = [&](uint32_t p0, uint32_t p1, const unsigned char*& r0,
+                       const unsigned char*& r1) {
+      const unsigned char* base = reinterpret_cast<const unsigned char*>(a.child_rows) + 16 * g4;
+      r0 = base + (size_t)(2u * p0 + (uint32_t)(lane & 1)) * rowbytes;
+      r1 = base + (size_t)(2u * p1 + (uint32_t)(lane & 1)) * rowbytes;
+    };
+    // The steps of consecutive groups form one pipeline: while a stage is
+    // multiplied, the next one (possibly the first stage of the wave's next
+    // group) is in flight.  Loads are unconditional (steps past a row re-read
+    // its last step) so the number in flight is static and the compiler waits
+    // only for the stage it is about to use.
+    const int slast = nsteps - 1;
+    uint4 bA0[kPipe], bA1[kPipe], bB0[kPipe], bB1[kPipe];
     uint32_t np0 = 0, np1 = 0, nslot = 0;
     uint64_t npm0 = 0ull, npm1 = 0ull;
-    if ((uint32_t)wave < gtot) fetch(wave, np0, npm0, np1, npm1, nslot);
+    if ((uint32_t)wave < gtot) {
+      fetch(wave, np0, npm0, np1, npm1, nslot);
+      const unsigned char *r0, *r1;
+      rows_of(np0, np1, r0, r1);
+#pragma unroll
+      for (int u = 0; u < kPipe; ++u) {
+        const int st = u < slast ? u : slast;
+        bA0[u] = ld_global16(r0 + 64 * st);
+        bA1[u] = ld_global16(r1 + 64 * st);
+      }
+    }
     bool pend = false;
     uint32_t pend_child = 0, pend_slot = 0;
     uint64_t pend_mask = 0ull, pend_bal = 0ull;
@@ -287,23 +330,14 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
       const uint64_t pm0 = npm0, pm1 = npm1;
       const uint32_t child0 = 2u * p0 + (uint32_t)(lane & 1);
       const uint32_t child1 = 2u * p1 + (uint32_t)(lane & 1);
-      const unsigned char* arow0 = reinterpret_cast<const unsigned char*>(a.child_rows) +
-                                   (size_t)child0 * rowbytes + 16 * g4;
-      const unsigned char* arow1 = reinterpret_cast<const unsigned char*>(a.child_rows) +
-                                   (size_t)child1 * rowbytes + 16 * g4;
+      const unsigned char *arow0, *arow1;
+      rows_of(p0, p1, arow0, arow1);
       const unsigned char* brow = qlds + c16 * rs + 16 * g4;
-      uint4 bA0[kPipe], bA1[kPipe], bB0[kPipe], bB1[kPipe];
-#pragma unroll
-      for (int u = 0; u < kPipe; ++u)
-        if (u < nsteps) {
-          bA0[u] = ld_global16(arow0 + 64 * u);
-          bA1[u] = ld_global16(arow1 + 64 * u);
-        }
-      if (gg + nwaves < gtot) fetch(gg + nwaves, np0, npm0, np1, npm1, nslot);
+      const bool has_next = gg + nwaves < gtot;
+      // the next group's entries (this group's again when there is none)
+      fetch(has_next ? gg + nwaves : gg, np0, npm0, np1, npm1, nslot);
       // reserve output slots for the previous group; the reply is awaited
       // only after this group's matrix work
-      uint32_t pend_base = 0;
-      if (pend && lane == 0) pend_base = atomicAdd(&a.out_count[pend_slot], (uint32_t)__popcll(pend_bal));
       if (a.bitmap && lane < 16) {
         if (pm0) {
           const uint64_t row = (uint64_t)a.bit_base + child0;
@@ -314,6 +348,8 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
           atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
         }
       }
+      uint32_t pend_base = 0;
+      if (pend && lane == 0) pend_base = atomicAdd(&a.out_count[pend_slot], (uint32_t)__popcll(pend_bal));
 
       f32x4 acc[2][NQB];
 #pragma unroll
@@ -331,35 +367,50 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
           mma16x16<FMT>(x1, bq, acc[1][qb]);
         }
       };
+#pragma unroll
       for (int s0 = 0; s0 < nsteps; s0 += 2 * kPipe) {
 #pragma unroll
-        for (int u = 0; u < kPipe; ++u)
-          if (s0 + kPipe + u < nsteps) {
-            bB0[u] = ld_global16(arow0 + 64 * (s0 + kPipe + u));
-            bB1[u] = ld_global16(arow1 + 64 * (s0 + kPipe + u));
-          }
+        for (int u = 0; u < kPipe; ++u) {
+          const int st = s0 + kPipe + u < slast ? s0 + kPipe + u : slast;
+          bB0[u] = ld_global16(arow0 + 64 * st);
+          bB1[u] = ld_global16(arow1 + 64 * st);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < kPipe; ++u)
           if (s0 + u < nsteps) step(bA0[u], bA1[u], s0 + u);
-#pragma unroll
-        for (int u = 0; u < kPipe; ++u)
-          if (s0 + 2 * kPipe + u < nsteps) {
-            bA0[u] = ld_global16(arow0 + 64 * (s0 + 2 * kPipe + u));
-            bA1[u] = ld_global16(arow1 + 64 * (s0 + 2 * kPipe + u));
+        __builtin_amdgcn_sched_barrier(0);
+        {
+          // next stage of this group, or the first stage of the next group
+          const bool same = s0 + 2 * kPipe < nsteps;
+          if (!same && pend) {
+            // Survivors of the previous group go out here, before the next
+            // group's loads are issued: waiting for the slot reservation then
+            // only waits for loads that the next stage needs anyway.
+            pend_base = __shfl(pend_base, 0, 64);
+            if (lane < 32 && pend_mask) {
+              const uint32_t pos = pend_base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
+              const size_t o = (size_t)pend_slot * a.bcap + pos;
+              a.out_node[o] = pend_child;
+              a.out_mask[o] = pend_mask;
+            }
+            pend = false;
           }
+          const unsigned char *r0 = arow0, *r1 = arow1;
+          if (!same) rows_of(np0, np1, r0, r1);
+          const int sf = same ? s0 + 2 * kPipe : 0;
+#pragma unroll
+          for (int u = 0; u < kPipe; ++u) {
+            const int st = sf + u < slast ? sf + u : slast;
+            bA0[u] = ld_global16(r0 + 64 * st);
+            bA1[u] = ld_global16(r1 + 64 * st);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < kPipe; ++u)
           if (s0 + kPipe + u < nsteps) step(bB0[u], bB1[u], s0 + kPipe + u);
-      }
-
-      if (pend) {
-        pend_base = __shfl(pend_base, 0, 64);
-        if (lane < 32 && pend_mask) {
-          const uint32_t pos = pend_base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
-          const size_t o = (size_t)pend_slot * a.bcap + pos;
-          a.out_node[o] = pend_child;
-          a.out_mask[o] = pend_mask;
-        }
+        __builtin_amdgcn_sched_barrier(0);
       }
 
       // Child row r (lane r < 32): block r / 16, register r % 4, lane group
@@ -373,7 +424,7 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
           uint64_t part = 0ull;
 #pragma unroll
           for (int qb = 0; qb < NQB; ++qb) {
-            const uint64_t bal = __ballot(acc[rb][qb][i] >= thr[qb]);
+            const uint64_t bal = __ballot(acc[rb][qb][i] >= thr_lds[16 * qb + c16]);
             part |= ((bal >> gsel) & 0xffffull) << (16 * qb);
           }
           if ((lane >> 4) == rb && (lane & 3) == i) mine = part;
@@ -962,26 +1013,29 @@ int grid_for(int64_t work, int block) {
 
 }  // namespace
 
+template <int FMT, int NFAST>
+hipError_t launch_walk_fmt(const WalkLevelArgs& a, int grid, hipStream_t s) {
+  const int nsteps = a.dp * WalkFmt<FMT>::ESZ / 64;
+  if (nsteps == NFAST)
+    hipLaunchKernelGGL((k_walk_level<FMT, NFAST>), dim3(grid), dim3(kWalkThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_walk_level<FMT, 0>), dim3(grid), dim3(kWalkThreads), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s) {
   // whole workgroups per XCD; bucket and slot limits of the kernels
   grid = kXcds * ((grid + kXcds - 1) / kXcds);
   if (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
       a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles)
     return hipErrorInvalidValue;
+  // fast paths: padded width 1024
   switch (fmt) {
-    case GT_POOL_BF16:
-      hipLaunchKernelGGL(k_walk_level<GT_POOL_BF16>, dim3(grid), dim3(kWalkThreads), 0, s, a);
-      break;
-    case GT_POOL_FP8E4M3:
-      hipLaunchKernelGGL(k_walk_level<GT_POOL_FP8E4M3>, dim3(grid), dim3(kWalkThreads), 0, s, a);
-      break;
-    case GT_POOL_F32:
-      hipLaunchKernelGGL(k_walk_level<GT_POOL_F32>, dim3(grid), dim3(kWalkThreads), 0, s, a);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case GT_POOL_BF16: return launch_walk_fmt<GT_POOL_BF16, 32>(a, grid, s);
+    case GT_POOL_FP8E4M3: return launch_walk_fmt<GT_POOL_FP8E4M3, 16>(a, grid, s);
+    case GT_POOL_F32: return launch_walk_fmt<GT_POOL_F32, 64>(a, grid, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {
