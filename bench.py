@@ -25,6 +25,41 @@ METRIC = "queries/sec at N=1M,d=1000,100% recall vs exhaustive GEMM; p50/p99 lat
 HBM_PEAK_GBS = 8000.0
 
 
+# Counter-measured HBM traffic per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE,
+# scaled by a 1 GiB copy), kept in a profile summary together with a hash of
+# the kernel sources it was taken on; reported only while the sources match.
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_walk_bf16_n1m_d1000_b1024_rho0.9.md")
+KERNEL_SOURCES = ["k_walk.hip", "gt_numerics.h", "gt_device.h", "gt_internal.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_02573_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic():
+    """{kernel: bytes per launch} from the counter summary, or {} if it is
+    missing or was taken on other kernel sources."""
+    try:
+        text = open(COUNTER_SUMMARY).read()
+    except OSError:
+        return {}
+    vals, src = {}, None
+    for line in text.splitlines():
+        line = line.strip()
+        if line.startswith("traffic_source_sha256:"):
+            src = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch "):
+            k, v = line[len("traffic_bytes_per_launch "):].rsplit(":", 1)
+            vals[k.strip()] = float(v)
+    return vals if src == kernel_source_hash() else {}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -51,6 +86,8 @@ def main():
                     help="end with a 1 GiB device-to-device copy (reference for memory counters)")
     ap.add_argument("--sweep-dense", action="store_true",
                     help="also time the walk for several dense/sparse split levels")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of each loaded serving run (0: no serving leg)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU (this build has no multi-GPU path); use --gpus 1",
@@ -152,7 +189,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": None,
+        "traffic": stored_traffic().get(dom),
         "algorithmic_bytes_per_launch": b / max(1, nl),
         "launches_per_batch": nl,
         "avg_launch_ms": ms / max(1, nl),
@@ -255,8 +292,12 @@ def main():
     }
     if sweep is not None:
         out["dense_last_sweep_ms"] = sweep
-    print(json.dumps(out), flush=True)
     idx.close()
+    del idx, q
+    torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
+        out["serving"] = serving_leg(args.serve_seconds, torch, gt, synth, dev)
+    print(json.dumps(out), flush=True)
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -264,6 +305,75 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copy reference: 1 GiB read + 1 GiB written")
+
+
+def serving_leg(seconds, torch, gt, synth, dev):
+    """Continuous batching under load: N0 = 2^22 float16 rows, d = 512, requests
+    of U{1..512} queries at rho = 0.9 arriving as a Poisson process, 10,000
+    inserted rows per second in groups of 100 every 10 ms.  The saturated rate
+    is measured first (every request waiting at t = 0); loaded runs offer 50%
+    and 80% of it.  Latency = completion - arrival, host clock."""
+    from paper_2311_02573_amd import serve
+
+    t0 = time.time()
+    w = synth.workload3()
+    feats = w.feats.to(dev)
+    qpool = torch.from_numpy(w.queries).to(dev)
+    idx = gt.GTIndex(feats, capacity=w.capacity, pools=("f32", "bf16"))
+    torch.cuda.synchronize()
+    del feats
+    log(f"serving index: N0={w.n} d={w.d} f16, capacity {w.capacity}, built in "
+        f"{time.time() - t0:.1f}s (incl. generation)")
+    # one synchronous 1024-query call, kernel groups timed with HIP events
+    idx.query(qpool[:1024], float(w.rho[0]))
+    idx.set_option("profile", 1)
+    r1 = idx.query(qpool[:1024], float(w.rho[0]))
+    st = idx.stats()
+    idx.set_option("profile", 0)
+    call = {k: round(st[k], 3) for k in ("ms_total", "ms_dense", "ms_frontier", "ms_leaf",
+                                         "ms_recheck", "ms_compact")}
+    call["results"] = r1.total
+    log(f"serving index, one 1024-query call: {call}")
+    backend = serve.GpuBackend(idx)
+    nqp = qpool.shape[0]
+    make_q = lambda i, k: qpool[(i * 613) % (nqp - 512):(i * 613) % (nqp - 512) + k]
+    rho_of = lambda i, k: np.full(k, w.rho[0])
+    n_ins = [0]
+
+    def ins_rows(k):
+        rows = synth.insert_rows(3, 100, w.d, w.temp, offset=k)
+        n_ins[0] += 100
+        return torch.from_numpy(rows).to(dev, torch.float16)
+
+    def server():
+        return serve.Server(backend, n_workspaces=4, max_queries=1024, pool="bf16")
+
+    # saturated: a backlog of requests, all present at t = 0
+    sched = [(0.0, k) for _, k in synth.poisson_arrivals(3, 400.0, 1.0, 512, seed_offset=1)]
+    srv = server()
+    reqs, wall, _ = serve.run_poisson(srv, sched, make_q, rho_of, 0.0)
+    sat_qps = sum(r.nq for r in reqs) / wall
+    log(f"serving: saturated {sat_qps:.0f} queries/s ({len(reqs)} requests in {wall:.2f}s)")
+    out = {"workload": f"N0={w.n} d={w.d} float16, capacity {w.capacity}, bf16 pools, "
+                       "requests U{1..512} queries at rho=0.9, Poisson arrivals, "
+                       "inserts 10000/s in groups of 100",
+           "saturated_qps": round(sat_qps, 1), "workspaces": 4, "max_queries_per_call": 1024,
+           "call_1024_queries": call}
+    for load in (0.5, 0.8):
+        rate = load * sat_qps / 256.5          # requests/s (mean request 256.5 queries)
+        sched = synth.poisson_arrivals(3, rate, seconds, 512, seed_offset=int(load * 10))
+        n_ins[0] = 0
+        srv = server()
+        reqs, wall, k_ins = serve.run_poisson(srv, sched, make_q, rho_of, seconds,
+                                              insert_every_s=0.01, insert_rows=ins_rows)
+        lat = serve.latency_summary(reqs)
+        nq_tot = sum(r.nq for r in reqs)
+        out[f"load_{int(load * 100)}"] = dict(
+            offered_qps=round(load * sat_qps, 1), achieved_qps=round(nq_tot / wall, 1),
+            inserted_rows=n_ins[0], inserts_per_s=round(n_ins[0] / wall, 1), **lat)
+        log(f"serving at {load:.0%}: {lat}, {n_ins[0]} rows inserted")
+    idx.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -158,8 +158,12 @@ gt_status gt_exhaustive(gt_index* index, const float* q_dev, int32_t nq, const d
  *   gt_batch_poll    *done_out = 1 once the device has reached the result
  *                    count of the call in flight (non-blocking).
  *   gt_batch_finish  completes the call as gt_query_batch does (waits,
- *                    writes offsets, ids, sims; same errors and overflow
- *                    contract) and frees the workspace for the next call.
+ *                    writes offsets, ids, sims; same errors) and frees the
+ *                    workspace for the next call.  On RESULT_OVERFLOW the
+ *                    call stays in flight with its results kept: *total_out
+ *                    and offsets are written, and gt_batch_finish may be
+ *                    called again with max_results >= *total_out (nothing is
+ *                    recomputed).
  * Inserts may run between submit and finish: the call keeps its epoch, and
  * float32 / bfloat16 pools only grow, which keeps its pruning sound; with
  * float8 pools built, gt_insert first waits for the device.  One host thread

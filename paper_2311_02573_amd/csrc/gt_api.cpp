@@ -87,7 +87,10 @@ int head_of(const Index* ix) {
 // matrix cores are 16x slower than bfloat16 ones).
 int dense_last_of(const Index* ix, int fmt, int h) {
   if (fmt == GT_POOL_F32 || ix->dense_last == -1) return -1;
-  int dl = ix->dense_last >= 0 ? ix->dense_last : ix->depth - 6;
+  // automatic: the level whose pools hold about 64 of the populated rows
+  int lg = 0;
+  while ((int64_t(1) << lg) < ix->n) ++lg;
+  int dl = ix->dense_last >= 0 ? ix->dense_last : lg - 6;
   dl = std::min(dl, ix->depth - 1);
   return dl > h ? dl : -1;
 }
@@ -349,6 +352,10 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
     for (int L = h + 1; L <= dl; ++L) {
       gt::DenseLevelArgs a{};
       a.level = L;
+      // pools beyond the last one holding a row below the epoch are all zero
+      // and can hold no result: they are not tested
+      a.rows = std::max<int64_t>(1, std::min<int64_t>(int64_t(1) << L,
+                                                     (b->n_epoch + (int64_t(1) << (D - L)) - 1) >> (D - L)));
       a.nt = nt;
       a.dp = ix->dp;
       a.nb = b->nb;
@@ -586,8 +593,10 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
 }
 
 // Waits for the counters, handles buffer overflow, writes offsets, ids and sims.
+// keep_on_overflow: after GT_ERR_RESULT_OVERFLOW the call stays in flight, so
+// finish can be called again with larger buffers without recomputing it.
 gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int64_t* ids,
-                 float* sims, int64_t* total_out) {
+                 float* sims, int64_t* total_out, bool keep_on_overflow) {
   if (!b->pending) return fail(GT_ERR_INVALID_ARG, "no call in flight on this workspace");
   b->pending = false;
   if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
@@ -617,8 +626,10 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
   const int64_t total = (int64_t)b->h_ctr->total;
   *total_out = total;
   HIPCHK(hipMemcpyAsync(offsets, b->offs, (size_t)(b->nq + 1) * 8, hipMemcpyDeviceToDevice, s));
-  if (total > max_results)
+  if (total > max_results) {
+    b->pending = keep_on_overflow;
     return fail(GT_ERR_RESULT_OVERFLOW, "need max_results >= " + std::to_string(total));
+  }
   if (total > 0) {
     TRY(ensure_out(b, total));
     TRY(zero_dev(b->qcursor, (size_t)b->nq_pad * 4, s));
@@ -851,7 +862,7 @@ gt_status gt_query_batch(gt_index* ix, const float* q_dev, int32_t nq, const dou
   if (!offsets_dev) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
   if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
   TRY(submit(ix, ix->def, 1, q_dev, nq, rho_host, (int)fmt, (hipStream_t)stream));
-  return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out);
+  return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out, false);
 }
 
 gt_status gt_exhaustive(gt_index* ix, const float* q_dev, int32_t nq, const double* rho_host,
@@ -863,7 +874,7 @@ gt_status gt_exhaustive(gt_index* ix, const float* q_dev, int32_t nq, const doub
   if (!offsets_dev) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
   if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
   TRY(submit(ix, ix->def, 2, q_dev, nq, rho_host, 0, (hipStream_t)stream));
-  return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out);
+  return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out, false);
 }
 
 gt_status gt_batch_create(gt_index* ix, int32_t max_queries, gt_batch** out) {
@@ -916,7 +927,7 @@ gt_status gt_batch_finish(gt_batch* b, int64_t max_results, int64_t* offsets_dev
                           float* sims_dev, int64_t* total_out) {
   g_err.clear();
   if (!b) return fail(GT_ERR_INVALID_ARG, "batch is NULL");
-  return finish(b->ix, b, max_results, offsets_dev, ids_dev, sims_dev, total_out);
+  return finish(b->ix, b, max_results, offsets_dev, ids_dev, sims_dev, total_out, true);
 }
 
 void gt_batch_destroy(gt_batch* b) {

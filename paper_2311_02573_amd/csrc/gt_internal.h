@@ -79,6 +79,7 @@ struct WalkLevelArgs {
 // Arguments of a dense level step (children at `level`, all 2^level pools).
 struct DenseLevelArgs {
   int level, nt, dp;
+  int64_t rows;             // pools tested: those holding a row below the epoch
   int nb;                   // bucket bits of the sparse output
   int64_t bcap;
   const void* child_rows;   // first row of `level` in the pool format

@@ -476,7 +476,7 @@ __global__ __launch_bounds__(256) void k_dense_level(DenseLevelArgs a) {
   static_assert(F::TQ == 64, "dense steps use 64-query tiles");
   __shared__ __attribute__((aligned(16))) unsigned char As[kDR * kDStride];
   __shared__ __attribute__((aligned(16))) unsigned char Bs[kDQ * kDStride];
-  const int64_t rows = int64_t(1) << a.level;
+  const int64_t rows = a.rows;  // pools holding a row below the call's epoch
   const int64_t RB = (rows + kDR - 1) / kDR;
   const int QB = (a.nt + 1) / 2;
   const int64_t total = RB * QB;
@@ -1042,7 +1042,8 @@ hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {
   if (!a.out_dense &&
       (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots || a.level < a.nb))
     return hipErrorInvalidValue;
-  const int64_t rows = int64_t(1) << a.level;
+  if (a.rows < 1 || a.rows > (int64_t(1) << a.level)) return hipErrorInvalidValue;
+  const int64_t rows = a.rows;
   const int64_t total = ((rows + kDR - 1) / kDR) * ((a.nt + 1) / 2);
   const int64_t grid = 8 * ((total + 7) / 8);
   switch (fmt) {

@@ -297,10 +297,14 @@ class Workspace:
                                        ctypes.c_void_p(ids.data_ptr()), ctypes.c_void_p(sims.data_ptr()),
                                        ctypes.byref(total))
             if st == GT_ERR_RESULT_OVERFLOW and max_results is None:
-                # the call is complete; run it again with room for every result
-                self._max_results = max(self._max_results, total.value)
-                self.submit(self._q, self._rho, self._pool)
-                return self.finish(total.value)
+                # the results are kept on the device: finish again with room for all
+                need = total.value
+                self._max_results = max(self._max_results, need + need // 4)
+                ids = torch.empty(max(need, 1), dtype=torch.int64, device=dev)
+                sims = torch.empty(max(need, 1), dtype=torch.float32, device=dev)
+                st = lib().gt_batch_finish(self._h, need, ctypes.c_void_p(offsets.data_ptr()),
+                                           ctypes.c_void_p(ids.data_ptr()),
+                                           ctypes.c_void_p(sims.data_ptr()), ctypes.byref(total))
             _check(st)
         torch.cuda.current_stream().wait_stream(self.stream)
         res = Results(offsets, ids, sims, total.value)

@@ -150,6 +150,20 @@ def workload1(nq: int = 1024, rho: float = 0.9, n: int = 1 << 20, d: int = 1000,
                     queries[:nq].copy(), np.full(nq, rho), planted[:nq], capacity=n)
 
 
+def workload3(n0: int = 1 << 22, d: int = 512, capacity: int = 1 << 23, nq_pool: int = 8192,
+              rho: float = 0.9) -> Workload:
+    """Serving workload: N0=2^22 rows, d=512, T=0.2, stored float16, room for
+    inserts up to `capacity`; a pool of queries drawn the same way from which
+    requests take consecutive slices.  Arrivals: poisson_arrivals(3, ...);
+    inserted rows: insert_rows(3, ...)."""
+    temp = 0.2
+    feats = softmax_rows(stream_seed(3, STREAM_DB), n0, d, temp)
+    queries = softmax_rows(stream_seed(3, STREAM_QUERY), nq_pool, d, temp)
+    return Workload(f"softmax N0={n0} d={d} T=0.2 f16", 3, n0, d, temp, "f16",
+                    to_storage(feats, "f16"), queries, np.full(nq_pool, rho),
+                    [np.zeros(0, np.int64)] * nq_pool, capacity=capacity)
+
+
 def workload_small(n: int, d: int, nq: int, temp: float = 0.25, rho: float = 0.9,
                    max_planted: int = 8, seed_offset: int = 0, dtype: str = "f32",
                    capacity: int | None = None) -> Workload:

@@ -243,6 +243,42 @@ def test_errors_and_overflow(gtmod):
     idx.close()
 
 
+def test_workspace_overflow_keeps_results(gtmod):
+    """gt_batch_finish with too small buffers reports the size and keeps the
+    call's results; a second finish with room returns them without a rerun."""
+    import ctypes
+
+    w = synth.workload_small(3000, 96, 12, temp=0.25, seed_offset=17)
+    F = np.asarray(w.feats)
+    idx = gtmod.GTIndex(_dev(F))
+    q = _dev(w.queries)
+    ora = ob.range_search(F, w.queries, 0.3)
+    total = sum(len(i) for i, _ in ora)
+    assert total > 1
+    ws = gtmod.Workspace(idx, 64)
+    ws.submit(q, 0.3, "bf16")
+    lib = gtmod.lib()
+    offs = torch.empty(13, dtype=torch.int64, device="cuda")
+    ids = torch.empty(total, dtype=torch.int64, device="cuda")
+    sims = torch.empty(total, dtype=torch.float32, device="cuda")
+    got = ctypes.c_int64(0)
+    st = lib.gt_batch_finish(ws._h, 1, ctypes.c_void_p(offs.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                             ctypes.c_void_p(sims.data_ptr()), ctypes.byref(got))
+    assert st == gtmod.GT_ERR_RESULT_OVERFLOW and got.value == total
+    st = lib.gt_batch_finish(ws._h, total, ctypes.c_void_p(offs.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                             ctypes.c_void_p(sims.data_ptr()), ctypes.byref(got))
+    assert st == gtmod.GT_OK and got.value == total
+    torch.cuda.synchronize()
+    res = gtmod.Results(offs, ids, sims, total)
+    assert_same(res.to_lists(), ora, "workspace finish after overflow")
+    # the workspace is free again; the binding's own retry path gives the same
+    ws._max_results = 1
+    ws.submit(q, 0.3, "bf16")
+    assert_same(ws.finish().to_lists(), ora, "binding retry")
+    ws.close()
+    idx.close()
+
+
 # --------------------------------------------------------- determinism / mixes
 def test_result_of_a_query_does_not_depend_on_its_batch(gtmod):
     w = synth.workload_small(20000, 200, 150, temp=0.2, seed_offset=16)
