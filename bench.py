@@ -86,6 +86,8 @@ def main():
                     help="end with a 1 GiB device-to-device copy (reference for memory counters)")
     ap.add_argument("--sweep-dense", action="store_true",
                     help="also time the walk for several dense/sparse split levels")
+    ap.add_argument("--dense-last", type=int, default=-2,
+                    help="last level walked with dense steps (-2: automatic, -1: none)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of each loaded serving run (0: no serving leg)")
     args = ap.parse_args()
@@ -119,6 +121,8 @@ def main():
         f"{st0['bytes_device'] / 2**30:.2f} GiB")
     del feats
     torch.cuda.empty_cache()
+    if args.dense_last != -2:
+        idx.set_option("dense_last", args.dense_last)
 
     def run(pool, steps, warmup):
         fn = (lambda: idx.exhaustive(q, args.rho)) if pool == "exh" else \
@@ -210,7 +214,7 @@ def main():
             idx.set_option("dense_last", dl)
             _, wl, _ = run(args.pool, 5, 1)
             sweep[dl] = round(wl / 5 * 1e3, 3)
-        idx.set_option("dense_last", -2)
+        idx.set_option("dense_last", args.dense_last)
         log(f"dense_last sweep (ms/batch): {sweep}")
 
     # ---- comparators and recall against the exhaustive GEMM
@@ -334,6 +338,29 @@ def serving_leg(seconds, torch, gt, synth, dev):
                                          "ms_recheck", "ms_compact")}
     call["results"] = r1.total
     log(f"serving index, one 1024-query call: {call}")
+    # streaming inserts: groups of 100 rows (the serving rate's unit) and one
+    # bulk insert, each call timed to completion on the host clock
+    ins_lat = []
+    for k in range(50):
+        rows = torch.from_numpy(synth.insert_rows(3, 100, w.d, w.temp, offset=100000 + k)).to(
+            dev, torch.float16)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        idx.insert(rows)
+        torch.cuda.synchronize()
+        ins_lat.append((time.perf_counter() - t1) * 1e3)
+    bulk = torch.from_numpy(synth.insert_rows(3, 100000, w.d, w.temp, offset=200000)).to(
+        dev, torch.float16)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    idx.insert(bulk)
+    torch.cuda.synchronize()
+    bulk_s = time.perf_counter() - t1
+    del bulk
+    inserts = {"group_100_rows_ms": {"p50": round(pct(ins_lat, 50), 3), "p99": round(pct(ins_lat, 99), 3)},
+               "groups_of_100_rows_per_s": round(100 * 1e3 / float(np.mean(ins_lat)), 1),
+               "bulk_100000_rows_per_s": round(1e5 / bulk_s, 1)}
+    log(f"serving index, inserts: {inserts}")
     backend = serve.GpuBackend(idx)
     nqp = qpool.shape[0]
     make_q = lambda i, k: qpool[(i * 613) % (nqp - 512):(i * 613) % (nqp - 512) + k]
@@ -358,7 +385,7 @@ def serving_leg(seconds, torch, gt, synth, dev):
                        "requests U{1..512} queries at rho=0.9, Poisson arrivals, "
                        "inserts 10000/s in groups of 100",
            "saturated_qps": round(sat_qps, 1), "workspaces": 4, "max_queries_per_call": 1024,
-           "call_1024_queries": call}
+           "call_1024_queries": call, "inserts": inserts}
     for load in (0.5, 0.8):
         rate = load * sat_qps / 256.5          # requests/s (mean request 256.5 queries)
         sched = synth.poisson_arrivals(3, rate, seconds, 512, seed_offset=int(load * 10))

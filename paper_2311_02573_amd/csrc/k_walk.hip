@@ -458,50 +458,130 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
 
 // Dense level step: every pool of a level against every query, as a matrix
 // product with a masked epilogue.  Used where almost every (pool, query tile)
-// pair is live (the first levels below the head), so reading each pool row
-// once per workgroup column and keeping the queries in LDS beats a per-tile
-// frontier, which would read each row once per tile.  A workgroup (4 waves)
-// computes 128 pools x 128 queries (2 tiles); each wave owns 64 pools x one
-// 64-query tile.  K is staged through LDS 128 bytes per row at a time with a
-// register prefetch of the next stage; several workgroups share a CU so one
-// computes while another waits for memory.  Child j of level L survives for
-// query b iff its parent's bit b is set and its score reaches tau'_b.  Output:
-// per-(pool, tile) masks for the next dense level, or the tiles' sparse
-// frontiers for the walk that follows.
-constexpr int kDR = 128, kDQ = 128, kDChunk = 128, kDStride = kDChunk + 16;
+// pair is live (the first levels below the head): each pool row is read once
+// per 128-query column block instead of once per tile.  A workgroup (8 waves)
+// computes 256 pools x 128 queries (2 tiles); each wave owns 64 pools x one
+// 64-query tile (2 x 2 blocks of 32x32 matrix-core tiles).  K advances 128
+// bytes per row per stage: a stage's global loads (each instruction moves 8
+// rows x 128 contiguous bytes) are issued two stages ahead into one of two
+// register sets, then written to one of two LDS buffers.  Within a row the
+// 16-byte chunks are stored XOR-swizzled so that the matrix-core operand
+// reads of any aligned 8 or 16 lanes hit distinct LDS banks.  Child j of
+// level L survives for query b iff its parent's bit b is set and its score
+// reaches tau'_b.  Output: per-(pool, tile) masks for the next dense level,
+// or the bucketed sparse frontier for the walk that follows.
+constexpr int kDM = 256, kDN = 128, kDK = 128;  // pools, queries, K bytes per stage
+constexpr int kDStageA = kDM * kDK, kDStage = (kDM + kDN) * kDK;  // 32 KB + 16 KB
+constexpr int kDThreads = 512;
+
+// physical 16-byte chunk of logical chunk c in LDS row r: c ^ dswz(r)
+__device__ __forceinline__ int dswz(int r) { return (r + (r >> 3)) & 7; }
+
+// The six load slots of a thread in a dense stage (see k_dense_level).
+struct DenseSlots {
+  int lr0, lc, rowbytes;
+  int64_t row0, rows;
+  const unsigned char* crow;
+  const unsigned char* qbase;
+};
+__device__ __forceinline__ void dense_slot(const DenseSlots& d, int m, const unsigned char*& g,
+                                           int& l) {
+  const int lr = d.lr0 + 64 * (m & 3);  // row within the pool (m < 4) or query (m >= 4) block
+  const int off = 16 * (d.lc ^ dswz(lr));
+  if (m < 4) {
+    const int64_t gr = d.row0 + lr < d.rows ? d.row0 + lr : d.rows - 1;
+    g = d.crow + (size_t)gr * d.rowbytes + 16 * d.lc;
+    l = lr * kDK + off;
+  } else {
+    g = d.qbase + (size_t)lr * d.rowbytes + 16 * d.lc;
+    l = kDStageA + lr * kDK + off;
+  }
+}
+// One register set of a stage: six 16-byte slots, kept as separate values so
+// that they live in registers.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct DenseRegs {
+  u32x4 v0, v1, v2, v3, v4, v5;
+};
+template <int M>
+__device__ __forceinline__ u32x4& dense_reg(DenseRegs& r) {
+  if constexpr (M == 0) return r.v0;
+  else if constexpr (M == 1) return r.v1;
+  else if constexpr (M == 2) return r.v2;
+  else if constexpr (M == 3) return r.v3;
+  else if constexpr (M == 4) return r.v4;
+  else return r.v5;
+}
+template <int M>
+__device__ __forceinline__ void dense_gload1(const DenseSlots& d, int ss, DenseRegs& R) {
+  const unsigned char* g;
+  int l;
+  dense_slot(d, M, g, l);
+  dense_reg<M>(R) = *reinterpret_cast<const u32x4*>(g + ss * kDK);
+}
+template <int M>
+__device__ __forceinline__ void dense_lwrite1(const DenseSlots& d, DenseRegs& R, unsigned char* buf) {
+  const unsigned char* g;
+  int l;
+  dense_slot(d, M, g, l);
+  *reinterpret_cast<u32x4*>(buf + l) = dense_reg<M>(R);
+}
+__device__ __forceinline__ void dense_gload(const DenseSlots& d, int s, int slast, DenseRegs& R) {
+  const int ss = s < slast ? s : slast;
+  dense_gload1<0>(d, ss, R);
+  dense_gload1<1>(d, ss, R);
+  dense_gload1<2>(d, ss, R);
+  dense_gload1<3>(d, ss, R);
+  dense_gload1<4>(d, ss, R);
+  dense_gload1<5>(d, ss, R);
+}
+__device__ __forceinline__ void dense_lwrite(const DenseSlots& d, DenseRegs& R, unsigned char* buf) {
+  dense_lwrite1<0>(d, R, buf);
+  dense_lwrite1<1>(d, R, buf);
+  dense_lwrite1<2>(d, R, buf);
+  dense_lwrite1<3>(d, R, buf);
+  dense_lwrite1<4>(d, R, buf);
+  dense_lwrite1<5>(d, R, buf);
+}
 
 template <int FMT>
-__global__ __launch_bounds__(256) void k_dense_level(DenseLevelArgs a) {
+__global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) {
   using F = WalkFmt<FMT>;
   static_assert(F::TQ == 64, "dense steps use 64-query tiles");
-  __shared__ __attribute__((aligned(16))) unsigned char As[kDR * kDStride];
-  __shared__ __attribute__((aligned(16))) unsigned char Bs[kDQ * kDStride];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds0[kDStage];
+  __shared__ __attribute__((aligned(1024))) unsigned char lds1[kDStage];
   const int64_t rows = a.rows;  // pools holding a row below the call's epoch
-  const int64_t RB = (rows + kDR - 1) / kDR;
+  const int64_t RB = (rows + kDM - 1) / kDM;
   const int QB = (a.nt + 1) / 2;
   const int64_t total = RB * QB;
+  // XCD-aware order: the workgroups of one XCD take consecutive tiles, i.e.
+  // all query blocks of a pool block, which then passes through one L2
   const int64_t per_xcd = (total + 7) / 8;
   const int64_t wid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (wid >= total) return;
   const int qb = (int)(wid % QB);
-  const int64_t row0 = (wid / QB) * kDR;
+  const int64_t row0 = (wid / QB) * kDM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wt = wave & 1;
   const int t = qb * 2 + wt;
   const int r = lane & 31, half = lane >> 5;
   const int rowbytes = a.dp * F::ESZ;
-  const int nqrows = a.nt * 64;
+  const int nst = rowbytes / kDK;
+  const int slast = nst - 1;
   const unsigned char* crow = reinterpret_cast<const unsigned char*>(a.child_rows);
   const unsigned char* qrow = reinterpret_cast<const unsigned char*>(a.qtile);
 
-  // does any of this wave's 32 parents survive for tile t?
-  bool active = false;
-  if (t < a.nt) {
-    const int64_t par = ((row0 + wr * 64) >> 1) + (lane & 31);
-    uint64_t pm = 0ull;
-    if (2 * par < rows) pm = a.parent ? a.parent[par * a.nt + t] : a.tile_mask[t];
-    active = __ballot(pm != 0ull) != 0ull;
-  }
+  // A stage is 48 load instructions of 8 rows x 128 bytes (32 for the pool
+  // rows, 16 for the query rows); wave w issues instructions w + 8 m.  Lane l
+  // moves chunk l % 8 of row l / 8 of the instruction.
+  DenseSlots sl6;
+  sl6.lr0 = wave * 8 + (lane >> 3);
+  sl6.lc = lane & 7;
+  sl6.row0 = row0;
+  sl6.rows = rows;
+  sl6.qbase = qrow + (size_t)qb * kDN * rowbytes;
+  sl6.crow = crow;
+  sl6.rowbytes = rowbytes;
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -511,63 +591,58 @@ __global__ __launch_bounds__(256) void k_dense_level(DenseLevelArgs a) {
 #pragma unroll
       for (int x = 0; x < 16; ++x) acc[i][j][x] = 0.0f;
 
-  // staging: thread tid moves the 16-byte pieces of rows tid/8 + 32 v (v < 4),
-  // byte (tid % 8) * 16 of each 128-byte stage, for pools and for queries
-  const int prow = tid >> 3, pc16 = (tid & 7) * 16;
-  const unsigned char* ga[4];
-  const unsigned char* gq[4];
+  auto compute = [&](const unsigned char* As) {
+    const unsigned char* Bs = As + kDStageA;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int64_t gr = row0 + prow + 32 * v < rows ? row0 + prow + 32 * v : rows - 1;
-    ga[v] = crow + (size_t)gr * rowbytes + pc16;
-    gq[v] = qrow + (size_t)min(qb * kDQ + prow + 32 * v, nqrows - 1) * rowbytes + pc16;
-  }
-  uint4 ra0 = *reinterpret_cast<const uint4*>(ga[0]);
-  uint4 ra1 = *reinterpret_cast<const uint4*>(ga[1]);
-  uint4 ra2 = *reinterpret_cast<const uint4*>(ga[2]);
-  uint4 ra3 = *reinterpret_cast<const uint4*>(ga[3]);
-  uint4 rq0 = *reinterpret_cast<const uint4*>(gq[0]);
-  uint4 rq1 = *reinterpret_cast<const uint4*>(gq[1]);
-  uint4 rq2 = *reinterpret_cast<const uint4*>(gq[2]);
-  uint4 rq3 = *reinterpret_cast<const uint4*>(gq[3]);
-  for (int k0 = 0; k0 < rowbytes; k0 += kDChunk) {
-    __syncthreads();
-    *reinterpret_cast<uint4*>(As + (prow + 0) * kDStride + pc16) = ra0;
-    *reinterpret_cast<uint4*>(As + (prow + 32) * kDStride + pc16) = ra1;
-    *reinterpret_cast<uint4*>(As + (prow + 64) * kDStride + pc16) = ra2;
-    *reinterpret_cast<uint4*>(As + (prow + 96) * kDStride + pc16) = ra3;
-    *reinterpret_cast<uint4*>(Bs + (prow + 0) * kDStride + pc16) = rq0;
-    *reinterpret_cast<uint4*>(Bs + (prow + 32) * kDStride + pc16) = rq1;
-    *reinterpret_cast<uint4*>(Bs + (prow + 64) * kDStride + pc16) = rq2;
-    *reinterpret_cast<uint4*>(Bs + (prow + 96) * kDStride + pc16) = rq3;
-    __syncthreads();
-    if (k0 + kDChunk < rowbytes) {
-      const int kn = k0 + kDChunk;
-      ra0 = *reinterpret_cast<const uint4*>(ga[0] + kn);
-      ra1 = *reinterpret_cast<const uint4*>(ga[1] + kn);
-      ra2 = *reinterpret_cast<const uint4*>(ga[2] + kn);
-      ra3 = *reinterpret_cast<const uint4*>(ga[3] + kn);
-      rq0 = *reinterpret_cast<const uint4*>(gq[0] + kn);
-      rq1 = *reinterpret_cast<const uint4*>(gq[1] + kn);
-      rq2 = *reinterpret_cast<const uint4*>(gq[2] + kn);
-      rq3 = *reinterpret_cast<const uint4*>(gq[3] + kn);
-    }
-    if (active) {
+    for (int sl = 0; sl < kDK / 32; ++sl) {
+      const int c = 2 * sl + half;
+      uint4 av[2], bv[2];
 #pragma unroll
-      for (int sl = 0; sl < kDChunk / 32; ++sl) {
-        uint4 b[2], av[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          b[j] = *reinterpret_cast<const uint4*>(Bs + (wt * 64 + j * 32 + r) * kDStride + 32 * sl + 16 * half);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          av[i] = *reinterpret_cast<const uint4*>(As + (wr * 64 + i * 32 + r) * kDStride + 32 * sl + 16 * half);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) mma16<FMT>(av[i], b[j], acc[i][j]);
+      for (int i = 0; i < 2; ++i) {
+        const int ar = wr * 64 + i * 32 + r;
+        av[i] = *reinterpret_cast<const uint4*>(As + ar * kDK + 16 * (c ^ dswz(ar)));
       }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int br = wt * 64 + j * 32 + r;
+        bv[j] = *reinterpret_cast<const uint4*>(Bs + br * kDK + 16 * (c ^ dswz(br)));
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) mma16<FMT>(av[i], bv[j], acc[i][j]);
     }
+  };
+  // Step s: stage s is in LDS buffer s % 2, stage s + 1 in one register set,
+  // stage s + 2 in flight into the other.  After the barrier (every wave is
+  // done with stage s - 1, whose buffer now takes stage s + 1) the first set
+  // is written out and refilled with stage s + 3.  Loads past the last stage
+  // re-read it, so every step issues the same number and the compiler waits
+  // only for the set it writes out.
+  DenseRegs R0, R1;
+  dense_gload(sl6, 0, slast, R0);
+  dense_gload(sl6, 1, slast, R1);
+  dense_lwrite(sl6, R0, lds0);
+  dense_gload(sl6, 2, slast, R0);
+  // stage pairs, so that both halves of the loop body keep the accumulators
+  // in the same registers; an odd last stage follows the loop
+  int s = 0;
+  for (; s + 1 < nst; s += 2) {
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS writes are done
+    __builtin_amdgcn_s_barrier();
+    dense_lwrite(sl6, R1, lds1);
+    dense_gload(sl6, s + 3, slast, R1);
+    compute(lds0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    dense_lwrite(sl6, R0, lds0);
+    dense_gload(sl6, s + 4, slast, R0);
+    compute(lds1);
+  }
+  if (s < nst) {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    compute(lds0);
   }
   if (t >= a.nt) return;
 
@@ -1043,15 +1118,16 @@ hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {
       (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots || a.level < a.nb))
     return hipErrorInvalidValue;
   if (a.rows < 1 || a.rows > (int64_t(1) << a.level)) return hipErrorInvalidValue;
+  if ((a.dp * (fmt == GT_POOL_FP8E4M3 ? 1 : 2)) % kDK != 0) return hipErrorInvalidValue;
   const int64_t rows = a.rows;
-  const int64_t total = ((rows + kDR - 1) / kDR) * ((a.nt + 1) / 2);
+  const int64_t total = ((rows + kDM - 1) / kDM) * ((a.nt + 1) / 2);
   const int64_t grid = 8 * ((total + 7) / 8);
   switch (fmt) {
     case GT_POOL_BF16:
-      hipLaunchKernelGGL(k_dense_level<GT_POOL_BF16>, dim3((unsigned)grid), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_dense_level<GT_POOL_BF16>, dim3((unsigned)grid), dim3(kDThreads), 0, s, a);
       break;
     case GT_POOL_FP8E4M3:
-      hipLaunchKernelGGL(k_dense_level<GT_POOL_FP8E4M3>, dim3((unsigned)grid), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_dense_level<GT_POOL_FP8E4M3>, dim3((unsigned)grid), dim3(kDThreads), 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;

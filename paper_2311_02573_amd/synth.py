@@ -164,6 +164,32 @@ def workload3(n0: int = 1 << 22, d: int = 512, capacity: int = 1 << 23, nq_pool:
                     [np.zeros(0, np.int64)] * nq_pool, capacity=capacity)
 
 
+def workload4(n: int = 1 << 17, d: int = 256, nq: int = 200, clusters: int = 8,
+              per_cluster: int = 2000, sigma: float = 0.02, cluster_query_frac: float = 0.1,
+              rho_lo: float = 0.75, rho_hi: float = 0.95) -> Workload:
+    """Stress shape at a reduced size: rows softmax(z/0.3) stored as bfloat16;
+    `clusters` centres each with `per_cluster` near-duplicates (logit noise
+    sigma) written over uniformly chosen rows; a fraction of the queries are a
+    centre plus the same noise (thousands of neighbours each); per-query
+    thresholds uniform in [rho_lo, rho_hi]."""
+    temp = 0.3
+    feats = softmax_rows(stream_seed(4, STREAM_DB), n, d, temp)
+    g = _rng(stream_seed(4, STREAM_PLANT), 0)
+    centres = g.standard_normal((clusters, d))
+    counts = np.full(clusters, per_cluster)
+    members = _plant(feats, centres, counts, temp, sigma, stream_seed(4, STREAM_PLANT) + 1)
+    queries, _ = softmax_rows(stream_seed(4, STREAM_QUERY), nq, d, temp, return_logits=True)
+    nc = int(round(cluster_query_frac * nq))
+    owner = g.integers(0, clusters, size=nc)
+    queries[:nc] = _softmax_unit_rows(centres[owner] + g.standard_normal((nc, d)) * sigma,
+                                      temp).astype(np.float32)
+    rho = g.uniform(rho_lo, rho_hi, size=nq)
+    planted = [members[o] for o in owner] + [np.zeros(0, np.int64)] * (nq - nc)
+    return Workload(f"softmax N={n} d={d} T=0.3 bf16 clusters {clusters}x{per_cluster}", 4, n,
+                    d, temp, "bf16", to_storage(feats, "bf16"), queries, rho, planted,
+                    capacity=n)
+
+
 def workload_small(n: int, d: int, nq: int, temp: float = 0.25, rho: float = 0.9,
                    max_planted: int = 8, seed_offset: int = 0, dtype: str = "f32",
                    capacity: int | None = None) -> Workload:

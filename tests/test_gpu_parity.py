@@ -139,6 +139,22 @@ def test_half_precision_features(gtmod):
     run_all(gtmod, w.feats, w.queries, 0.8, label="bf16 features")
 
 
+def test_clustered_near_duplicates_per_query_thresholds(gtmod):
+    """Stress shape at a reduced size: bfloat16 rows with 8 clusters of 2000
+    near-duplicates, a tenth of the queries inside a cluster (thousands of
+    neighbours each, many pools live down to the leaves), per-query
+    thresholds in [0.75, 0.95]; every path against the oracle."""
+    w = synth.workload4()
+    say("clustered workload: oracle")
+    ora = run_all(gtmod, w.feats, w.queries, w.rho, label="clusters")
+    big = [len(ora[b][0]) for b in range(20)]
+    assert min(big) >= 1000, big
+    # every near-duplicate whose oracle cosine reaches the threshold is found
+    for b in range(20):
+        want = set(ora[b][0].tolist())
+        assert set(w.planted[b].tolist()) & want, b
+
+
 # --------------------------------------------------------------- tree contents
 def test_pool_sums_are_upper_bounds_and_rounded_up(gtmod):
     """Stored float32 pools bracket the exact member sums from above within
