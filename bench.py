@@ -204,6 +204,9 @@ def main():
         "sparse_raw_bytes": raw_sparse,
         "leaf_raw_bytes": raw_leaf,
         "entries_per_level": {l: entries[l] for l in range(h + 1, D)},
+        "tests_per_level": {l: su["pairs"][l] for l in range(h + 1, D)},
+        "leaf_pairs": su["leaf_pairs"], "leaf_candidates": su["candidates"],
+        "rechecked": su["rechecked"], "results": su["results"],
         "unique_rows_per_level": {l: uniq[l] for l in range(h + 1, D + 1)},
     }
 
@@ -337,6 +340,9 @@ def serving_leg(seconds, torch, gt, synth, dev):
     call = {k: round(st[k], 3) for k in ("ms_total", "ms_dense", "ms_frontier", "ms_leaf",
                                          "ms_recheck", "ms_compact")}
     call["results"] = r1.total
+    call["leaf_pairs"] = st["leaf_pairs"]
+    call["leaf_level_entries"] = st["entries"][st["depth"] - 1]
+    call["depth"] = st["depth"]
     log(f"serving index, one 1024-query call: {call}")
     # streaming inserts: groups of 100 rows (the serving rate's unit) and one
     # bulk insert, each call timed to completion on the host clock
