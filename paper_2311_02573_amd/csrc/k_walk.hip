@@ -715,6 +715,7 @@ struct LeafEntry {
   int t;
   uint32_t p;
   uint64_t m;
+  float inv0, inv1;  // inverse norms of vectors 2p and 2p+1 (0: beyond the epoch or zero)
 };
 
 __device__ __forceinline__ LeafEntry leaf_entry(const LeafArgs& a, const uint32_t* epre, int nsl,
@@ -723,6 +724,7 @@ __device__ __forceinline__ LeafEntry leaf_entry(const LeafArgs& a, const uint32_
   x.t = 0;
   x.p = 0;
   x.m = 0ull;
+  x.inv0 = x.inv1 = 0.0f;
   if (idx >= etot) return x;
   const int sl = find_slot(epre, nsl, idx);
   const int gs = slot0 + sl;
@@ -736,6 +738,14 @@ __device__ __forceinline__ LeafEntry leaf_entry(const LeafArgs& a, const uint32_
     x.m = a.in_mask[(size_t)gs * a.bcap + e];
   }
   return x;
+}
+
+// Inverse norms of an entry's two vectors, fetched one round before its use
+// (the entry itself is fetched two rounds before).
+__device__ __forceinline__ void leaf_norms(const LeafArgs& a, LeafEntry& x) {
+  const int64_t i0 = 2 * (int64_t)x.p;
+  x.inv0 = i0 < a.n_epoch ? a.invn_f[i0] : 0.0f;
+  x.inv1 = i0 + 1 < a.n_epoch ? a.invn_f[i0 + 1] : 0.0f;
 }
 
 // Workgroup -> XCD x = blockIdx % 8, which owns the bucket slots of buckets
@@ -765,10 +775,18 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
   uint32_t idx = 2u * ((blockIdx.x / kXcds) * nw + w);
   LeafEntry nx0 = leaf_entry(a, epre, nsl, slot0, idx, etot);
   LeafEntry nx1 = leaf_entry(a, epre, nsl, slot0, idx + 1, etot);
+  leaf_norms(a, nx0);
+  leaf_norms(a, nx1);
+  LeafEntry nn0 = leaf_entry(a, epre, nsl, slot0, idx + stride, etot);
+  LeafEntry nn1 = leaf_entry(a, epre, nsl, slot0, idx + stride + 1, etot);
   for (; idx < etot; idx += stride) {
     LeafEntry en[2] = {nx0, nx1};
-    nx0 = leaf_entry(a, epre, nsl, slot0, idx + stride, etot);
-    nx1 = leaf_entry(a, epre, nsl, slot0, idx + stride + 1, etot);
+    nx0 = nn0;
+    nx1 = nn1;
+    leaf_norms(a, nx0);
+    leaf_norms(a, nx1);
+    nn0 = leaf_entry(a, epre, nsl, slot0, idx + 2 * stride, etot);
+    nn1 = leaf_entry(a, epre, nsl, slot0, idx + 2 * stride + 1, etot);
     float inv[2][2];
     const float* frow[2][2];
 #pragma unroll
@@ -776,7 +794,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int64_t i = 2 * (int64_t)en[s2].p + c;
-        inv[s2][c] = (en[s2].m && i < a.n_epoch) ? a.invn_f[i] : 0.0f;
+        inv[s2][c] = en[s2].m ? (c == 0 ? en[s2].inv0 : en[s2].inv1) : 0.0f;
         frow[s2][c] = a.leaves + i * a.dp;
         if (a.bitmap && lane == 0 && inv[s2][c] != 0.0f)
           atomicOr(&a.bitmap[(a.bit_base + i) >> 5], 1u << ((a.bit_base + i) & 31));
