@@ -294,12 +294,32 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
       pm0 = e0 < hi ? (a.dense ? tmask : lm0) : 0ull;
       pm1 = e1 < hi ? (a.dense ? tmask : lm1) : 0ull;
     };
-    // Rows of a group's child pools for this lane (row c16 and 16 + c16).
+    // Rows this lane loads.  A load instruction gives each 4 consecutive
+    // lanes 64 contiguous bytes of one row (lanes 4R .. 4R+3: row R of the
+    // block, entry R / 2, child R % 2), so each lane quad touches one cache
+    // line; the matrix-core layout (row = lane % 16) would give every quad
+    // four rows.  p0 / p1 are the entries of this lane's output rows
+    // (c16 / 2 and 8 + c16 / 2); lane 2e holds entry e.
     auto rows_of = [&](uint32_t p0, uint32_t p1, const unsigned char*& r0,
                        const unsigned char*& r1) {
-      const unsigned char* base = reinterpret_cast<const unsigned char*>(a.child_rows) + 16 * g4;
-      r0 = base + (size_t)(2u * p0 + (uint32_t)(lane & 1)) * rowbytes;
-      r1 = base + (size_t)(2u * p1 + (uint32_t)(lane & 1)) * rowbytes;
+      const int src = 2 * (lane >> 3);
+      const uint32_t q0 = (uint32_t)__shfl((int)p0, src, 64);
+      const uint32_t q1 = (uint32_t)__shfl((int)p1, src, 64);
+      const uint32_t ch = (uint32_t)((lane >> 2) & 1);
+      const unsigned char* base = reinterpret_cast<const unsigned char*>(a.child_rows) + 16 * (lane & 3);
+      r0 = base + (size_t)(2u * q0 + ch) * rowbytes;
+      r1 = base + (size_t)(2u * q1 + ch) * rowbytes;
+    };
+    // Loaded slice -> matrix-core operand: lane 16 g + i takes row i, 16-byte
+    // chunk g of the step, which the load left in lane 4 i + g.
+    const int bp_addr = 4 * (4 * c16 + g4);
+    auto to_mfma = [&](const uint4& v) {
+      uint4 r;
+      r.x = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.x);
+      r.y = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.y);
+      r.z = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.z);
+      r.w = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.w);
+      return r;
     };
     // The steps of consecutive groups form one pipeline: while a stage is
     // multiplied, the next one (possibly the first stage of the wave's next
@@ -359,7 +379,8 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc[rb][qb][i] = 0.0f;
 
-      auto step = [&](const uint4& x0, const uint4& x1, int s) {
+      auto step = [&](const uint4& l0, const uint4& l1, int s) {
+        const uint4 x0 = to_mfma(l0), x1 = to_mfma(l1);
 #pragma unroll
         for (int qb = 0; qb < NQB; ++qb) {
           const uint4 bq = ld_lds16(brow + qb * 16 * rs + 64 * s);
