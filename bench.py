@@ -213,7 +213,7 @@ def main():
     sweep = None
     if args.sweep_dense:
         sweep = {}
-        for dl in [-1] + list(range(max(h + 1, D - 7), D)):
+        for dl in [-1] + list(range(max(1, D - 9), D)):
             idx.set_option("dense_last", dl)
             _, wl, _ = run(args.pool, 5, 1)
             sweep[dl] = round(wl / 5 * 1e3, 3)

@@ -62,7 +62,8 @@ typedef struct {
   int64_t capacity;       /* leaves of the tree (power of two) */
   int32_t d, d_pad;       /* dimension and padded row length */
   int32_t depth;          /* log2(capacity): leaves are at this level */
-  int32_t head_level;     /* first level whose pools are tested */
+  int32_t head_level;     /* pools of this level are all taken as live; tests start
+                           * at its children (the last call's, else the index default) */
   uint32_t pool_formats;
   double m_min;           /* smallest norm over non-zero rows */
   uint64_t epoch;         /* bumped by every successful insert */
@@ -193,7 +194,9 @@ gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int
 
 /* Runtime knobs (benchmarking and tests; results never depend on them):
  *   "profile"     0/1: time kernel groups with HIP events (gt_stats.ms_*)
- *   "head_level"  first tested level, 0..depth-1 (-1 = automatic)
+ *   "head_level"  level whose pools are all taken as live, 0..depth-1; tests
+ *                 start at level head_level + 1 (-1 = automatic: with dense
+ *                 steps only the last dense level is tested)
  *   "grid"        workgroups of the persistent walk kernels (0 = one per CU)
  *   "dense_last"  last level tested with dense steps, every pool against every
  *                 query (-2 = automatic, -1 = none; bf16 and fp8 pools only)

@@ -87,10 +87,10 @@ int head_of(const Index* ix) {
 // matrix cores are 16x slower than bfloat16 ones).
 int dense_last_of(const Index* ix, int fmt, int h) {
   if (fmt == GT_POOL_F32 || ix->dense_last == -1) return -1;
-  // automatic: the level whose pools hold about 64 of the populated rows
+  // automatic: the level whose pools hold about 32 of the populated rows
   int lg = 0;
   while ((int64_t(1) << lg) < ix->n) ++lg;
-  int dl = ix->dense_last >= 0 ? ix->dense_last : lg - 6;
+  int dl = ix->dense_last >= 0 ? ix->dense_last : lg - 5;
   dl = std::min(dl, ix->depth - 1);
   return dl > h ? dl : -1;
 }
@@ -540,6 +540,12 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   b->n_epoch = ix->n;
   b->head = head_of(ix);
   b->dense_last = kind == 1 ? dense_last_of(ix, fmt, b->head) : -1;
+  // A dense step computes every pool of its level against every query, and
+  // a pool's score never exceeds its parent's (non-negative rows, sums
+  // rounded up), so a chain of dense steps keeps the same (pool, query) pairs
+  // as its last step alone, up to rounding, which only keeps more.  With an
+  // automatic head only the last dense level is tested.
+  if (b->dense_last >= 0 && ix->head_level < 0) b->head = b->dense_last - 1;
   b->nb = bucket_bits_of(b->dense_last >= 0 ? b->dense_last : b->head, nt);
   b->profile = ix->profile;
   b->nw = 0;
@@ -589,6 +595,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   b->last_nq = nq;
   b->last_nt = nt;
   b->last_fmt = kind == 1 ? fmt : 0;
+  b->last_head = b->head;
   return GT_OK;
 }
 
@@ -946,7 +953,6 @@ gt_status gt_get_stats(const gt_index* ix, gt_stats* out) {
   out->d = ix->d;
   out->d_pad = ix->dp;
   out->depth = ix->depth;
-  out->head_level = head_of(ix);
   out->pool_formats = ix->formats;
   out->m_min = ix->m_min;
   out->epoch = ix->epoch;
@@ -956,6 +962,7 @@ gt_status gt_get_stats(const gt_index* ix, gt_stats* out) {
   out->last_nq = b->last_nq;
   out->last_tiles = b->last_nt;
   out->last_format = b->last_fmt;
+  out->head_level = b->last_nt > 0 && b->last_head >= 0 ? b->last_head : head_of(ix);
   if (b->ctr && b->last_nt > 0) {
     HIPCHK(hipDeviceSynchronize());
     std::vector<uint32_t> cnt((size_t)GT_MAX_LEVELS * gt::kMaxSlots);

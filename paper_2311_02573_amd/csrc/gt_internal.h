@@ -183,7 +183,7 @@ struct Batch {
   bool profile = false;
 
   // counters of the last finished call
-  int last_nq = 0, last_nt = 0, last_fmt = 0;
+  int last_nq = 0, last_nt = 0, last_fmt = 0, last_head = -1;
   double ms[8] = {0};
   int frontier_launches = 0, dense_launches = 0;
 };

@@ -320,19 +320,31 @@ def test_result_of_a_query_does_not_depend_on_its_batch(gtmod):
     idx.close()
 
 
-@pytest.mark.parametrize("dense_last", [-1, -2, "deepest"])
-def test_dense_and_sparse_level_steps_agree(gtmod, dense_last):
+@pytest.mark.parametrize("dense_last,head", [(-1, -1), (-2, -1), ("deepest", -1),
+                                             ("deepest", 2), (-2, 0), (11, 6)])
+def test_dense_and_sparse_level_steps_agree(gtmod, dense_last, head):
     """The walk may test the first levels densely (every pool x every query) and
-    the rest with per-tile frontiers; any split gives the oracle's result."""
+    the rest with per-tile frontiers; any split gives the oracle's result.  An
+    explicit head chains several dense steps (each masked by its parent's
+    result); the automatic head tests only the last dense level."""
     w = synth.workload_small(20000, 300, 200, temp=0.2, seed_offset=17)
     F = np.asarray(w.feats)
     idx = gtmod.GTIndex(_dev(F))
     depth = idx.stats()["depth"]
     idx.set_option("dense_last", depth - 1 if dense_last == "deepest" else dense_last)
+    idx.set_option("head_level", head)
     q = _dev(w.queries)
     for rho in (0.6, 0.9):
         ora = ob.range_search(F, w.queries, rho)
         for f in FORMATS:
-            say(f"dense_last={dense_last} {f} rho={rho}")
-            assert_same(idx.query(q, rho, pool=f).to_lists(), ora, f"dense_last={dense_last} {f}")
+            say(f"dense_last={dense_last} head={head} {f} rho={rho}")
+            assert_same(idx.query(q, rho, pool=f).to_lists(), ora,
+                        f"dense_last={dense_last} head={head} {f}")
+            st = idx.stats()
+            if head >= 0:
+                assert st["head_level"] == head
+            elif f != "f32" and dense_last != -1:
+                # only the last dense level is tested
+                h = st["head_level"]
+                assert st["pairs"][h] == 0 and st["pairs"][h + 1] > 0
     idx.close()
