@@ -156,7 +156,6 @@ void free_query_arrays(Batch* b) {
   dfree(ix, &b->thr, o);
   dfree(ix, &b->thr_gemm, o);
   dfree(ix, &b->qcount, o);
-  dfree(ix, &b->qcursor, o);
   dfree(ix, &b->offs, o + 1);
   if (b->h_rho) (void)hipHostFree(b->h_rho);
   b->h_rho = nullptr;
@@ -185,6 +184,8 @@ void free_batch(Batch* b) {
   dfree(ix, &b->out_sim, (size_t)b->out_cap);
   dfree(ix, &b->tmp_id, (size_t)b->out_cap);
   dfree(ix, &b->tmp_sim, (size_t)b->out_cap);
+  dfree(ix, &b->fin_id, (size_t)b->out_cap);
+  dfree(ix, &b->fin_sim, (size_t)b->out_cap);
   dfree(ix, &b->dmask[0], (size_t)b->dmask_len);
   dfree(ix, &b->dmask[1], (size_t)b->dmask_len);
   dfree(ix, &b->bitmap, (size_t)b->bitmap_words);
@@ -245,7 +246,6 @@ gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
     TRY(dalloc(ix, &b->thr, nqa));
     TRY(dalloc(ix, &b->thr_gemm, nqa));
     TRY(dalloc(ix, &b->qcount, nqa));
-    TRY(dalloc(ix, &b->qcursor, nqa));
     TRY(dalloc(ix, &b->offs, nqa + 1));
     HIPCHK(hipHostMalloc((void**)&b->h_rho, nqa * sizeof(double), hipHostMallocDefault));
     b->nq_alloc = nq_pad;
@@ -284,12 +284,16 @@ gt_status ensure_out(Batch* b, int64_t need) {
   dfree(ix, &b->out_sim, o);
   dfree(ix, &b->tmp_id, o);
   dfree(ix, &b->tmp_sim, o);
+  dfree(ix, &b->fin_id, o);
+  dfree(ix, &b->fin_sim, o);
   b->out_cap = 0;
   const int64_t cap = std::max<int64_t>(need + need / 4, int64_t(1) << 16);
   TRY(dalloc(ix, &b->out_id, (size_t)cap));
   TRY(dalloc(ix, &b->out_sim, (size_t)cap));
   TRY(dalloc(ix, &b->tmp_id, (size_t)cap));
   TRY(dalloc(ix, &b->tmp_sim, (size_t)cap));
+  TRY(dalloc(ix, &b->fin_id, (size_t)cap));
+  TRY(dalloc(ix, &b->fin_sim, (size_t)cap));
   b->out_cap = cap;
   return GT_OK;
 }
@@ -465,7 +469,21 @@ gt_status enqueue_pair_check(Index* ix, Batch* b) {
   return GT_OK;
 }
 
-// recheck, offsets and the copy of the counters the host needs
+// Placement of the accepted pairs by query and the per-query sort by id.
+// lim: largest result count the outputs can take; the kernels check the
+// count on the device and do nothing when it is larger.
+gt_status enqueue_place(Batch* b, int64_t lim, int64_t* ids, float* sims) {
+  hipStream_t s = b->stream;
+  const unsigned long long hc = (unsigned long long)b->hit_cap, l = (unsigned long long)lim;
+  HIPCHK(gt::launch_scatter(b->hits, b->ctr, hc, l, b->offs, b->out_id, b->out_sim, s));
+  HIPCHK(gt::launch_sort_segments(b->offs, b->nq, b->out_id, b->out_sim, b->tmp_id, b->tmp_sim,
+                                  ids, sims, b->ctr, hc, l, s));
+  return GT_OK;
+}
+
+// recheck, offsets, placement and sort of the results (before the host has
+// seen their count, so that a call needs one wait), and the copy of the
+// counters the host needs
 gt_status enqueue_tail(Index* ix, Batch* b) {
   hipStream_t s = b->stream;
   HIPCHK(gt::launch_recheck(b->hits, b->band_idx, &b->ctr->nband, (unsigned long long)b->hit_cap,
@@ -473,6 +491,11 @@ gt_status enqueue_tail(Index* ix, Batch* b) {
                             b->ctr, s));
   ev_mark(b, 4);
   HIPCHK(gt::launch_scan_offsets(b->qcount, b->nq, b->offs, nullptr, b->ctr, s));
+  TRY(ensure_out(b, 1));
+  b->spec_direct = b->tgt_ids != nullptr;
+  b->spec_lim = b->spec_direct ? std::min(b->out_cap, b->tgt_max) : b->out_cap;
+  TRY(enqueue_place(b, b->spec_lim, b->spec_direct ? b->tgt_ids : b->fin_id,
+                    b->spec_direct ? b->tgt_sims : b->fin_sim));
   HIPCHK(hipMemcpyAsync(b->h_ctr, b->ctr, sizeof(gt::DevCounters), hipMemcpyDeviceToHost, s));
   HIPCHK(hipEventRecord(b->done, s));
   ev_mark(b, 5);
@@ -480,6 +503,12 @@ gt_status enqueue_tail(Index* ix, Batch* b) {
 }
 
 // candidate stage again after the candidate buffers grew
+void set_targets(Batch* b, int64_t max_results, int64_t* ids, float* sims) {
+  b->tgt_ids = max_results > 0 ? ids : nullptr;
+  b->tgt_sims = max_results > 0 ? sims : nullptr;
+  b->tgt_max = max_results;
+}
+
 gt_status redo_candidates(Index* ix, Batch* b) {
   hipStream_t s = b->stream;
   TRY(zero_dev(b->qcount, (size_t)b->nq_pad * 4, s));
@@ -616,6 +645,8 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
     HIPCHK(hipEventSynchronize(b->done));
     const gt::DevCounters& c = *b->h_ctr;
     if (c.err) return fail(GT_ERR_INVALID_INPUT, "query contains a NaN, infinite or negative value");
+    if (c.slot_over)
+      return fail(GT_ERR_CAPACITY, "a query has more than 2^30 results");
     const bool cand_over = b->kind == 2 && (int64_t)c.ncand > b->cand_cap;
     const bool hit_over = (int64_t)c.nhits > b->hit_cap;
     if (!cand_over && !hit_over) break;
@@ -638,12 +669,14 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
     return fail(GT_ERR_RESULT_OVERFLOW, "need max_results >= " + std::to_string(total));
   }
   if (total > 0) {
-    TRY(ensure_out(b, total));
-    TRY(zero_dev(b->qcursor, (size_t)b->nq_pad * 4, s));
-    HIPCHK(gt::launch_scatter(b->hits, &b->ctr->nhits, (unsigned long long)b->hit_cap, b->offs,
-                              b->qcursor, b->out_id, b->out_sim, s));
-    HIPCHK(gt::launch_sort_segments(b->offs, b->nq, b->out_id, b->out_sim, b->tmp_id, b->tmp_sim,
-                                    ids, sims, s));
+    if (total > b->spec_lim) {
+      // the enqueued placement did nothing: buffers were too small
+      TRY(ensure_out(b, total));
+      TRY(enqueue_place(b, total, ids, sims));
+    } else if (!(b->spec_direct && ids == b->tgt_ids && sims == b->tgt_sims)) {
+      HIPCHK(hipMemcpyAsync(ids, b->fin_id, (size_t)total * 8, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(sims, b->fin_sim, (size_t)total * 4, hipMemcpyDeviceToDevice, s));
+    }
   }
   ev_mark(b, 6);
   if (b->profile) {
@@ -868,6 +901,8 @@ gt_status gt_query_batch(gt_index* ix, const float* q_dev, int32_t nq, const dou
   if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
   if (!offsets_dev) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
   if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
+  if (max_results > 0 && (!ids_dev || !sims_dev)) return fail(GT_ERR_INVALID_ARG, "NULL output buffer");
+  set_targets(ix->def, max_results, ids_dev, sims_dev);
   TRY(submit(ix, ix->def, 1, q_dev, nq, rho_host, (int)fmt, (hipStream_t)stream));
   return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out, false);
 }
@@ -880,6 +915,8 @@ gt_status gt_exhaustive(gt_index* ix, const float* q_dev, int32_t nq, const doub
   if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
   if (!offsets_dev) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
   if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
+  if (max_results > 0 && (!ids_dev || !sims_dev)) return fail(GT_ERR_INVALID_ARG, "NULL output buffer");
+  set_targets(ix->def, max_results, ids_dev, sims_dev);
   TRY(submit(ix, ix->def, 2, q_dev, nq, rho_host, 0, (hipStream_t)stream));
   return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out, false);
 }
@@ -912,6 +949,7 @@ gt_status gt_batch_submit(gt_batch* b, const float* q_dev, int32_t nq, const dou
                           gt_pool fmt, void* stream) {
   g_err.clear();
   if (!b) return fail(GT_ERR_INVALID_ARG, "batch is NULL");
+  if (!b->pending) set_targets(b, 0, nullptr, nullptr);
   return submit(b->ix, b, 1, q_dev, nq, rho_host, (int)fmt, (hipStream_t)stream);
 }
 

@@ -26,7 +26,7 @@ __device__ __forceinline__ void stage_hits(Hit* buf, int& cnt, bool have, const 
     const unsigned long long slot = base + i;
     if (slot < hit_cap) {
       hits[slot] = x;
-      if (x.flag == HIT_BAND) {
+      if (hit_kind(x.flag) == HIT_BAND) {
         const unsigned long long bp = atomicAdd(&ctr->nband, 1ull);
         if (bp < hit_cap) band_idx[bp] = (uint32_t)slot;
       }
@@ -34,6 +34,16 @@ __device__ __forceinline__ void stage_hits(Hit* buf, int& cnt, bool have, const 
   }
   __builtin_amdgcn_wave_barrier();
   cnt = 0;
+}
+
+// Slot of an accepted pair among its query's results (shifted into the flag).
+__device__ __forceinline__ uint32_t accept_slot(unsigned int* qcount, DevCounters* ctr) {
+  const uint32_t r = atomicAdd(qcount, 1u);
+  if (r >= kMaxResultsPerQuery) {
+    atomicOr(&ctr->slot_over, 1u);
+    return 0u;
+  }
+  return r << 2;
 }
 
 // Classification of a float32 cosine against rho (the float32 value is within

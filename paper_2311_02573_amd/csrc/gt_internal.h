@@ -34,11 +34,17 @@ constexpr int kMaxDpBf16 = 1152, kMaxDpFp8 = 2304, kMaxDpF32 = 1152;
 
 enum : uint32_t { HIT_ACCEPT = 1u, HIT_BAND = 2u, HIT_REJECT = 3u };
 
-struct Hit {           // one candidate (query, vector) pair
+// One candidate (query, vector) pair.  flag: kind in bits 0-1 (HIT_*); an
+// accepted pair carries in bits 2-31 its slot among its query's results, the
+// value of the query's result counter when it was accepted.
+struct Hit {
   uint32_t q, id;
   float sim;
   uint32_t flag;
 };
+__host__ __device__ inline uint32_t hit_kind(uint32_t flag) { return flag & 3u; }
+__host__ __device__ inline uint32_t hit_slot(uint32_t flag) { return flag >> 2; }
+constexpr uint32_t kMaxResultsPerQuery = 1u << 30;
 
 // Counters written by the device during a query call.  Zeroed at call start.
 struct DevCounters {
@@ -49,7 +55,7 @@ struct DevCounters {
   unsigned long long rechecked;
   unsigned long long nband;         // candidates within the recheck band
   unsigned int err;                 // invalid query input seen
-  unsigned int pad;
+  unsigned int slot_over;           // a query reached kMaxResultsPerQuery results
   unsigned long long pairs[GT_MAX_LEVELS];
 };
 
@@ -147,18 +153,27 @@ struct Batch {
   float* thr = nullptr;
   float* thr_gemm = nullptr;
   unsigned int* qcount = nullptr;
-  unsigned int* qcursor = nullptr;
   int64_t* offs = nullptr;   // [nq + 1]
   Hit* hits = nullptr;
   uint32_t* band_idx = nullptr;
   int64_t hit_cap = 0;
   uint2* cand = nullptr;     // exhaustive candidates
   int64_t cand_cap = 0;
-  uint32_t* out_id = nullptr;    // sorted staging
+  uint32_t* out_id = nullptr;    // results placed by query, unsorted
   float* out_sim = nullptr;
-  uint32_t* tmp_id = nullptr;
+  uint32_t* tmp_id = nullptr;    // radix sort scratch
   float* tmp_sim = nullptr;
+  int64_t* fin_id = nullptr;     // sorted results when the caller's buffers are not known yet
+  float* fin_sim = nullptr;
   int64_t out_cap = 0;
+  // Placement and sort are enqueued with the call, before the host has seen
+  // the result count: into the caller's buffers (tgt_*) when the call passed
+  // them, else into fin_*.  They do nothing unless the count fits spec_lim.
+  int64_t* tgt_ids = nullptr;
+  float* tgt_sims = nullptr;
+  int64_t tgt_max = 0;
+  int64_t spec_lim = -1;
+  bool spec_direct = false;
   uint64_t* dmask[2] = {nullptr, nullptr};  // dense survival masks, ping-pong
   int64_t dmask_len = 0;
   uint32_t* bitmap = nullptr;
@@ -245,12 +260,13 @@ hipError_t launch_recheck(Hit* hits, const uint32_t* band_idx, const unsigned lo
                           unsigned int* qcount, DevCounters* ctr, hipStream_t s);
 hipError_t launch_scan_offsets(const unsigned int* qcount, int nq, int64_t* offs_internal,
                                int64_t* offs_out, DevCounters* ctr, hipStream_t s);
-hipError_t launch_scatter(const Hit* hits, const unsigned long long* nhits, unsigned long long cap,
-                          const int64_t* offs, unsigned int* cursor, uint32_t* out_id,
+hipError_t launch_scatter(const Hit* hits, const DevCounters* ctr, unsigned long long hit_cap,
+                          unsigned long long lim, const int64_t* offs, uint32_t* out_id,
                           float* out_sim, hipStream_t s);
 hipError_t launch_sort_segments(const int64_t* offs, int nq, uint32_t* id, float* sim,
                                 uint32_t* tmp_id, float* tmp_sim, int64_t* ids_out,
-                                float* sims_out, hipStream_t s);
+                                float* sims_out, const DevCounters* ctr,
+                                unsigned long long hit_cap, unsigned long long lim, hipStream_t s);
 hipError_t launch_exhaustive_gemm(const float* qf, int nq_pad, const float* leaves, int64_t n,
                                   int dp, const float* thr_gemm, const float* nf, uint2* cand,
                                   unsigned long long cand_cap, DevCounters* ctr, int nq,

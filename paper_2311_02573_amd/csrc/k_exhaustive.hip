@@ -190,8 +190,7 @@ __global__ __launch_bounds__(256) void k_pair_check(const uint2* cand, const uns
       h.q = x.x;
       h.id = x.y;
       h.sim = cs;
-      h.flag = flag;
-      if (flag == HIT_ACCEPT) atomicAdd(&qcount[x.x], 1u);
+      h.flag = flag == HIT_ACCEPT ? flag | accept_slot(&qcount[x.x], ctr) : flag;
       ++npairs;
     }
     stage_hits(buf, cnt, flag != 0u, h, false, ctr, hits, hit_cap, band_idx, lane);

@@ -908,8 +908,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
         h.q = (uint32_t)qg;
         h.id = id;
         h.sim = cs;
-        h.flag = flag;
-        if (flag == HIT_ACCEPT) atomicAdd(&a.qcount[qg], 1u);
+        h.flag = flag == HIT_ACCEPT ? flag | accept_slot(&a.qcount[qg], a.ctr) : flag;
         ++npairs;
       }
       stage_hits(buf, cnt, flag != 0u, h, false, a.ctr, a.hits, a.hit_cap, a.band_idx, lane);
@@ -964,9 +963,8 @@ __global__ __launch_bounds__(256) void k_recheck(Hit* hits, const uint32_t* band
       const double cs = __ddiv_rn(s, __dmul_rn(__dsqrt_rn(qq[x.q]), __dsqrt_rn(ff[x.id])));
       atomicAdd(&ctr->rechecked, 1ull);
       if (cs >= rho[x.q]) {
-        x.flag = HIT_ACCEPT;
+        x.flag = HIT_ACCEPT | accept_slot(&qcount[x.q], ctr);
         x.sim = (float)cs;
-        atomicAdd(&qcount[x.q], 1u);
       } else {
         x.flag = HIT_REJECT;
       }
@@ -1006,33 +1004,63 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(const unsigned int* qcoun
   }
 }
 
-__global__ void k_scatter(const Hit* hits, const unsigned long long* nhits, unsigned long long cap,
-                          const int64_t* offs, unsigned int* cursor, uint32_t* out_id,
+// Accepted pairs to their query's segment: slot = offset of the query + the
+// pair's slot among the query's results.  Enqueued before the host has seen
+// the counts; does nothing unless every candidate was kept (hit_cap) and the
+// results fit the output (lim).
+__device__ __forceinline__ bool results_fit(const DevCounters* ctr, unsigned long long hit_cap,
+                                            unsigned long long lim) {
+  return ctr->nhits <= hit_cap && ctr->total <= lim && ctr->slot_over == 0u && ctr->err == 0u;
+}
+
+__global__ void k_scatter(const Hit* hits, const DevCounters* ctr, unsigned long long hit_cap,
+                          unsigned long long lim, const int64_t* offs, uint32_t* out_id,
                           float* out_sim) {
-  const unsigned long long n = *nhits < cap ? *nhits : cap;
+  if (!results_fit(ctr, hit_cap, lim)) return;
+  const unsigned long long n = ctr->nhits;
   for (unsigned long long h = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; h < n;
        h += (unsigned long long)gridDim.x * blockDim.x) {
     const Hit x = hits[h];
-    if (x.flag != HIT_ACCEPT) continue;
-    const int64_t pos = offs[x.q] + atomicAdd(&cursor[x.q], 1u);
+    if (hit_kind(x.flag) != HIT_ACCEPT) continue;
+    const int64_t pos = offs[x.q] + (int64_t)hit_slot(x.flag);
     out_id[pos] = x.id;
     out_sim[pos] = x.sim;
   }
 }
 
-// Sort each query's results by id.  Up to 4096: bitonic sort in LDS; larger
-// segments: stable 4-bit LSD radix sort by the same workgroup.
+// Sort each query's results by id (ids of one query are distinct).  Up to
+// 512: each thread places its elements by counting the smaller keys; up to
+// 4096: bitonic sort in LDS; larger segments: stable 4-bit LSD radix sort by
+// the same workgroup.
 __global__ __launch_bounds__(256) void k_sort_segments(const int64_t* offs, uint32_t* id,
                                                        float* sim, uint32_t* tmp_id,
                                                        float* tmp_sim, int64_t* ids_out,
-                                                       float* sims_out) {
+                                                       float* sims_out, const DevCounters* ctr,
+                                                       unsigned long long hit_cap,
+                                                       unsigned long long lim) {
   __shared__ uint32_t key[4096];
   __shared__ float val[4096];
   __shared__ uint32_t hist[16 * 256];
   __shared__ uint32_t tot[256];
+  if (!results_fit(ctr, hit_cap, lim)) return;
   const int q = blockIdx.x, t = threadIdx.x;
   const int64_t lo = offs[q], n = offs[q + 1] - lo;
   if (n <= 0) return;
+  if (n <= 512) {
+    for (int i = t; i < n; i += 256) {
+      key[i] = id[lo + i];
+      val[i] = sim[lo + i];
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += 256) {
+      const uint32_t k = key[i];
+      int r = 0;
+      for (int j = 0; j < n; ++j) r += key[j] < k;
+      ids_out[lo + r] = (int64_t)k;
+      sims_out[lo + r] = val[i];
+    }
+    return;
+  }
   if (n <= 4096) {
     int P = 1;
     while (P < n) P <<= 1;
@@ -1199,20 +1227,21 @@ hipError_t launch_scan_offsets(const unsigned int* qcount, int nq, int64_t* offs
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(const Hit* hits, const unsigned long long* nhits, unsigned long long cap,
-                          const int64_t* offs, unsigned int* cursor, uint32_t* out_id,
+hipError_t launch_scatter(const Hit* hits, const DevCounters* ctr, unsigned long long hit_cap,
+                          unsigned long long lim, const int64_t* offs, uint32_t* out_id,
                           float* out_sim, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3(1024), dim3(256), 0, s, hits, nhits, cap, offs, cursor, out_id,
+  hipLaunchKernelGGL(k_scatter, dim3(1024), dim3(256), 0, s, hits, ctr, hit_cap, lim, offs, out_id,
                      out_sim);
   return hipGetLastError();
 }
 
 hipError_t launch_sort_segments(const int64_t* offs, int nq, uint32_t* id, float* sim,
                                 uint32_t* tmp_id, float* tmp_sim, int64_t* ids_out,
-                                float* sims_out, hipStream_t s) {
+                                float* sims_out, const DevCounters* ctr,
+                                unsigned long long hit_cap, unsigned long long lim, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sort_segments, dim3(nq), dim3(256), 0, s, offs, id, sim, tmp_id, tmp_sim,
-                     ids_out, sims_out);
+                     ids_out, sims_out, ctr, hit_cap, lim);
   return hipGetLastError();
 }
 
