@@ -199,6 +199,9 @@ def main():
         "avg_launch_ms": ms / max(1, nl),
         "kernels": {k: {"bytes": v[0], "ms": round(v[1], 4), "launches": v[2], "GBps": gbps(v[0], v[1])}
                     for k, v in groups.items()},
+        # per-stage device time of one call (HIP events, median over the profiled calls)
+        "stage_ms": {k[3:]: round(med(k), 4) for k in ("ms_prep", "ms_dense", "ms_frontier", "ms_leaf",
+                                                      "ms_recheck", "ms_compact", "ms_total")},
         "walk_all_levels": {"bytes": dense_bytes + sparse_bytes, "ms": round(ms_dense + ms_sparse, 4),
                             "GBps": gbps(dense_bytes + sparse_bytes, ms_dense + ms_sparse)},
         "sparse_raw_bytes": raw_sparse,

@@ -1038,7 +1038,7 @@ __global__ __launch_bounds__(256) void k_sort_segments(const int64_t* offs, uint
                                                        float* sims_out, const DevCounters* ctr,
                                                        unsigned long long hit_cap,
                                                        unsigned long long lim) {
-  __shared__ uint32_t key[4096];
+  __shared__ __attribute__((aligned(16))) uint32_t key[4096];
   __shared__ float val[4096];
   __shared__ uint32_t hist[16 * 256];
   __shared__ uint32_t tot[256];
@@ -1047,15 +1047,23 @@ __global__ __launch_bounds__(256) void k_sort_segments(const int64_t* offs, uint
   const int64_t lo = offs[q], n = offs[q + 1] - lo;
   if (n <= 0) return;
   if (n <= 512) {
-    for (int i = t; i < n; i += 256) {
-      key[i] = id[lo + i];
-      val[i] = sim[lo + i];
+    // keys padded to a multiple of 4 with the largest value, which is never
+    // below a key, and compared 4 at a time
+    const int n4 = (int)((n + 3) & ~int64_t(3));
+    for (int i = t; i < n4; i += 256) {
+      key[i] = i < n ? id[lo + i] : 0xFFFFFFFFu;
+      val[i] = i < n ? sim[lo + i] : 0.0f;
     }
     __syncthreads();
+    const uint4* k4 = reinterpret_cast<const uint4*>(key);
     for (int i = t; i < n; i += 256) {
       const uint32_t k = key[i];
       int r = 0;
-      for (int j = 0; j < n; ++j) r += key[j] < k;
+#pragma unroll 4
+      for (int j = 0; j < n4 / 4; ++j) {
+        const uint4 v = k4[j];
+        r += (int)(v.x < k) + (int)(v.y < k) + (int)(v.z < k) + (int)(v.w < k);
+      }
       ids_out[lo + r] = (int64_t)k;
       sims_out[lo + r] = val[i];
     }
