@@ -87,10 +87,10 @@ int head_of(const Index* ix) {
 // matrix cores are 16x slower than bfloat16 ones).
 int dense_last_of(const Index* ix, int fmt, int h) {
   if (fmt == GT_POOL_F32 || ix->dense_last == -1) return -1;
-  // automatic: the level whose pools hold about 32 of the populated rows
+  // automatic: the level whose pools hold about 16 of the populated rows
   int lg = 0;
   while ((int64_t(1) << lg) < ix->n) ++lg;
-  int dl = ix->dense_last >= 0 ? ix->dense_last : lg - 5;
+  int dl = ix->dense_last >= 0 ? ix->dense_last : lg - 4;
   dl = std::min(dl, ix->depth - 1);
   return dl > h ? dl : -1;
 }

@@ -479,73 +479,72 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
 
 // Dense level step: every pool of a level against every query, as a matrix
 // product with a masked epilogue.  Used where almost every (pool, query tile)
-// pair is live (the first levels below the head): each pool row is read once
-// per 128-query column block instead of once per tile.  A workgroup (8 waves)
-// computes 256 pools x 128 queries (2 tiles); each wave owns 64 pools x one
-// 64-query tile (2 x 2 blocks of 32x32 matrix-core tiles).  K advances 128
-// bytes per row per stage: a stage's global loads (each instruction moves 8
-// rows x 128 contiguous bytes) are issued two stages ahead into one of two
-// register sets, then written to one of two LDS buffers.  Within a row the
-// 16-byte chunks are stored XOR-swizzled so that the matrix-core operand
-// reads of any aligned 8 or 16 lanes hit distinct LDS banks.  Child j of
-// level L survives for query b iff its parent's bit b is set and its score
-// reaches tau'_b.  Output: per-(pool, tile) masks for the next dense level,
-// or the bucketed sparse frontier for the walk that follows.
-constexpr int kDM = 256, kDN = 128, kDK = 128;  // pools, queries, K bytes per stage
-constexpr int kDStageA = kDM * kDK, kDStage = (kDM + kDN) * kDK;  // 32 KB + 16 KB
+// pair is live (the first tested level): each pool row is read once per
+// 256-query column block instead of once per tile.  A workgroup (8 waves)
+// computes 256 pools x 256 queries (4 tiles); wave w owns pools 64 (w / 2)
+// .. +63 and tiles 2 (w % 2), 2 (w % 2) + 1 (2 x 4 blocks of 32x32
+// matrix-core tiles).  K advances 128 bytes per row per stage: a stage's
+// global loads (each instruction moves 8 rows x 128 contiguous bytes) are
+// issued one stage ahead into registers, then written to one of two LDS
+// buffers.  Within a row the 16-byte chunks are stored XOR-swizzled
+// so that the matrix-core operand reads of any aligned 8 or 16 lanes hit
+// distinct LDS banks.  Child j of level L survives for query b iff its
+// parent's bit b is set and its score reaches tau'_b.  Output: per-(pool,
+// tile) masks for a following dense level, or the bucketed sparse frontier
+// for the walk that follows.
+constexpr int kDM = 256, kDN = 256, kDK = 128;  // pools, queries, K bytes per stage
+constexpr int kDStageA = kDM * kDK, kDStage = (kDM + kDN) * kDK;  // 32 KB + 32 KB
 constexpr int kDThreads = 512;
+constexpr int kDTiles = kDN / 64;  // query tiles per workgroup
 
 // physical 16-byte chunk of logical chunk c in LDS row r: c ^ dswz(r)
 __device__ __forceinline__ int dswz(int r) { return (r + (r >> 3)) & 7; }
 
-// The six load slots of a thread in a dense stage (see k_dense_level).
+// The eight load slots of a thread in a dense stage (see k_dense_level):
+// slots 0-3 are pool rows lr0 + 64 m, slots 4-7 query rows lr0 + 64 (m - 4).
 struct DenseSlots {
   int lr0, lc, rowbytes;
   int64_t row0, rows;
+  int q0, qrows;  // first query row of the workgroup; query rows that exist
   const unsigned char* crow;
-  const unsigned char* qbase;
+  const unsigned char* qrow;
 };
 __device__ __forceinline__ void dense_slot(const DenseSlots& d, int m, const unsigned char*& g,
                                            int& l) {
-  const int lr = d.lr0 + 64 * (m & 3);  // row within the pool (m < 4) or query (m >= 4) block
+  const int lr = d.lr0 + 64 * (m & 3);  // row within the pool or query block
   const int off = 16 * (d.lc ^ dswz(lr));
   if (m < 4) {
     const int64_t gr = d.row0 + lr < d.rows ? d.row0 + lr : d.rows - 1;
     g = d.crow + (size_t)gr * d.rowbytes + 16 * d.lc;
     l = lr * kDK + off;
   } else {
-    g = d.qbase + (size_t)lr * d.rowbytes + 16 * d.lc;
+    // query rows past the last tile re-read the last row; their columns are
+    // never tested
+    const int qr = d.q0 + lr < d.qrows ? d.q0 + lr : d.qrows - 1;
+    g = d.qrow + (size_t)qr * d.rowbytes + 16 * d.lc;
     l = kDStageA + lr * kDK + off;
   }
 }
-// One register set of a stage: six 16-byte slots, kept as separate values so
-// that they live in registers.
+// One register set of a stage: eight 16-byte slots, kept as separate values
+// so that they live in registers.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 struct DenseRegs {
-  u32x4 v0, v1, v2, v3, v4, v5;
+  u32x4 v[8];
 };
-template <int M>
-__device__ __forceinline__ u32x4& dense_reg(DenseRegs& r) {
-  if constexpr (M == 0) return r.v0;
-  else if constexpr (M == 1) return r.v1;
-  else if constexpr (M == 2) return r.v2;
-  else if constexpr (M == 3) return r.v3;
-  else if constexpr (M == 4) return r.v4;
-  else return r.v5;
-}
 template <int M>
 __device__ __forceinline__ void dense_gload1(const DenseSlots& d, int ss, DenseRegs& R) {
   const unsigned char* g;
   int l;
   dense_slot(d, M, g, l);
-  dense_reg<M>(R) = *reinterpret_cast<const u32x4*>(g + ss * kDK);
+  R.v[M] = *reinterpret_cast<const u32x4*>(g + ss * kDK);
 }
 template <int M>
-__device__ __forceinline__ void dense_lwrite1(const DenseSlots& d, DenseRegs& R, unsigned char* buf) {
+__device__ __forceinline__ void dense_lwrite1(const DenseSlots& d, const DenseRegs& R,
+                                              unsigned char* buf) {
   const unsigned char* g;
   int l;
   dense_slot(d, M, g, l);
-  *reinterpret_cast<u32x4*>(buf + l) = dense_reg<M>(R);
+  *reinterpret_cast<u32x4*>(buf + l) = R.v[M];
 }
 __device__ __forceinline__ void dense_gload(const DenseSlots& d, int s, int slast, DenseRegs& R) {
   const int ss = s < slast ? s : slast;
@@ -555,14 +554,19 @@ __device__ __forceinline__ void dense_gload(const DenseSlots& d, int s, int slas
   dense_gload1<3>(d, ss, R);
   dense_gload1<4>(d, ss, R);
   dense_gload1<5>(d, ss, R);
+  dense_gload1<6>(d, ss, R);
+  dense_gload1<7>(d, ss, R);
 }
-__device__ __forceinline__ void dense_lwrite(const DenseSlots& d, DenseRegs& R, unsigned char* buf) {
+__device__ __forceinline__ void dense_lwrite(const DenseSlots& d, const DenseRegs& R,
+                                             unsigned char* buf) {
   dense_lwrite1<0>(d, R, buf);
   dense_lwrite1<1>(d, R, buf);
   dense_lwrite1<2>(d, R, buf);
   dense_lwrite1<3>(d, R, buf);
   dense_lwrite1<4>(d, R, buf);
   dense_lwrite1<5>(d, R, buf);
+  dense_lwrite1<6>(d, R, buf);
+  dense_lwrite1<7>(d, R, buf);
 }
 
 template <int FMT>
@@ -573,7 +577,7 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
   __shared__ __attribute__((aligned(1024))) unsigned char lds1[kDStage];
   const int64_t rows = a.rows;  // pools holding a row below the call's epoch
   const int64_t RB = (rows + kDM - 1) / kDM;
-  const int QB = (a.nt + 1) / 2;
+  const int QB = (a.nt + kDTiles - 1) / kDTiles;
   const int64_t total = RB * QB;
   // XCD-aware order: the workgroups of one XCD take consecutive tiles, i.e.
   // all query blocks of a pool block, which then passes through one L2
@@ -583,32 +587,31 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
   const int qb = (int)(wid % QB);
   const int64_t row0 = (wid / QB) * kDM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wt = wave & 1;
-  const int t = qb * 2 + wt;
+  const int wr = wave >> 1, wq = wave & 1;
   const int r = lane & 31, half = lane >> 5;
   const int rowbytes = a.dp * F::ESZ;
   const int nst = rowbytes / kDK;
   const int slast = nst - 1;
-  const unsigned char* crow = reinterpret_cast<const unsigned char*>(a.child_rows);
-  const unsigned char* qrow = reinterpret_cast<const unsigned char*>(a.qtile);
 
-  // A stage is 48 load instructions of 8 rows x 128 bytes (32 for the pool
-  // rows, 16 for the query rows); wave w issues instructions w + 8 m.  Lane l
+  // A stage is 64 load instructions of 8 rows x 128 bytes (32 for the pool
+  // rows, 32 for the query rows); wave w issues instructions w + 8 m.  Lane l
   // moves chunk l % 8 of row l / 8 of the instruction.
-  DenseSlots sl6;
-  sl6.lr0 = wave * 8 + (lane >> 3);
-  sl6.lc = lane & 7;
-  sl6.row0 = row0;
-  sl6.rows = rows;
-  sl6.qbase = qrow + (size_t)qb * kDN * rowbytes;
-  sl6.crow = crow;
-  sl6.rowbytes = rowbytes;
+  DenseSlots sl8;
+  sl8.lr0 = wave * 8 + (lane >> 3);
+  sl8.lc = lane & 7;
+  sl8.row0 = row0;
+  sl8.rows = rows;
+  sl8.q0 = qb * kDN;
+  sl8.qrows = a.nt * 64;
+  sl8.crow = reinterpret_cast<const unsigned char*>(a.child_rows);
+  sl8.qrow = reinterpret_cast<const unsigned char*>(a.qtile);
+  sl8.rowbytes = rowbytes;
 
-  f32x16 acc[2][2];
+  f32x16 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int x = 0; x < 16; ++x) acc[i][j][x] = 0.0f;
 
@@ -617,47 +620,46 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
 #pragma unroll
     for (int sl = 0; sl < kDK / 32; ++sl) {
       const int c = 2 * sl + half;
-      uint4 av[2], bv[2];
+      uint4 av[2], bv[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int ar = wr * 64 + i * 32 + r;
         av[i] = *reinterpret_cast<const uint4*>(As + ar * kDK + 16 * (c ^ dswz(ar)));
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int br = wt * 64 + j * 32 + r;
+      for (int j = 0; j < 4; ++j) {
+        const int br = wq * 128 + j * 32 + r;
         bv[j] = *reinterpret_cast<const uint4*>(Bs + br * kDK + 16 * (c ^ dswz(br)));
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) mma16<FMT>(av[i], bv[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) mma16<FMT>(av[i], bv[j], acc[i][j]);
     }
   };
-  // Step s: stage s is in LDS buffer s % 2, stage s + 1 in one register set,
-  // stage s + 2 in flight into the other.  After the barrier (every wave is
-  // done with stage s - 1, whose buffer now takes stage s + 1) the first set
-  // is written out and refilled with stage s + 3.  Loads past the last stage
-  // re-read it, so every step issues the same number and the compiler waits
-  // only for the set it writes out.
-  DenseRegs R0, R1;
-  dense_gload(sl6, 0, slast, R0);
-  dense_gload(sl6, 1, slast, R1);
-  dense_lwrite(sl6, R0, lds0);
-  dense_gload(sl6, 2, slast, R0);
+  // Step s: stage s is in LDS buffer s % 2 and stage s + 1 in flight into the
+  // register set.  After the barrier (every wave is done with stage s - 1,
+  // whose buffer now takes stage s + 1) the set is written out and refilled
+  // with stage s + 2, and stage s is multiplied: a load has one stage of
+  // matrix work (32 MFMAs per wave) to arrive.  Loads past the last stage
+  // re-read it.
+  DenseRegs R;
+  dense_gload(sl8, 0, slast, R);
+  dense_lwrite(sl8, R, lds0);
+  dense_gload(sl8, 1, slast, R);
   // stage pairs, so that both halves of the loop body keep the accumulators
   // in the same registers; an odd last stage follows the loop
   int s = 0;
   for (; s + 1 < nst; s += 2) {
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS writes are done
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS accesses are done
     __builtin_amdgcn_s_barrier();
-    dense_lwrite(sl6, R1, lds1);
-    dense_gload(sl6, s + 3, slast, R1);
+    dense_lwrite(sl8, R, lds1);
+    dense_gload(sl8, s + 2, slast, R);
     compute(lds0);
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_s_barrier();
-    dense_lwrite(sl6, R0, lds0);
-    dense_gload(sl6, s + 4, slast, R0);
+    dense_lwrite(sl8, R, lds0);
+    dense_gload(sl8, s + 3, slast, R);
     compute(lds1);
   }
   if (s < nst) {
@@ -665,60 +667,64 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
     __builtin_amdgcn_s_barrier();
     compute(lds0);
   }
-  if (t >= a.nt) return;
 
-  float thr[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int qi = t * 64 + 32 * j + r;
-    float th = a.thr[qi];
-    if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
-    thr[j] = th;
-  }
   unsigned long long pairs = 0;
   const int bshift = a.level - a.nb;  // node -> bucket of the sparse output
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int64_t row = row0 + wr * 64 + i * 32 + r;
-    const bool rv = lane < 32 && row < rows;
-    uint64_t pm = 0ull;
-    if (rv) pm = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
-    uint64_t mine = 0ull;
+  for (int tt = 0; tt < 2; ++tt) {
+    const int t = qb * kDTiles + 2 * wq + tt;
+    if (t >= a.nt) break;
+    float thr[2];
 #pragma unroll
-    for (int x = 0; x < 16; ++x) {
-      const uint64_t b0 = __ballot(acc[i][0][x] >= thr[0]);
-      const uint64_t b1 = __ballot(acc[i][1][x] >= thr[1]);
-      const uint64_t lo = (b0 & 0xffffffffull) | (b1 << 32);
-      const uint64_t hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
-      const int rr = 8 * (x >> 2) + (x & 3);
-      if (lane == rr) mine = lo;
-      if (lane == rr + 4) mine = hi;
+    for (int j = 0; j < 2; ++j) {
+      const int qi = t * 64 + 32 * j + r;
+      float th = a.thr[qi];
+      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+      thr[j] = th;
     }
-    mine &= pm;
-    if (rv) pairs += (unsigned long long)__popcll(pm);
-    if (a.bitmap && rv && pm) atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
-    const uint64_t eb = __ballot(rv && mine != 0ull);
-    if (a.out_dense) {
-      if (rv) a.out_dense[row * a.nt + t] = mine;
-      if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
-    } else if (eb && bshift >= 5) {
-      // the 32 rows (aligned) share one bucket: one reservation per wave
-      const uint32_t slot = (uint32_t)((row0 + wr * 64 + i * 32) >> bshift) * (uint32_t)a.nt + t;
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(eb));
-      base = __shfl(base, 0, 64);
-      if (rv && mine) {
-        const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int64_t row = row0 + wr * 64 + i * 32 + r;
+      const bool rv = lane < 32 && row < rows;
+      uint64_t pm = 0ull;
+      if (rv) pm = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
+      uint64_t mine = 0ull;
+#pragma unroll
+      for (int x = 0; x < 16; ++x) {
+        const uint64_t b0 = __ballot(acc[i][2 * tt][x] >= thr[0]);
+        const uint64_t b1 = __ballot(acc[i][2 * tt + 1][x] >= thr[1]);
+        const uint64_t lo = (b0 & 0xffffffffull) | (b1 << 32);
+        const uint64_t hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
+        const int rr = 8 * (x >> 2) + (x & 3);
+        if (lane == rr) mine = lo;
+        if (lane == rr + 4) mine = hi;
+      }
+      mine &= pm;
+      if (rv) pairs += (unsigned long long)__popcll(pm);
+      if (a.bitmap && rv && pm) atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
+      const uint64_t eb = __ballot(rv && mine != 0ull);
+      if (a.out_dense) {
+        if (rv) a.out_dense[row * a.nt + t] = mine;
+        if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
+      } else if (eb && bshift >= 5) {
+        // the 32 rows (aligned) share one bucket: one reservation per wave
+        const uint32_t slot = (uint32_t)((row0 + wr * 64 + i * 32) >> bshift) * (uint32_t)a.nt + t;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(eb));
+        base = __shfl(base, 0, 64);
+        if (rv && mine) {
+          const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
+          const size_t o = (size_t)slot * a.bcap + pos;
+          a.out_node[o] = (uint32_t)row;
+          a.out_mask[o] = mine;
+        }
+      } else if (eb && rv && mine) {
+        const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
+        const uint32_t pos = atomicAdd(&a.out_count[slot], 1u);
         const size_t o = (size_t)slot * a.bcap + pos;
         a.out_node[o] = (uint32_t)row;
         a.out_mask[o] = mine;
       }
-    } else if (eb && rv && mine) {
-      const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
-      const uint32_t pos = atomicAdd(&a.out_count[slot], 1u);
-      const size_t o = (size_t)slot * a.bcap + pos;
-      a.out_node[o] = (uint32_t)row;
-      a.out_mask[o] = mine;
     }
   }
   if (a.stat_pairs) {
@@ -1195,7 +1201,7 @@ hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {
   if (a.rows < 1 || a.rows > (int64_t(1) << a.level)) return hipErrorInvalidValue;
   if ((a.dp * (fmt == GT_POOL_FP8E4M3 ? 1 : 2)) % kDK != 0) return hipErrorInvalidValue;
   const int64_t rows = a.rows;
-  const int64_t total = ((rows + kDM - 1) / kDM) * ((a.nt + 1) / 2);
+  const int64_t total = ((rows + kDM - 1) / kDM) * ((a.nt + kDTiles - 1) / kDTiles);
   const int64_t grid = 8 * ((total + 7) / 8);
   switch (fmt) {
     case GT_POOL_BF16:
