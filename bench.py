@@ -79,7 +79,8 @@ def main():
     ap.add_argument("--rho", type=float, default=0.9)
     ap.add_argument("--pool", default="bf16", choices=["bf16", "fp8", "f32"])
     ap.add_argument("--side-steps", type=int, default=5)
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=384,
+                    help="queries of the batch the CPU oracle scans (about 10 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
