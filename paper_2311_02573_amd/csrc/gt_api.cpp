@@ -477,7 +477,7 @@ gt_status enqueue_place(Batch* b, int64_t lim, int64_t* ids, float* sims) {
   const unsigned long long hc = (unsigned long long)b->hit_cap, l = (unsigned long long)lim;
   HIPCHK(gt::launch_scatter(b->hits, b->ctr, hc, l, b->offs, b->out_id, b->out_sim, s));
   HIPCHK(gt::launch_sort_segments(b->offs, b->nq, b->out_id, b->out_sim, b->tmp_id, b->tmp_sim,
-                                  ids, sims, b->ctr, hc, l, s));
+                                  ids, sims, b->ctr, hc, l, b->n_epoch, s));
   return GT_OK;
 }
 

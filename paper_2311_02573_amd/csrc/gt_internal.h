@@ -266,7 +266,8 @@ hipError_t launch_scatter(const Hit* hits, const DevCounters* ctr, unsigned long
 hipError_t launch_sort_segments(const int64_t* offs, int nq, uint32_t* id, float* sim,
                                 uint32_t* tmp_id, float* tmp_sim, int64_t* ids_out,
                                 float* sims_out, const DevCounters* ctr,
-                                unsigned long long hit_cap, unsigned long long lim, hipStream_t s);
+                                unsigned long long hit_cap, unsigned long long lim,
+                                int64_t id_bound, hipStream_t s);
 hipError_t launch_exhaustive_gemm(const float* qf, int nq_pad, const float* leaves, int64_t n,
                                   int dp, const float* thr_gemm, const float* nf, uint2* cand,
                                   unsigned long long cand_cap, DevCounters* ctr, int nq,

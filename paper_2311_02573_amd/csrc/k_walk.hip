@@ -650,16 +650,20 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
   // stage pairs, so that both halves of the loop body keep the accumulators
   // in the same registers; an odd last stage follows the loop
   int s = 0;
+  // (the scheduling barriers keep each stage's loads ahead of the matrix
+  // work they are meant to overlap; the compiler would otherwise sink them)
   for (; s + 1 < nst; s += 2) {
     __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS accesses are done
     __builtin_amdgcn_s_barrier();
     dense_lwrite(sl8, R, lds1);
     dense_gload(sl8, s + 2, slast, R);
+    __builtin_amdgcn_sched_barrier(0);
     compute(lds0);
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_s_barrier();
     dense_lwrite(sl8, R, lds0);
     dense_gload(sl8, s + 3, slast, R);
+    __builtin_amdgcn_sched_barrier(0);
     compute(lds1);
   }
   if (s < nst) {
@@ -1035,76 +1039,86 @@ __global__ void k_scatter(const Hit* hits, const DevCounters* ctr, unsigned long
 }
 
 // Sort each query's results by id (ids of one query are distinct).  Up to
-// 512: each thread places its elements by counting the smaller keys; up to
-// 4096: bitonic sort in LDS; larger segments: stable 4-bit LSD radix sort by
-// the same workgroup.
+// 4096 results: a counting sort on the top 8 bits of the id (id >> shift,
+// shift chosen by the host so that every id below the call's epoch has a
+// top part below 256) groups the ids in LDS, then each id is placed at its
+// group's start plus the number of smaller ids in its group.  Larger
+// segments: stable 4-bit LSD radix sort by the same workgroup.
+constexpr int kSortPerThread = 16;  // 4096 / 256
 __global__ __launch_bounds__(256) void k_sort_segments(const int64_t* offs, uint32_t* id,
                                                        float* sim, uint32_t* tmp_id,
                                                        float* tmp_sim, int64_t* ids_out,
                                                        float* sims_out, const DevCounters* ctr,
                                                        unsigned long long hit_cap,
-                                                       unsigned long long lim) {
-  __shared__ __attribute__((aligned(16))) uint32_t key[4096];
+                                                       unsigned long long lim, int shift) {
+  __shared__ uint32_t key[4096];
   __shared__ float val[4096];
   __shared__ uint32_t hist[16 * 256];
-  __shared__ uint32_t tot[256];
+  __shared__ uint32_t tot[257];
   if (!results_fit(ctr, hit_cap, lim)) return;
   const int q = blockIdx.x, t = threadIdx.x;
   const int64_t lo = offs[q], n = offs[q + 1] - lo;
   if (n <= 0) return;
-  if (n <= 512) {
-    // keys padded to a multiple of 4 with the largest value, which is never
-    // below a key, and compared 4 at a time
-    const int n4 = (int)((n + 3) & ~int64_t(3));
-    for (int i = t; i < n4; i += 256) {
-      key[i] = i < n ? id[lo + i] : 0xFFFFFFFFu;
-      val[i] = i < n ? sim[lo + i] : 0.0f;
-    }
-    __syncthreads();
-    const uint4* k4 = reinterpret_cast<const uint4*>(key);
-    for (int i = t; i < n; i += 256) {
-      const uint32_t k = key[i];
-      int r = 0;
-#pragma unroll 4
-      for (int j = 0; j < n4 / 4; ++j) {
-        const uint4 v = k4[j];
-        r += (int)(v.x < k) + (int)(v.y < k) + (int)(v.z < k) + (int)(v.w < k);
-      }
-      ids_out[lo + r] = (int64_t)k;
-      sims_out[lo + r] = val[i];
-    }
-    return;
-  }
   if (n <= 4096) {
-    int P = 1;
-    while (P < n) P <<= 1;
-    for (int i = t; i < P; i += 256) {
-      key[i] = i < n ? id[lo + i] : 0xFFFFFFFFu;
-      val[i] = i < n ? sim[lo + i] : 0.0f;
-    }
+    const int ni = (int)n;
+    tot[t] = 0u;
+    if (t == 0) tot[256] = 0u;
     __syncthreads();
-    for (int k = 2; k <= P; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = t; i < P; i += 256) {
-          const int ixj = i ^ j;
-          if (ixj > i) {
-            const bool asc = (i & k) == 0;
-            const uint32_t ki = key[i], kj = key[ixj];
-            if ((ki > kj) == asc) {
-              key[i] = kj;
-              key[ixj] = ki;
-              const float v = val[i];
-              val[i] = val[ixj];
-              val[ixj] = v;
-            }
-          }
-        }
-        __syncthreads();
+    uint32_t k[kSortPerThread], g[kSortPerThread], r[kSortPerThread];
+    float v[kSortPerThread];
+#pragma unroll
+    for (int e = 0; e < kSortPerThread; ++e) {
+      const int i = t + 256 * e;
+      if (i < ni) {
+        k[e] = id[lo + i];
+        v[e] = sim[lo + i];
+        const uint32_t gg = k[e] >> shift;
+        g[e] = gg < 255u ? gg : 255u;
+        r[e] = atomicAdd(&tot[g[e]], 1u);
       }
     }
-    for (int i = t; i < n; i += 256) {
-      ids_out[lo + i] = (int64_t)key[i];
-      sims_out[lo + i] = val[i];
+    __syncthreads();
+    if (t < 64) {  // exclusive prefix of the 256 group sizes, four per lane
+      uint32_t c[4], sum = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[j] = tot[4 * t + j];
+        sum += c[j];
+      }
+      uint32_t incl = sum;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t x = __shfl_up(incl, o, 64);
+        if (t >= o) incl += x;
+      }
+      uint32_t run = incl - sum;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        hist[4 * t + j] = run;
+        run += c[j];
+      }
+      if (t == 63) hist[256] = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kSortPerThread; ++e) {
+      const int i = t + 256 * e;
+      if (i < ni) {
+        key[hist[g[e]] + r[e]] = k[e];
+        val[hist[g[e]] + r[e]] = v[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < kSortPerThread; ++e) {
+      const int i = t + 256 * e;
+      if (i < ni) {
+        const uint32_t b0 = hist[g[e]], b1 = hist[g[e] + 1];
+        uint32_t pos = b0;
+        for (uint32_t j = b0; j < b1; ++j) pos += key[j] < k[e];
+        ids_out[lo + pos] = (int64_t)k[e];
+        sims_out[lo + pos] = v[e];
+      }
     }
     return;
   }
@@ -1252,10 +1266,15 @@ hipError_t launch_scatter(const Hit* hits, const DevCounters* ctr, unsigned long
 hipError_t launch_sort_segments(const int64_t* offs, int nq, uint32_t* id, float* sim,
                                 uint32_t* tmp_id, float* tmp_sim, int64_t* ids_out,
                                 float* sims_out, const DevCounters* ctr,
-                                unsigned long long hit_cap, unsigned long long lim, hipStream_t s) {
+                                unsigned long long hit_cap, unsigned long long lim,
+                                int64_t id_bound, hipStream_t s) {
   if (nq <= 0) return hipSuccess;
+  // top 8 bits of the ids below id_bound
+  int bits = 0;
+  while (bits < 32 && (int64_t(1) << bits) < id_bound) ++bits;
+  const int shift = bits > 8 ? bits - 8 : 0;
   hipLaunchKernelGGL(k_sort_segments, dim3(nq), dim3(256), 0, s, offs, id, sim, tmp_id, tmp_sim,
-                     ids_out, sims_out, ctr, hit_cap, lim);
+                     ids_out, sims_out, ctr, hit_cap, lim, shift);
   return hipGetLastError();
 }
 
