@@ -91,6 +91,11 @@ def main():
                     help="also time the walk for several dense/sparse split levels")
     ap.add_argument("--dense-last", type=int, default=-2,
                     help="last level walked with dense steps (-2: automatic, -1: none)")
+    ap.add_argument("--walk-subtract", type=int, default=-1,
+                    help="subtraction step of the bfloat16 walk: 0 off, 1 every sparse level, "
+                         "2 all but the last, -1 automatic")
+    ap.add_argument("--sweep-subtract", action="store_true",
+                    help="also time the walk with each subtraction setting")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of each loaded serving run (0: no serving leg)")
     args = ap.parse_args()
@@ -126,6 +131,7 @@ def main():
     torch.cuda.empty_cache()
     if args.dense_last != -2:
         idx.set_option("dense_last", args.dense_last)
+    idx.set_option("walk_subtract", args.walk_subtract)
 
     def run(pool, steps, warmup):
         fn = (lambda: idx.exhaustive(q, args.rho)) if pool == "exh" else \
@@ -259,6 +265,26 @@ def main():
         idx.set_option("dense_last", args.dense_last)
         log(f"dense_last sweep (ms/batch): {sweep}")
 
+    sub_sweep = None
+    if args.sweep_subtract:
+        sub_sweep = {}
+        for ws in (0, 1, 2):
+            idx.set_option("walk_subtract", ws)
+            _, wl, _ = run(args.pool, 5, 1)
+            idx.set_option("profile", 1)
+            ps = []
+            for _ in range(3):
+                idx.query(q, args.rho, pool=args.pool)
+                ps.append(idx.stats())
+            idx.set_option("profile", 0)
+            sub_sweep[ws] = {"ms_batch": round(wl / 5 * 1e3, 3),
+                             **{k: round(float(np.median([p[k] for p in ps])), 4)
+                                for k in ("ms_dense", "ms_frontier", "ms_leaf", "ms_total")},
+                             "leaf_pairs": ps[-1]["leaf_pairs"],
+                             "tests_per_level": list(ps[-1]["pairs"])}
+        idx.set_option("walk_subtract", args.walk_subtract)
+        log(f"walk_subtract sweep: {sub_sweep}")
+
     # ---- comparators and recall against the exhaustive GEMM
     comparators = {}
     exh = None
@@ -340,6 +366,8 @@ def main():
     }
     if sweep is not None:
         out["dense_last_sweep_ms"] = sweep
+    if sub_sweep is not None:
+        out["walk_subtract_sweep"] = sub_sweep
     idx.close()
     del idx, q
     torch.cuda.empty_cache()

@@ -155,6 +155,7 @@ void free_query_arrays(Batch* b) {
   dfree(ix, &b->rho, o);
   dfree(ix, &b->thr, o);
   dfree(ix, &b->thr_gemm, o);
+  dfree(ix, &b->sabs, o);
   dfree(ix, &b->qcount, o);
   dfree(ix, &b->offs, o + 1);
   if (b->h_rho) (void)hipHostFree(b->h_rho);
@@ -166,8 +167,10 @@ void free_frontier(Batch* b) {
   for (int k = 0; k < 2; ++k) {
     dfree(b->ix, &b->fr_node[k], (size_t)b->nt_alloc * b->fr_cap);
     dfree(b->ix, &b->fr_mask[k], (size_t)b->nt_alloc * b->fr_cap);
+    dfree(b->ix, &b->fr_rec[k], (size_t)b->rec_len * 64);
   }
   b->nt_alloc = 0;
+  b->rec_len = 0;
 }
 
 void free_batch(Batch* b) {
@@ -245,6 +248,7 @@ gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
     TRY(dalloc(ix, &b->rho, nqa));
     TRY(dalloc(ix, &b->thr, nqa));
     TRY(dalloc(ix, &b->thr_gemm, nqa));
+    TRY(dalloc(ix, &b->sabs, nqa));
     TRY(dalloc(ix, &b->qcount, nqa));
     TRY(dalloc(ix, &b->offs, nqa + 1));
     HIPCHK(hipHostMalloc((void**)&b->h_rho, nqa * sizeof(double), hipHostMallocDefault));
@@ -343,6 +347,23 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   uint32_t* bitmap = b->counted ? b->bitmap : nullptr;
   b->frontier_launches = 0;
   b->dense_launches = 0;
+  // Subtraction step (bfloat16 pools, score records from a dense step):
+  // sparse levels sub_from .. sub_to read only the right children.
+  const int ws = ix->walk_subtract < 0 ? 1 : ix->walk_subtract;
+  const bool sub = f == GT_POOL_BF16 && dl >= 0 && ws > 0 && dl <= D - 2;
+  const int sub_to = !sub ? -1 : (ws == 2 ? D - 3 : D - 2);
+  if (sub && sub_to >= dl) {
+    const int64_t need = (int64_t)nt * b->fr_cap;
+    if (need > b->rec_len) {
+      dfree(ix, &b->fr_rec[0], (size_t)b->rec_len * 64);
+      dfree(ix, &b->fr_rec[1], (size_t)b->rec_len * 64);
+      b->rec_len = 0;
+      TRY(dalloc(ix, &b->fr_rec[0], (size_t)need * 64));
+      TRY(dalloc(ix, &b->fr_rec[1], (size_t)need * 64));
+      b->rec_len = need;
+    }
+  }
+  const bool use_rec = sub && sub_to >= dl;
   if (dl >= 0) {
     const size_t need = ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt;
     if ((int64_t)need > b->dmask_len) {
@@ -378,6 +399,7 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
       a.stat_pairs = &b->ctr->pairs[L];
       a.bitmap = bitmap;
       a.bit_base = level_row(L);
+      a.out_rec = (use_rec && L == dl) ? b->fr_rec[L & 1] : nullptr;
       ev_launch_begin(b);
       HIPCHK(gt::launch_dense_level(f, a, s));
       ev_launch_end(b, true);
@@ -409,7 +431,16 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
     a.bitmap = bitmap;
     a.bit_base = level_row(l + 1);
     ev_launch_begin(b);
-    HIPCHK(gt::launch_walk_level(f, a, grid, s));
+    if (use_rec && l <= sub_to) {
+      a.in_rec = b->fr_rec[l & 1];
+      a.out_rec = l + 1 <= sub_to ? b->fr_rec[(l + 1) & 1] : nullptr;
+      a.sabs = b->sabs;
+      a.n_epoch = b->n_epoch;
+      a.depth = D;
+      HIPCHK(gt::launch_walk_sub(a, grid, s));
+    } else {
+      HIPCHK(gt::launch_walk_level(f, a, grid, s));
+    }
     ev_launch_end(b, false);
     b->frontier_launches++;
   }
@@ -602,7 +633,8 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
     HIPCHK(hipMemcpyAsync(b->rho, b->h_rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
     HIPCHK(gt::launch_query_prep(q, nq, ix->d, ix->dp, tq, b->rho, ix->d_mmin, b->qf, b->qbf,
                                  b->q8, b->qexp, b->invn_q, b->qq, b->thr, b->thr_gemm,
-                                 b->tile_mask, &b->ctr->err, nq_pad, s));
+                                 b->tile_mask, ix->master + level_row(0) * ix->dp, b->sabs,
+                                 &b->ctr->err, nq_pad, s));
   }
   ev_mark(b, 1);
   if (nq > 0 && ix->n > 0) {
@@ -1074,6 +1106,9 @@ gt_status gt_set_option(gt_index* ix, const char* key, int64_t value) {
   } else if (!strcmp(key, "dense_last")) {
     if (value < -2 || value > ix->depth - 1) return fail(GT_ERR_INVALID_ARG, "dense_last out of range");
     ix->dense_last = (int)value;
+  } else if (!strcmp(key, "walk_subtract")) {
+    if (value < -1 || value > 2) return fail(GT_ERR_INVALID_ARG, "walk_subtract out of range");
+    ix->walk_subtract = (int)value;
   } else if (!strcmp(key, "count_unique")) {
     ix->count_unique = value != 0;
   } else if (!strcmp(key, "grid")) {

@@ -80,6 +80,13 @@ struct WalkLevelArgs {
   unsigned long long* stat_pairs;
   uint32_t* bitmap;         // optional: one bit per tree row read
   int64_t bit_base;         // tree row of node 0 of level+1
+  // subtraction step (bfloat16 pools): per entry, 64 bfloat16 upper bounds of
+  // the pool's score for the tile's queries (entries' live queries only)
+  const uint16_t* in_rec;   // [slots * bcap * 64], parallel to in_node
+  uint16_t* out_rec;        // [slots * bcap * 64], parallel to out_node
+  const float* sabs;        // [nt * TQ] absolute term of the lower bound
+  int64_t n_epoch;          // rows visible to the call
+  int depth;                // leaves are at this level
 };
 
 // Arguments of a dense level step (children at `level`, all 2^level pools).
@@ -102,6 +109,7 @@ struct DenseLevelArgs {
   unsigned long long* stat_pairs;
   uint32_t* bitmap;
   int64_t bit_base;
+  uint16_t* out_rec;        // score records of the sparse output, or NULL
 };
 
 struct LeafArgs {
@@ -140,7 +148,10 @@ struct Batch {
   int nq_alloc = 0;
   uint32_t* fr_node[2] = {nullptr, nullptr};
   uint64_t* fr_mask[2] = {nullptr, nullptr};
+  uint16_t* fr_rec[2] = {nullptr, nullptr};  // score records (64 per entry)
+  float* sabs = nullptr;                     // [nq_pad] lower-bound absolute terms
   int64_t fr_cap = 0;        // entries per tile per buffer
+  int64_t rec_len = 0;       // entries of each fr_rec buffer
   uint32_t* lvl_count = nullptr;    // [GT_MAX_LEVELS x kMaxSlots]
   uint64_t* tile_mask = nullptr;    // [kMaxTiles]
   float* qf = nullptr;       // [nq_pad x dp]
@@ -214,6 +225,8 @@ struct Index {
   int head_level = -1;       // -1: automatic
   int grid = 0;              // 0: one workgroup per CU
   int dense_last = -2;       // last level walked densely (-2: automatic, -1: none)
+  int walk_subtract = -1;    // subtraction step (bfloat16 after a dense step): 0 off,
+                             // 1 every sparse level, 2 all but the last, -1 automatic
   bool profile = false;
   bool count_unique = false;
   double m_min = 0.0;        // host copy
@@ -250,8 +263,10 @@ hipError_t launch_quant_fp8(const float* src, uint8_t* dst, int64_t count, int l
 hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, const double* rho,
                              const double* mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
                              float* invn_q, double* qq, float* thr, float* thr_gemm,
-                             uint64_t* tile_mask, unsigned int* err, int nq_pad, hipStream_t s);
+                             uint64_t* tile_mask, const float* root, float* sabs,
+                             unsigned int* err, int nq_pad, hipStream_t s);
 hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s);
+hipError_t launch_walk_sub(const WalkLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s);
 hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s);
 hipError_t launch_recheck(Hit* hits, const uint32_t* band_idx, const unsigned long long* nband,

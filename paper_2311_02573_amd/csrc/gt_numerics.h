@@ -76,6 +76,56 @@ __host__ __device__ __forceinline__ double pool_slack(int K) {
   return (double)(K + 2) * 0x1p-22;
 }
 
+// Score bounds of the subtraction step (paper Sec. 2 and Alg. 1: the score of
+// one half of a pool is the pool's score minus the other half's).  A pool of
+// level l holds exactly the members of its two children, so for the real
+// scores  q.S_left = q.S_pool - q.S_right.  With an upper bound on q.S_pool
+// and a lower bound on q.S_right this bounds the left child from above
+// without reading it.  A score s is computed by the matrix cores from
+// operands rounded up to bfloat16 (values below 2^-126 raised to 2^-126),
+// K <= 4096 products accumulated in float32; the real score q.S uses the
+// float32 query and rows.
+//  * Upper bound: the rounded-up operands give an exact dot product P >= q.S
+//    (all terms >= 0).  Products below 2^-126 may be flushed (each loses less
+//    than 2^-126) and the accumulation loses less than (K+1) ulps relative
+//    (section on pool slack), so P <= (s + K 2^-126) / (1 - (K+1) 2^-23)
+//    <= 1.000489 s + K 2^-126 (1 + 2^-10).  score_upper computes
+//    s * 1.0006 + K 2^-125 with one rounding to nearest (2^-24 relative,
+//    2^-149 absolute at most), which stays above that.
+//  * Lower bound: each stored operand is at most (1 + 2^-7) times the real
+//    one plus 2^-126, the master sums exceed the real sums by their upward
+//    roundings over at most 40 levels (factor 1 + 40 2^-23), and the
+//    accumulation rounds up by less than (K+1) ulps; so
+//      q.S >= s / ((1 + (K+1) 2^-23) (1 + 2^-7)^2 (1 + 40 2^-23)) - A
+//          >= 0.984071 s - A,
+//    A = 2^-126 (c |S|_1 + c |q|_1 + K 2^-126), c < 1.01.  The query
+//    preparation gives a = 2 A + 2^-126 (with |S|_1 <= |root|_1), and
+//    score_lower computes s * 0.9839 - a with one rounding to nearest, which
+//    stays below 0.984071 s - A; a negative value is replaced by 0.
+//  * The difference of the two is rounded up explicitly (diff_upper).
+constexpr float kScoreUp = 1.0006f;
+constexpr float kScoreLow = 0.9839f;
+__device__ __forceinline__ float score_abs_up(int K) { return (float)K * 0x1p-125f; }
+__device__ __forceinline__ float score_upper(float s, float abs_up) {
+  return __fmaf_rn(s, kScoreUp, abs_up);
+}
+__device__ __forceinline__ float score_lower(float s, float a) {
+  return fmaxf(__fmaf_rn(s, kScoreLow, -a), 0.0f);
+}
+// Upper bound of u - l for u >= 0 (or +infinity) and finite l >= 0, at least
+// 0: the nearest difference, moved up by one float when it is positive.
+__device__ __forceinline__ float diff_upper(float u, float l) {
+  const float d = __fsub_rn(u, l);
+  return d > 0.0f ? (d < INFINITY ? __uint_as_float(__float_as_uint(d) + 1u) : d) : 0.0f;
+}
+// Least bfloat16 >= x for x >= 0 or +infinity, subnormals kept (bounds are
+// only used in float32 arithmetic, never as matrix-core operands), as the
+// high half of a 32-bit word.
+__device__ __forceinline__ uint32_t bf16_ceil_hi(float x) {
+  return (__float_as_uint(x) + 0xFFFFu) & 0xFFFF0000u;
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 // In-lane part of a fixed-order float32 dot product of two rows, wave-wide
 // (64 lanes).  In chunk c (1024 elements), lane l owns the 16 elements
 //   c*1024 + 256 v + 4 l + j      (v, j = 0..3),

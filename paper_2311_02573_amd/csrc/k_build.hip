@@ -132,9 +132,10 @@ __global__ __launch_bounds__(256) void k_query_prep(
     const float* __restrict__ q, int nq, int d, int dp, int tq, const double* __restrict__ rho,
     const double* __restrict__ mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
     float* invn_q, double* qq_out, float* thr, float* thr_gemm, uint64_t* tile_mask,
-    unsigned int* err) {
+    const float* __restrict__ root, float* sabs, unsigned int* err) {
   __shared__ float qs[4096];
   __shared__ float red[4];
+  __shared__ double l1red[4];
   __shared__ double qq_s;
   const int b = blockIdx.x, t = threadIdx.x;
   const bool real = b < nq;
@@ -147,8 +148,17 @@ __global__ __launch_bounds__(256) void k_query_prep(
     mx = fmaxf(mx, v);
   }
   if (bad) atomicOr(err, 1u);
+  // |q|_1 + |root pool|_1 (any order: only an upper bound is needed)
+  double l1 = 0.0;
+  for (int k = t; k < d; k += blockDim.x) l1 += (double)qs[k];
+  if (root)
+    for (int k = t; k < dp; k += blockDim.x) l1 += (double)root[k];
   for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-  if ((t & 63) == 0) red[t >> 6] = mx;
+  for (int o = 32; o >= 1; o >>= 1) l1 += __shfl_xor(l1, o, 64);
+  if ((t & 63) == 0) {
+    red[t >> 6] = mx;
+    l1red[t >> 6] = l1;
+  }
   __syncthreads();
   if (t == 0) {
     double acc = 0.0;
@@ -199,6 +209,15 @@ __global__ __launch_bounds__(256) void k_query_prep(
     }
     thr[b] = th;
     thr_gemm[b] = tg;
+    if (sabs) {
+      // absolute term of the subtraction step's lower bound: 2^-125 (|S|_1 +
+      // |q|_1 + dp 2^-126) + 2^-126, a normal float32 rounded up
+      const double l1s = (l1red[0] + l1red[1]) + (l1red[2] + l1red[3]);
+      const double v = ldexp(1.01 * l1s + (double)dp * 0x1p-126, -125) + 0x1p-126;
+      float f = (float)v;
+      if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+      sabs[b] = f;
+    }
   }
 }
 
@@ -260,10 +279,11 @@ hipError_t launch_quant_fp8(const float* src, uint8_t* dst, int64_t count, int l
 hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, const double* rho,
                              const double* mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
                              float* invn_q, double* qq, float* thr, float* thr_gemm,
-                             uint64_t* tile_mask, unsigned int* err, int nq_pad, hipStream_t s) {
+                             uint64_t* tile_mask, const float* root, float* sabs,
+                             unsigned int* err, int nq_pad, hipStream_t s) {
   if (nq_pad <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_query_prep, dim3(nq_pad), dim3(256), 0, s, q, nq, d, dp, tq, rho, mmin, qf,
-                     qbf, q8, qexp, invn_q, qq, thr, thr_gemm, tile_mask, err);
+                     qbf, q8, qexp, invn_q, qq, thr, thr_gemm, tile_mask, root, sabs, err);
   return hipGetLastError();
 }
 

@@ -477,6 +477,343 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
   }
 }
 
+// Level step with subtraction (bfloat16 pools; paper Sec. 2 and Alg. 1 derive
+// the score of one half of a pool from the pool's score and the other half's).
+// Every entry carries a score record: upper bounds of its pool's real score
+// for all 64 queries of the tile, as bfloat16, query q at 4 (q % 16) + q / 16
+// (so that a lane's four values of a pool are eight contiguous bytes).  A
+// wave takes 32 entries and reads only their right children (one row each):
+// the right child's score s is computed with the matrix cores and tested as
+// in k_walk_level; the left child's real score is at most
+//   U = diff_upper(sp, score_lower(s, a_b))
+// (sp the entry's record, a_b the query's absolute term), and the left child
+// is kept for query b iff U >= tau'_b.  Where the right child holds rows at
+// or beyond the call's epoch (which later inserts may have grown), U is just
+// sp: a part of a pool never scores above the pool.  Every kept child gets a
+// complete record (score_upper(s) for the right child, U for the left, each
+// rounded up to bfloat16), so the values of queries that are not live are
+// bounds too.  Halves the pool rows read per level.
+constexpr int kSubGroup = 32;  // entries per wave step
+constexpr int kSubPipe = 4;   // 64-byte steps of a lane's two rows fetched ahead
+
+template <int NSTEPS, int PIPE>
+__global__ __launch_bounds__(kWalkThreads, 1) void k_walk_sub(WalkLevelArgs a) {
+  constexpr int FMT = GT_POOL_BF16;
+  using F = WalkFmt<FMT>;
+  constexpr int TQ = F::TQ;
+  constexpr int NQB = TQ / 16;
+  static_assert(TQ == 64, "records hold 64 queries");
+  __shared__ __attribute__((aligned(16))) unsigned char qlds[TQ * (F::MAXDP * F::ESZ + 16)];
+  __shared__ uint32_t gpre[kMaxBucketsPerXcd + 1];
+  __shared__ uint32_t glo[kMaxBucketsPerXcd], ghi[kMaxBucketsPerXcd];
+  __shared__ float thr_lds[TQ], sabs_lds[TQ];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int rowbytes = a.dp * F::ESZ;
+  const int rs = rowbytes + 16;
+  const int nsteps = NSTEPS > 0 ? NSTEPS : rowbytes / 64;
+  const int c16 = lane & 15, g4 = lane >> 4;
+  const int e32 = lane & 31;  // the entry this lane fetches (lanes 32-63 repeat 0-31)
+
+  const int nbk = 1 << a.nb;
+  const int xs = nbk < kXcds ? nbk : kXcds;
+  const int R = nbk / xs;
+  const int x = blockIdx.x % kXcds;
+  const int W = gridDim.x / kXcds, j = blockIdx.x / kXcds;
+  if (x >= xs) return;
+  int t0, tstep, m, c;
+  if (a.nt <= W) {
+    t0 = j % a.nt;
+    tstep = a.nt;
+    m = j / a.nt;
+    c = (W - 1 - t0) / a.nt + 1;
+  } else {
+    t0 = j;
+    tstep = W;
+    m = 0;
+    c = 1;
+  }
+  // right child 2p+1 of a level-l pool p covers leaves [(2p+1) 2^s, (2p+2) 2^s)
+  const int lshift = a.depth - a.level - 1;
+  // subtraction is used where the right child lies wholly below the epoch:
+  // then the parent and both children hold only rows the call sees, none of
+  // which an insert changes
+  auto sub_ok = [&](uint32_t ep) {
+    return ((uint64_t)(2u * ep + 2u) << lshift) <= (uint64_t)a.n_epoch;
+  };
+  // upper bound of the left child's score from the pool's bound sp and the
+  // right child's computed score sr (a right score that overflowed gives no
+  // lower bound)
+  auto left_ub = [&](float sp, float sr, float sa, bool sub) {
+    if (!sub || !(sr < INFINITY)) return sp;
+    return diff_upper(sp, score_lower(sr, sa));
+  };
+  const float aup = score_abs_up(a.dp);
+  unsigned long long pairs = 0;
+
+  for (int t = t0; t < a.nt; t += tstep) {
+    const uint64_t tmask = a.tile_mask[t];
+    __syncthreads();
+    if (wave == 0) {
+      uint32_t ng = 0, lo = 0, hi = 0;
+      if (lane < R && tmask) {
+        const uint32_t n = a.in_count[(size_t)(x * R + lane) * a.nt + t];
+        lo = (uint32_t)(((uint64_t)n * m) / c);
+        hi = (uint32_t)(((uint64_t)n * (m + 1)) / c);
+        ng = (hi - lo + kSubGroup - 1) / kSubGroup;
+      }
+      uint32_t incl = ng;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+      }
+      if (lane < R) {
+        gpre[lane] = incl - ng;
+        glo[lane] = lo;
+        ghi[lane] = hi;
+      }
+      if (lane == 63) gpre[R] = incl;
+    }
+    __syncthreads();
+    const uint32_t gtot = gpre[R];
+    if (gtot == 0) continue;
+    {
+      const unsigned char* src =
+          reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)t * TQ * rowbytes;
+      const int vec_per_row = rowbytes / 16;
+      const int nvec = TQ * vec_per_row;
+      for (int v0 = 0; v0 < nvec; v0 += 8 * kWalkThreads) {
+        uint4 buf[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int v = v0 + k * kWalkThreads + tid;
+          const int vv = v < nvec ? v : nvec - 1;
+          const int row = vv / vec_per_row, col = vv - row * vec_per_row;
+          buf[k] = *reinterpret_cast<const uint4*>(src + (size_t)row * rowbytes + col * 16);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int v = v0 + k * kWalkThreads + tid;
+          if (v < nvec) {
+            const int row = v / vec_per_row, col = v - row * vec_per_row;
+            *reinterpret_cast<uint4*>(qlds + row * rs + col * 16) = buf[k];
+          }
+        }
+      }
+    }
+    if (tid < TQ) {
+      thr_lds[tid] = a.thr[t * TQ + tid];
+      sabs_lds[tid] = a.sabs[t * TQ + tid];
+    }
+    __syncthreads();
+
+    // entry e32 of group gg: its pool, mask and position (padding lanes take
+    // the group's first entry with an empty mask, so every load is valid)
+    auto fetch = [&](uint32_t gg, uint32_t& p, uint64_t& pm, uint32_t& pos, uint32_t& slot) {
+      const int r = find_slot(gpre, R, gg);
+      const uint32_t ef = glo[r] + (gg - gpre[r]) * kSubGroup;
+      const uint32_t e = ef + (uint32_t)e32;
+      const uint32_t hi = ghi[r];
+      slot = (uint32_t)(x * R + r) * (uint32_t)a.nt + (uint32_t)t;
+      const uint32_t ie = e < hi ? e : ef;
+      pos = (uint32_t)((size_t)slot * a.bcap + ie);
+      p = a.in_node[pos];
+      const uint64_t lm = a.in_mask[pos];
+      pm = e < hi ? lm : 0ull;
+    };
+    // The right-child rows this lane loads: lanes 4R' .. 4R'+3 take 64
+    // contiguous bytes of entry R' (block 0) and entry 16 + R' (block 1).
+    auto rows_of = [&](uint32_t p, const unsigned char*& r0, const unsigned char*& r1) {
+      const uint32_t q0 = (uint32_t)__shfl((int)p, lane >> 2, 64);
+      const uint32_t q1 = (uint32_t)__shfl((int)p, 16 + (lane >> 2), 64);
+      const unsigned char* base = reinterpret_cast<const unsigned char*>(a.child_rows) + 16 * (lane & 3);
+      r0 = base + (size_t)(2u * q0 + 1u) * rowbytes;
+      r1 = base + (size_t)(2u * q1 + 1u) * rowbytes;
+    };
+    const int bp_addr = 4 * (4 * c16 + g4);
+    auto to_mfma = [&](const uint4& v) {
+      uint4 r;
+      r.x = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.x);
+      r.y = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.y);
+      r.z = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.z);
+      r.w = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.w);
+      return r;
+    };
+    const int slast = nsteps - 1;
+    uint4 bA0[PIPE], bA1[PIPE], bB0[PIPE], bB1[PIPE];
+    uint32_t np = 0, npos = 0, nslot = 0;
+    uint64_t npm = 0ull;
+    if ((uint32_t)wave < gtot) {
+      fetch(wave, np, npm, npos, nslot);
+      const unsigned char *r0, *r1;
+      rows_of(np, r0, r1);
+#pragma unroll
+      for (int u = 0; u < PIPE; ++u) {
+        const int st = u < slast ? u : slast;
+        bA0[u] = ld_global16(r0 + 64 * st);
+        bA1[u] = ld_global16(r1 + 64 * st);
+      }
+    }
+
+    for (uint32_t gg = wave; gg < gtot; gg += nwaves) {
+      const uint32_t p = np, pos = npos, slot = nslot;
+      const uint64_t pm = npm;
+      const unsigned char *arow0, *arow1;
+      rows_of(p, arow0, arow1);
+      const unsigned char* brow = qlds + c16 * rs + 16 * g4;
+      // the pools' score records, read while the rows are multiplied: for
+      // entry 16 rb + 4 (l / 16) + i the bounds of queries c, 16 + c, 32 + c,
+      // 48 + c (c = l % 16), eight contiguous bytes
+      uint2 prec[2][4];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const uint32_t eps = (uint32_t)__shfl((int)pos, 16 * rb + 4 * g4 + i, 64);
+          prec[rb][i] = *reinterpret_cast<const uint2*>(a.in_rec + (size_t)eps * TQ + 4 * c16);
+        }
+      const bool has_next = gg + nwaves < gtot;
+      fetch(has_next ? gg + nwaves : gg, np, npm, npos, nslot);
+      if (a.bitmap && lane < 32 && pm) {
+        const uint64_t row = (uint64_t)a.bit_base + 2u * p + 1u;
+        atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
+      }
+
+      f32x4 acc[2][NQB];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int qb = 0; qb < NQB; ++qb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[rb][qb][i] = 0.0f;
+      auto step = [&](const uint4& l0, const uint4& l1, int s) {
+        const uint4 x0 = to_mfma(l0), x1 = to_mfma(l1);
+#pragma unroll
+        for (int qb = 0; qb < NQB; ++qb) {
+          const uint4 bq = ld_lds16(brow + qb * 16 * rs + 64 * s);
+          mma16x16<FMT>(x0, bq, acc[0][qb]);
+          mma16x16<FMT>(x1, bq, acc[1][qb]);
+        }
+      };
+#pragma unroll
+      for (int s0 = 0; s0 < nsteps; s0 += 2 * PIPE) {
+#pragma unroll
+        for (int u = 0; u < PIPE; ++u) {
+          const int st = s0 + PIPE + u < slast ? s0 + PIPE + u : slast;
+          bB0[u] = ld_global16(arow0 + 64 * st);
+          bB1[u] = ld_global16(arow1 + 64 * st);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PIPE; ++u)
+          if (s0 + u < nsteps) step(bA0[u], bA1[u], s0 + u);
+        __builtin_amdgcn_sched_barrier(0);
+        {
+          const bool same = s0 + 2 * PIPE < nsteps;
+          const unsigned char *r0 = arow0, *r1 = arow1;
+          if (!same) rows_of(np, r0, r1);
+          const int sf = same ? s0 + 2 * PIPE : 0;
+#pragma unroll
+          for (int u = 0; u < PIPE; ++u) {
+            const int st = sf + u < slast ? sf + u : slast;
+            bA0[u] = ld_global16(r0 + 64 * st);
+            bA1[u] = ld_global16(r1 + 64 * st);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < PIPE; ++u)
+          if (s0 + PIPE + u < nsteps) step(bB0[u], bB1[u], s0 + PIPE + u);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+
+      // Element (rb, qb, i) of lane l: entry 16 rb + 4 (l / 16) + i of the
+      // group, query 16 qb + l % 16.  Decisions are gathered per entry by
+      // ballots (lane j < 32 ends with entry j's masks, as in k_walk_level);
+      // then every kept child gets its complete record.
+      auto rec_of = [&](int rb, int i, int qb) {
+        const uint32_t w = qb < 2 ? prec[rb][i].x : prec[rb][i].y;
+        return bf16_to_f32((uint16_t)((qb & 1) ? (w >> 16) : (w & 0xFFFFu)));
+      };
+      const int gsel = 16 * ((lane & 15) >> 2);
+      uint64_t mine_r = 0ull, mine_l = 0ull;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int er = 16 * rb + 4 * g4 + i;
+          const uint64_t em = __shfl(pm, er, 64);
+          const bool sub = sub_ok((uint32_t)__shfl((int)p, er, 64));
+          uint64_t part_r = 0ull, part_l = 0ull;
+#pragma unroll
+          for (int qb = 0; qb < NQB; ++qb) {
+            const int q = 16 * qb + c16;
+            const bool live = (em >> q) & 1ull;
+            const float sr = acc[rb][qb][i];
+            const float th = thr_lds[q];
+            const uint64_t br = __ballot(live && sr >= th);
+            const uint64_t bl = __ballot(live && left_ub(rec_of(rb, i, qb), sr, sabs_lds[q], sub) >= th);
+            part_r |= ((br >> gsel) & 0xffffull) << (16 * qb);
+            part_l |= ((bl >> gsel) & 0xffffull) << (16 * qb);
+          }
+          if ((lane >> 4) == rb && (lane & 3) == i) {
+            mine_r = part_r;
+            mine_l = part_l;
+          }
+        }
+      // outputs: lane j < 32 the right child of entry j, lane 32 + j its left
+      // (the shuffle runs in every lane: a lane that is switched off gives
+      // no data to the others)
+      const uint64_t left_m = __shfl(mine_l, e32, 64);
+      const uint64_t out_m = lane < 32 ? mine_r : left_m;
+      if (lane < 32) pairs += 2ull * (unsigned long long)__popcll(pm);
+      const uint64_t bal = __ballot(out_m != 0ull);
+      if (bal == 0ull) continue;
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(bal));
+      base = __shfl(base, 0, 64);
+      const uint32_t opos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+      if (out_m) {
+        const size_t o = (size_t)slot * a.bcap + opos;
+        a.out_node[o] = 2u * p + (lane < 32 ? 1u : 0u);
+        a.out_mask[o] = out_m;
+      }
+      if (!a.out_rec) continue;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int er = 16 * rb + 4 * g4 + i;
+          const bool sub = sub_ok((uint32_t)__shfl((int)p, er, 64));
+          const bool keep_r = ((bal >> er) & 1ull) != 0ull;
+          const bool keep_l = ((bal >> (32 + er)) & 1ull) != 0ull;
+          const uint32_t or_ = (uint32_t)__shfl((int)opos, er, 64);
+          const uint32_t ol_ = (uint32_t)__shfl((int)opos, 32 + er, 64);
+          uint32_t vr[NQB], vl[NQB];
+#pragma unroll
+          for (int qb = 0; qb < NQB; ++qb) {
+            const int q = 16 * qb + c16;
+            const float sr = acc[rb][qb][i];
+            vr[qb] = bf16_ceil_hi(score_upper(sr, aup));
+            vl[qb] = bf16_ceil_hi(left_ub(rec_of(rb, i, qb), sr, sabs_lds[q], sub));
+          }
+          if (keep_r)
+            *reinterpret_cast<uint2*>(a.out_rec + ((size_t)slot * a.bcap + or_) * TQ + 4 * c16) =
+                make_uint2((vr[0] >> 16) | vr[1], (vr[2] >> 16) | vr[3]);
+          if (keep_l)
+            *reinterpret_cast<uint2*>(a.out_rec + ((size_t)slot * a.bcap + ol_) * TQ + 4 * c16) =
+                make_uint2((vl[0] >> 16) | vl[1], (vl[2] >> 16) | vl[3]);
+        }
+    }
+  }
+  if (a.stat_pairs) {
+    for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
+    if (lane == 0 && pairs) atomicAdd(a.stat_pairs, pairs);
+  }
+}
+
 // Dense level step: every pool of a level against every query, as a matrix
 // product with a masked epilogue.  Used where almost every (pool, query tile)
 // pair is live (the first tested level): each pool row is read once per
@@ -707,6 +1044,7 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
       if (rv) pairs += (unsigned long long)__popcll(pm);
       if (a.bitmap && rv && pm) atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
       const uint64_t eb = __ballot(rv && mine != 0ull);
+      int64_t oe = -1;  // output entry of this lane's row
       if (a.out_dense) {
         if (rv) a.out_dense[row * a.nt + t] = mine;
         if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
@@ -721,6 +1059,7 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
           const size_t o = (size_t)slot * a.bcap + pos;
           a.out_node[o] = (uint32_t)row;
           a.out_mask[o] = mine;
+          oe = (int64_t)o;
         }
       } else if (eb && rv && mine) {
         const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
@@ -728,6 +1067,39 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
         const size_t o = (size_t)slot * a.bcap + pos;
         a.out_node[o] = (uint32_t)row;
         a.out_mask[o] = mine;
+        oe = (int64_t)o;
+      }
+      if (FMT == GT_POOL_BF16 && a.out_rec && eb) {
+        // score record of every kept pool: upper bounds of its real score for
+        // all 64 queries of the tile, query q at 4 (q % 16) + q / 16.  Lane l
+        // holds queries l % 32 and 32 + l % 32 of row 8 (x / 4) + 4 (l / 32)
+        // + x % 4; lanes l and l ^ 16 together hold the four queries c, 16 +
+        // c, 32 + c, 48 + c (c = l % 16) of a row.  For a pair of registers
+        // x, x + 1 the lower lane of the two writes row x, the upper row x+1.
+        const float aup = score_abs_up(a.dp);
+        const bool up = (r >> 4) & 1;
+#pragma unroll
+        for (int x = 0; x < 16; x += 2) {
+          // bounds as the high halves of 32-bit words
+          const uint32_t lo0 = bf16_ceil_hi(score_upper(acc[i][2 * tt][x], aup));
+          const uint32_t lo1 = bf16_ceil_hi(score_upper(acc[i][2 * tt + 1][x], aup));
+          const uint32_t hi0 = bf16_ceil_hi(score_upper(acc[i][2 * tt][x + 1], aup));
+          const uint32_t hi1 = bf16_ceil_hi(score_upper(acc[i][2 * tt + 1][x + 1], aup));
+          // keep the row this lane writes, send the other to lane l ^ 16
+          // (queries r and 32 + r of it, as the low and high half)
+          const uint32_t send = up ? ((lo0 >> 16) | lo1) : ((hi0 >> 16) | hi1);
+          const uint32_t got = (uint32_t)__shfl_xor((int)send, 16, 64);
+          const int xr = up ? x + 1 : x;
+          const int64_t o = __shfl(oe, 8 * (xr >> 2) + 4 * half + (xr & 3), 64);
+          // own values are queries r and 32 + r; slots qb = 0..3 of the
+          // record are queries c, 16 + c, 32 + c, 48 + c
+          const uint32_t m0 = up ? hi0 : lo0, m1 = up ? hi1 : lo1;
+          uint2 v;
+          v.x = up ? ((got & 0xFFFFu) | m0) : ((m0 >> 16) | (got << 16));
+          v.y = up ? ((got >> 16) | m1) : ((m1 >> 16) | (got & 0xFFFF0000u));
+          if (o >= 0)
+            *reinterpret_cast<uint2*>(a.out_rec + (size_t)o * 64 + 4 * (r & 15)) = v;
+        }
       }
     }
   }
@@ -1206,6 +1578,19 @@ hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStrea
     case GT_POOL_F32: return launch_walk_fmt<GT_POOL_F32, 64>(a, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_walk_sub(const WalkLevelArgs& a, int grid, hipStream_t s) {
+  grid = kXcds * ((grid + kXcds - 1) / kXcds);
+  if (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
+      a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles || a.dense || !a.in_rec || !a.sabs ||
+      a.level + 1 >= a.depth || a.depth > 32)
+    return hipErrorInvalidValue;
+  if (a.dp * 2 / 64 == 32)
+    hipLaunchKernelGGL((k_walk_sub<32, kSubPipe>), dim3(grid), dim3(kWalkThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_walk_sub<0, kSubPipe>), dim3(grid), dim3(kWalkThreads), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s) {

@@ -348,3 +348,38 @@ def test_dense_and_sparse_level_steps_agree(gtmod, dense_last, head):
                 h = st["head_level"]
                 assert st["pairs"][h] == 0 and st["pairs"][h + 1] > 0
     idx.close()
+
+
+@pytest.mark.parametrize("ws", [0, 1, 2])
+def test_subtraction_step_agrees(gtmod, ws):
+    """The bfloat16 walk may bound each left child's score by its pool's bound
+    minus a lower bound of the right child's score (paper Sec. 2 and Alg. 1:
+    one dot product per split) instead of reading the left child.  Any setting
+    (0 off, 1 every sparse level, 2 all but the last) and any split between
+    dense and sparse steps gives the oracle's result.  The row count is not a
+    multiple of the pool sizes, so pools straddle the end of the data, where
+    the step falls back to the pool's own bound; inserted rows move that end."""
+    w = synth.workload_small(20077, 300, 200, temp=0.2, seed_offset=18)
+    F = np.asarray(w.feats)
+    idx = gtmod.GTIndex(_dev(F), capacity=1 << 15)
+    idx.set_option("walk_subtract", ws)
+    q = _dev(w.queries)
+    try:
+        for dl in (-2, 9, 12):
+            idx.set_option("dense_last", dl)
+            for rho in (0.5, 0.8, 0.9, 0.95):
+                say(f"walk_subtract={ws} dense_last={dl} rho={rho}")
+                ora = ob.range_search(F, w.queries, rho)
+                assert_same(idx.query(q, rho, pool="bf16").to_lists(), ora,
+                            f"walk_subtract={ws} dense_last={dl} rho={rho}")
+        extra = synth.insert_rows(w.index, 1500, 300, 0.2)
+        idx.insert(_dev(extra))
+        F2 = np.concatenate([F, extra])
+        idx.set_option("dense_last", -2)
+        for rho in (0.8, 0.9):
+            say(f"walk_subtract={ws} after insert rho={rho}")
+            ora = ob.range_search(F2, w.queries, rho)
+            assert_same(idx.query(q, rho, pool="bf16").to_lists(), ora,
+                        f"walk_subtract={ws} after insert rho={rho}")
+    finally:
+        idx.close()
