@@ -200,6 +200,11 @@ gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int
  *   "grid"        workgroups of the persistent walk kernels (0 = one per CU)
  *   "dense_last"  last level tested with dense steps, every pool against every
  *                 query (-2 = automatic, -1 = none; bf16 and fp8 pools only)
+ *   "walk_subtract" subtraction step of the bf16 walk after a dense step (paper
+ *                 Sec. 2, Alg. 1: one dot product per split, the other half
+ *                 bounded by the pool's score minus it): 0 off, 1 every sparse
+ *                 level, 2 all but the last, -1 automatic (= 1).  Each frontier
+ *                 entry then carries 64 bf16 score bounds (128 bytes).
  *   "count_unique" 0/1: count distinct rows read per level (gt_stats.unique_rows);
  *                 adds atomics to the walk, for measurement runs only
  * Errors: INVALID_ARG for an unknown key or a value out of range. */
