@@ -215,13 +215,30 @@ def main():
     sparse_bytes = sum(uniq[l] for l in range(first_sparse + 1, D)) * dp * esz
     leaf_bytes = uniq[D] * dp * 4
     entries = list(su["entries"])
-    raw_sparse = sum(entries[l] for l in range(first_sparse, D - 1)) * 2 * dp * esz
+    # subtraction step (bf16 after a dense step): sparse levels first_sparse ..
+    # sub_to read one child row per entry plus the entry's 128-byte score
+    # record, and write records for outputs that a subtraction step reads next
+    ws = 1 if args.walk_subtract == -1 else args.walk_subtract
+    sub_to = -1
+    if args.pool == "bf16" and n_dense > 0 and ws > 0 and first_sparse <= D - 2:
+        sub_to = D - 2 if ws == 1 else D - 3
+    sub_levels = [l for l in range(first_sparse, D - 1) if l <= sub_to]
+    rec_bytes = 128 * (sum(entries[l] for l in sub_levels)
+                       + sum(entries[l + 1] for l in sub_levels if l + 1 <= sub_to))
+    dense_rec_bytes = 128 * entries[first_sparse] if sub_levels else 0
+    dense_bytes += dense_rec_bytes
+    sparse_bytes += rec_bytes
+    raw_sparse = sum(entries[l] * (1 if l in sub_levels else 2)
+                     for l in range(first_sparse, D - 1)) * dp * esz
     if n_dense == 0:
         raw_sparse += ((1 << h) * su["last_tiles"] - entries[h]) * 2 * dp * esz
     raw_leaf = entries[D - 1] * 2 * dp * 4
+    n_sub = len(sub_levels)
+    walk_name = (f"k_walk_level<{args.pool}>" if n_sub == 0 else
+                 "k_walk_sub<bf16>" if n_sub == n_sparse else "k_walk_sub+k_walk_level<bf16>")
     groups = {
         f"k_dense_level<{args.pool}>": (dense_bytes, ms_dense, n_dense),
-        f"k_walk_level<{args.pool}>": (sparse_bytes, ms_sparse, n_sparse),
+        walk_name: (sparse_bytes, ms_sparse, n_sparse),
         "k_leaf": (leaf_bytes, ms_leaf, 1),
     }
     gbps = lambda b, ms: round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
@@ -247,6 +264,7 @@ def main():
         "walk_all_levels": {"bytes": dense_bytes + sparse_bytes, "ms": round(ms_dense + ms_sparse, 4),
                             "GBps": gbps(dense_bytes + sparse_bytes, ms_dense + ms_sparse)},
         "sparse_raw_bytes": raw_sparse,
+        "score_record_bytes": {"dense_writes": dense_rec_bytes, "walk_reads_writes": rec_bytes},
         "leaf_raw_bytes": raw_leaf,
         "entries_per_level": {l: entries[l] for l in range(h + 1, D)},
         "tests_per_level": {l: su["pairs"][l] for l in range(h + 1, D)},
