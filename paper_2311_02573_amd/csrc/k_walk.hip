@@ -906,6 +906,110 @@ __device__ __forceinline__ void dense_lwrite(const DenseSlots& d, const DenseReg
   dense_lwrite1<7>(d, R, buf);
 }
 
+// Thresholds of tile t for the two 32-query halves a lane's accumulator
+// columns belong to (query t * 64 + 32 j + r).
+template <int FMT>
+__device__ __forceinline__ void dense_thresholds(const DenseLevelArgs& a, int t, int r, float (&thr)[2]) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int qi = t * 64 + 32 * j + r;
+    float th = a.thr[qi];
+    if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+    thr[j] = th;
+  }
+}
+
+// Output of one 32-pool block (rows rb0 .. rb0 + 31) against tile t: c0 and
+// c1 are the 32x32 accumulators of the tile's query halves.  Lane l holds
+// query column l % 32 of rows 8 (x / 4) + 4 (l / 32) + x % 4 (register x).
+// Survival bits by ballots (lane r < 32 ends with row r's 64-query mask),
+// ANDed with the parent masks; then per-(pool, tile) masks for a following
+// dense level, or the bucketed sparse frontier (and, for the subtraction
+// step, the kept pools' score records).
+template <int FMT>
+__device__ __forceinline__ void dense_block_out(const DenseLevelArgs& a, const f32x16& c0,
+                                                const f32x16& c1, int64_t rb0, int t,
+                                                const float (&thr)[2], int lane,
+                                                unsigned long long& pairs) {
+  const int r = lane & 31, half = lane >> 5;
+  const int64_t rows = a.rows;
+  const int bshift = a.level - a.nb;  // node -> bucket of the sparse output
+  const int64_t row = rb0 + r;
+  const bool rv = lane < 32 && row < rows;
+  uint64_t pm = 0ull;
+  if (rv) pm = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
+  uint64_t mine = 0ull;
+#pragma unroll
+  for (int x = 0; x < 16; ++x) {
+    const uint64_t b0 = __ballot(c0[x] >= thr[0]);
+    const uint64_t b1 = __ballot(c1[x] >= thr[1]);
+    const uint64_t lo = (b0 & 0xffffffffull) | (b1 << 32);
+    const uint64_t hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
+    const int rr = 8 * (x >> 2) + (x & 3);
+    if (lane == rr) mine = lo;
+    if (lane == rr + 4) mine = hi;
+  }
+  mine &= pm;
+  if (rv) pairs += (unsigned long long)__popcll(pm);
+  if (a.bitmap && rv && pm) atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
+  const uint64_t eb = __ballot(rv && mine != 0ull);
+  int64_t oe = -1;  // output entry of this lane's row
+  if (a.out_dense) {
+    if (rv) a.out_dense[row * a.nt + t] = mine;
+    if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
+  } else if (eb && bshift >= 5) {
+    // the 32 rows (aligned) share one bucket: one reservation per wave
+    const uint32_t slot = (uint32_t)(rb0 >> bshift) * (uint32_t)a.nt + t;
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(eb));
+    base = __shfl(base, 0, 64);
+    if (rv && mine) {
+      const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
+      const size_t o = (size_t)slot * a.bcap + pos;
+      a.out_node[o] = (uint32_t)row;
+      a.out_mask[o] = mine;
+      oe = (int64_t)o;
+    }
+  } else if (eb && rv && mine) {
+    const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
+    const uint32_t pos = atomicAdd(&a.out_count[slot], 1u);
+    const size_t o = (size_t)slot * a.bcap + pos;
+    a.out_node[o] = (uint32_t)row;
+    a.out_mask[o] = mine;
+    oe = (int64_t)o;
+  }
+  if (FMT == GT_POOL_BF16 && a.out_rec && eb) {
+    // score record of every kept pool: upper bounds of its real score for
+    // all 64 queries of the tile, query q at 4 (q % 16) + q / 16.  Lanes l
+    // and l ^ 16 together hold the four queries c, 16 + c, 32 + c, 48 + c
+    // (c = l % 16) of a row.  For a pair of registers x, x + 1 the lower lane
+    // of the two writes row x, the upper row x + 1.
+    const float aup = score_abs_up(a.dp);
+    const bool up = (r >> 4) & 1;
+#pragma unroll
+    for (int x = 0; x < 16; x += 2) {
+      // bounds as the high halves of 32-bit words
+      const uint32_t lo0 = bf16_ceil_hi(score_upper(c0[x], aup));
+      const uint32_t lo1 = bf16_ceil_hi(score_upper(c1[x], aup));
+      const uint32_t hi0 = bf16_ceil_hi(score_upper(c0[x + 1], aup));
+      const uint32_t hi1 = bf16_ceil_hi(score_upper(c1[x + 1], aup));
+      // keep the row this lane writes, send the other to lane l ^ 16
+      // (queries r and 32 + r of it, as the low and high half)
+      const uint32_t send = up ? ((lo0 >> 16) | lo1) : ((hi0 >> 16) | hi1);
+      const uint32_t got = (uint32_t)__shfl_xor((int)send, 16, 64);
+      const int xr = up ? x + 1 : x;
+      const int64_t o = __shfl(oe, 8 * (xr >> 2) + 4 * half + (xr & 3), 64);
+      // own values are queries r and 32 + r; slots qb = 0..3 of the record
+      // are queries c, 16 + c, 32 + c, 48 + c
+      const uint32_t m0 = up ? hi0 : lo0, m1 = up ? hi1 : lo1;
+      uint2 v;
+      v.x = up ? ((got & 0xFFFFu) | m0) : ((m0 >> 16) | (got << 16));
+      v.y = up ? ((got >> 16) | m1) : ((m1 >> 16) | (got & 0xFFFF0000u));
+      if (o >= 0) *reinterpret_cast<uint2*>(a.out_rec + (size_t)o * 64 + 4 * (r & 15)) = v;
+    }
+  }
+}
+
 template <int FMT>
 __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) {
   using F = WalkFmt<FMT>;
@@ -1010,98 +1114,16 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
   }
 
   unsigned long long pairs = 0;
-  const int bshift = a.level - a.nb;  // node -> bucket of the sparse output
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
     const int t = qb * kDTiles + 2 * wq + tt;
     if (t >= a.nt) break;
     float thr[2];
+    dense_thresholds<FMT>(a, t, r, thr);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int qi = t * 64 + 32 * j + r;
-      float th = a.thr[qi];
-      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
-      thr[j] = th;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int64_t row = row0 + wr * 64 + i * 32 + r;
-      const bool rv = lane < 32 && row < rows;
-      uint64_t pm = 0ull;
-      if (rv) pm = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
-      uint64_t mine = 0ull;
-#pragma unroll
-      for (int x = 0; x < 16; ++x) {
-        const uint64_t b0 = __ballot(acc[i][2 * tt][x] >= thr[0]);
-        const uint64_t b1 = __ballot(acc[i][2 * tt + 1][x] >= thr[1]);
-        const uint64_t lo = (b0 & 0xffffffffull) | (b1 << 32);
-        const uint64_t hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
-        const int rr = 8 * (x >> 2) + (x & 3);
-        if (lane == rr) mine = lo;
-        if (lane == rr + 4) mine = hi;
-      }
-      mine &= pm;
-      if (rv) pairs += (unsigned long long)__popcll(pm);
-      if (a.bitmap && rv && pm) atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
-      const uint64_t eb = __ballot(rv && mine != 0ull);
-      int64_t oe = -1;  // output entry of this lane's row
-      if (a.out_dense) {
-        if (rv) a.out_dense[row * a.nt + t] = mine;
-        if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
-      } else if (eb && bshift >= 5) {
-        // the 32 rows (aligned) share one bucket: one reservation per wave
-        const uint32_t slot = (uint32_t)((row0 + wr * 64 + i * 32) >> bshift) * (uint32_t)a.nt + t;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(eb));
-        base = __shfl(base, 0, 64);
-        if (rv && mine) {
-          const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
-          const size_t o = (size_t)slot * a.bcap + pos;
-          a.out_node[o] = (uint32_t)row;
-          a.out_mask[o] = mine;
-          oe = (int64_t)o;
-        }
-      } else if (eb && rv && mine) {
-        const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
-        const uint32_t pos = atomicAdd(&a.out_count[slot], 1u);
-        const size_t o = (size_t)slot * a.bcap + pos;
-        a.out_node[o] = (uint32_t)row;
-        a.out_mask[o] = mine;
-        oe = (int64_t)o;
-      }
-      if (FMT == GT_POOL_BF16 && a.out_rec && eb) {
-        // score record of every kept pool: upper bounds of its real score for
-        // all 64 queries of the tile, query q at 4 (q % 16) + q / 16.  Lane l
-        // holds queries l % 32 and 32 + l % 32 of row 8 (x / 4) + 4 (l / 32)
-        // + x % 4; lanes l and l ^ 16 together hold the four queries c, 16 +
-        // c, 32 + c, 48 + c (c = l % 16) of a row.  For a pair of registers
-        // x, x + 1 the lower lane of the two writes row x, the upper row x+1.
-        const float aup = score_abs_up(a.dp);
-        const bool up = (r >> 4) & 1;
-#pragma unroll
-        for (int x = 0; x < 16; x += 2) {
-          // bounds as the high halves of 32-bit words
-          const uint32_t lo0 = bf16_ceil_hi(score_upper(acc[i][2 * tt][x], aup));
-          const uint32_t lo1 = bf16_ceil_hi(score_upper(acc[i][2 * tt + 1][x], aup));
-          const uint32_t hi0 = bf16_ceil_hi(score_upper(acc[i][2 * tt][x + 1], aup));
-          const uint32_t hi1 = bf16_ceil_hi(score_upper(acc[i][2 * tt + 1][x + 1], aup));
-          // keep the row this lane writes, send the other to lane l ^ 16
-          // (queries r and 32 + r of it, as the low and high half)
-          const uint32_t send = up ? ((lo0 >> 16) | lo1) : ((hi0 >> 16) | hi1);
-          const uint32_t got = (uint32_t)__shfl_xor((int)send, 16, 64);
-          const int xr = up ? x + 1 : x;
-          const int64_t o = __shfl(oe, 8 * (xr >> 2) + 4 * half + (xr & 3), 64);
-          // own values are queries r and 32 + r; slots qb = 0..3 of the
-          // record are queries c, 16 + c, 32 + c, 48 + c
-          const uint32_t m0 = up ? hi0 : lo0, m1 = up ? hi1 : lo1;
-          uint2 v;
-          v.x = up ? ((got & 0xFFFFu) | m0) : ((m0 >> 16) | (got << 16));
-          v.y = up ? ((got >> 16) | m1) : ((m1 >> 16) | (got & 0xFFFF0000u));
-          if (o >= 0)
-            *reinterpret_cast<uint2*>(a.out_rec + (size_t)o * 64 + 4 * (r & 15)) = v;
-        }
-      }
-    }
+    for (int i = 0; i < 2; ++i)
+      dense_block_out<FMT>(a, acc[i][2 * tt], acc[i][2 * tt + 1], row0 + wr * 64 + i * 32, t, thr,
+                           lane, pairs);
   }
   if (a.stat_pairs) {
     for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
