@@ -13,6 +13,8 @@ Everything here works on Python Fractions, so no rounding is involved:
 * `levelwise_walk`: the same implicit tree visited one level ("round") at a
   time (Sec. 5 analyses pruning per round), over a power-of-two capacity with
   zero padding, testing both children of every surviving pool directly.
+* `levelwise_walk_max`: that walk with Our-Max pools (Sec. 3), each pool the
+  element-wise maximum of its members.
 
 The binary-splitting and level-wise walks are the paper's method, kept here to
 show that it returns exactly the brute-force set; the GPU path is compared with
@@ -157,3 +159,38 @@ def levelwise_walk(F, q, rho, capacity: int | None = None):
         tests.append(2 * len(frontier))
         frontier = nxt
     return sorted(i for i in frontier if i < N), tests
+
+
+def levelwise_walk_max(F, q, rho, capacity: int | None = None):
+    """The same level-by-level walk with Our-Max pools (Sec. 3): a pool is the
+    element-wise maximum of its members.  For non-negative q and members,
+    q.max >= q.f_i for every member i, so a pool scoring below rho holds no
+    neighbour.  Both children of each surviving pool are tested directly; a
+    leaf (a single vector, its own maximum) is a member iff q.f >= rho.
+    Returns (ids, tests per level)."""
+    N = len(F)
+    if N == 0:
+        return [], []
+    cap = capacity or 1 << max(0, (N - 1).bit_length())
+    assert cap >= N and cap & (cap - 1) == 0
+    d = len(F[0])
+    qf = [Fraction(float(x)) for x in q]
+    leaves = [[Fraction(float(x)) for x in f] for f in F] + [[Fraction(0)] * d] * (cap - N)
+    levels = [leaves]
+    while len(levels[0]) > 1:
+        below = levels[0]
+        levels.insert(0, [[max(a, b) for a, b in zip(below[2 * j], below[2 * j + 1])]
+                          for j in range(len(below) // 2)])
+    r = Fraction(float(rho))
+    frontier = [0] if dot(qf, levels[0][0]) >= r else []
+    tests = [1]
+    for lvl in range(1, len(levels)):
+        nxt = []
+        for p in frontier:
+            for c in (2 * p, 2 * p + 1):
+                if dot(qf, levels[lvl][c]) >= r:
+                    nxt.append(c)
+        tests.append(2 * len(frontier))
+        frontier = nxt
+    return sorted(i for i in frontier if i < N), tests
+

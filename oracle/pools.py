@@ -50,3 +50,21 @@ def members(level: int, node: int, depth: int):
     """Row range [lo, hi) covered by node `node` of `level` in a depth-`depth` tree."""
     span = 1 << (depth - level)
     return node * span, (node + 1) * span
+
+
+def max_pool_tree(feats, capacity: int | None = None):
+    """Our-Max pools (Sec. 3): levels[l] = float64 [2^l, d], node j the
+    element-wise maximum of its members (exact: a maximum of float32 values is
+    one of them); levels[D] are the (zero-padded) leaves."""
+    f = np.asarray(feats, dtype=np.float64)
+    n, d = f.shape
+    cap = capacity or 1 << max(0, (n - 1).bit_length())
+    assert cap >= n and cap & (cap - 1) == 0
+    leaves = np.zeros((cap, d), np.float64)
+    leaves[:n] = f
+    levels = [leaves]
+    while levels[0].shape[0] > 1:
+        below = levels[0]
+        levels.insert(0, np.maximum(below[0::2], below[1::2]))
+    return levels
+

@@ -143,6 +143,70 @@ def test_toy_pool_example():
     assert exact.dot(q, y1) == qy - exact.dot(q, y2)
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16])
+def test_max_pool_walk_equals_brute_force_and_tests_no_more_than_sums(n):
+    """Sec. 3, Our-Max: a pool is the element-wise maximum of its members; with
+    non-negative vectors q.max >= q.f for every member, so the walk returns
+    exactly {i : q.f_i >= rho}.  A max pool never scores above the sum pool of
+    the same members, so at every level the max walk keeps a subset of the
+    sum walk's pools and runs at most as many tests."""
+    rng = np.random.default_rng(300 + n)
+    for trial in range(5):
+        d = 1 + trial % 4
+        F = _rand_nonneg(rng, n, d, 0.25)
+        q = _rand_nonneg(rng, 1, d, 0.1)[0]
+        qf = [Fraction(float(x)) for x in q]
+        for rho in (0.05, 0.2, 0.4, 0.8):
+            want = [i for i in range(n)
+                    if exact.dot(qf, [Fraction(float(x)) for x in F[i]]) >= Fraction(rho)]
+            got, tmax = exact.levelwise_walk_max(F, q, rho)
+            assert got == want, (n, trial, rho)
+            _, tsum = exact.levelwise_walk(F, q, rho)
+            assert len(tmax) == len(tsum)
+            assert all(a <= b for a, b in zip(tmax, tsum)), (tmax, tsum)
+
+
+def test_max_pool_worked_example():
+    """A hand-worked case (unit vectors in R^2, sim = q.f, Sec. 2): f0 = (3/5,
+    4/5), f1 = (4/5, 3/5), f2 = (1, 0), f3 = (0, 1), q = (0, 1), rho = 0.9.
+    Member scores 0.8, 0.6, 0, 1: the only neighbour is f3.  Sum pools of the
+    halves, (7/5, 7/5) and (1, 1), score 1.4 and 1 and both survive, so all
+    four vectors are tested (tests per level 1, 2, 4).  Max pools, (4/5, 4/5)
+    and (1, 1), score 0.8 and 1: the left half is pruned (tests 1, 2, 2)."""
+    F = np.array([[0.6, 0.8], [0.8, 0.6], [1.0, 0.0], [0.0, 1.0]])
+    q = np.array([0.0, 1.0])
+    ids_s, t_s = exact.levelwise_walk(F, q, 0.9)
+    ids_m, t_m = exact.levelwise_walk_max(F, q, 0.9)
+    assert ids_s == ids_m == [3]
+    assert t_s == [1, 2, 4] and t_m == [1, 2, 2]
+    lv = pools.max_pool_tree(F)
+    assert np.array_equal(lv[1], [[0.8, 0.8], [1.0, 1.0]])
+    assert np.array_equal(lv[0], [[1.0, 1.0]])
+
+
+def test_max_pool_tree_invariants_on_softmax_data():
+    """Every Our-Max pool equals the element-wise maximum of its members taken
+    directly, lies between each member and the sum pool, and scores at least
+    the largest member score."""
+    w = synth.workload_small(1000, 24, 4, seed_offset=4)
+    F = np.asarray(w.feats, np.float64)
+    mx = pools.max_pool_tree(F)
+    sm = pools.pool_tree(F)
+    D = len(mx) - 1
+    for level in range(D + 1):
+        span = 1 << (D - level)
+        for j in range(0, 1 << level, max(1, (1 << level) // 7)):
+            a, b = j * span, min(len(F), (j + 1) * span)
+            direct = F[a:b].max(axis=0) if a < b else np.zeros(F.shape[1])
+            assert np.array_equal(mx[level][j], direct)
+            assert np.all(mx[level][j] <= sm[level][j] * (1 + 1e-12))
+    for q in w.queries:
+        leaf = mx[D] @ q
+        for level in range(D):
+            span = 1 << (D - level)
+            assert np.all(mx[level] @ q >= leaf.reshape(-1, span).max(axis=1) * (1 - 1e-12))
+
+
 def test_prefix_sum_pool_identity():
     """Sec. 2, Eq. 1: with cumulative sums C, the right half-pool of N rows is
     C_N - C_{floor(N/2)}; the explicit tree's node (level 1, index 1) equals it."""
