@@ -121,7 +121,7 @@ def main():
     torch.cuda.synchronize()
 
     t0 = time.time()
-    idx = gt.GTIndex(feats, pools=("f32", "bf16", "fp8"))
+    idx = gt.GTIndex(feats, pools=("f32", "bf16", "fp8", "max_bf16"))
     torch.cuda.synchronize()
     build_s = time.time() - t0
     st0 = idx.stats()
@@ -307,12 +307,25 @@ def main():
     comparators = {}
     exh = None
     if not args.no_side:
-        for pool in ("f32", "fp8", "bf16"):
+        for pool in ("f32", "fp8", "bf16", "max_bf16"):
             if pool == args.pool:
                 continue
             r2, wall2, lat2 = run(pool, args.side_steps, 1)
             comparators[f"walk_{pool}_qps"] = round(args.nq * args.side_steps / wall2, 1)
             comparators[f"walk_{pool}_ms"] = round(wall2 / args.side_steps * 1e3, 3)
+            if pool == "max_bf16":
+                # Our-Max pools (paper Sec. 3): same result set, other pruning
+                comparators["walk_max_bf16_results_identical"] = r2.total == res.total and all(
+                    np.array_equal(a[0], b[0]) for a, b in zip(r2.to_lists(), res.to_lists()))
+                idx.set_option("profile", 1)
+                idx.query(q, args.rho, pool="max_bf16")
+                sm = idx.stats()
+                idx.set_option("profile", 0)
+                comparators["walk_max_bf16_stage_ms"] = {
+                    k[3:]: round(sm[k], 4) for k in ("ms_dense", "ms_frontier", "ms_leaf", "ms_total")}
+                comparators["walk_max_bf16_tests_per_level"] = {
+                    l: sm["pairs"][l] for l in range(len(sm["pairs"])) if sm["pairs"][l]}
+                comparators["walk_max_bf16_leaf_pairs"] = sm["leaf_pairs"]
         exh, wall3, lat3 = run("exh", max(2, args.side_steps // 2), 1)
         n3 = max(2, args.side_steps // 2)
         comparators["exhaustive_f32_qps"] = round(args.nq * n3 / wall3, 1)

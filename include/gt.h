@@ -49,11 +49,21 @@ typedef enum {
 
 typedef enum { GT_F32 = 0, GT_F16 = 1, GT_BF16 = 2 } gt_dtype; /* feature storage */
 
-/* Pool-sum storage formats.  Pool sums are kept as float32 master values
- * rounded upward; the reduced formats are upward-rounded copies (bfloat16, and
- * float8 e4m3 with one power-of-two scale per tree level).  Bit mask at build
- * time, one value per query call. */
-typedef enum { GT_POOL_F32 = 1, GT_POOL_BF16 = 2, GT_POOL_FP8E4M3 = 4 } gt_pool;
+/* Pool storage formats.  Pool sums are kept as float32 master values rounded
+ * upward; the reduced formats are upward-rounded copies (bfloat16, and float8
+ * e4m3 with one power-of-two scale per tree level).  The MAX formats are a
+ * second tree whose pools are the element-wise maximum of their members
+ * (paper Sec. 3, Our-Max: a query scores a max pool at least as high as any
+ * member, so the same prune rule holds), float32 (exact) and a bfloat16 copy
+ * rounded upward; asking for GT_POOL_MAX_BF16 also builds GT_POOL_MAX_F32.
+ * Bit mask at build time, one value per query call. */
+typedef enum {
+  GT_POOL_F32 = 1,
+  GT_POOL_BF16 = 2,
+  GT_POOL_FP8E4M3 = 4,
+  GT_POOL_MAX_F32 = 8,
+  GT_POOL_MAX_BF16 = 16
+} gt_pool;
 
 #define GT_MAX_LEVELS 40
 
@@ -186,7 +196,9 @@ gt_status gt_get_stats(const gt_index* index, gt_stats* out);
  * Rows first .. first+count-1 of the level, each d_pad values:
  *   GT_POOL_F32 -> float32 master sums (upward-rounded, >= the exact sums),
  *   GT_POOL_BF16 -> uint16 bfloat16 codes, GT_POOL_FP8E4M3 -> uint8 e4m3 codes
- *   (value = decoded code * 2^fp8_exp[level], see gt_stats).
+ *   (value = decoded code * 2^fp8_exp[level], see gt_stats),
+ *   GT_POOL_MAX_F32 -> float32 element-wise maxima (exact; level == depth gives
+ *   the leaf rows), GT_POOL_MAX_BF16 -> their bfloat16 codes, rounded up.
  * host_out must hold count * d_pad elements of that type.  Synchronises the
  * device.  Errors: INVALID_ARG (range, format not built), DEVICE. */
 gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int64_t count,

@@ -214,6 +214,8 @@ void free_tree(Index* ix) {
   dfree(ix, &ix->master, tree);
   dfree(ix, &ix->pbf16, tree);
   dfree(ix, &ix->pfp8, tree);
+  dfree(ix, &ix->mmax, tree);
+  dfree(ix, &ix->pmax16, tree);
   dfree(ix, &ix->d_lexp, GT_MAX_LEVELS);
   dfree(ix, &ix->d_levelmax, GT_MAX_LEVELS);
   dfree(ix, &ix->d_flags, GT_MAX_LEVELS);
@@ -341,16 +343,20 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   const void* qtile = f == GT_POOL_F32 ? (const void*)b->qf
                       : f == GT_POOL_BF16 ? (const void*)b->qbf : (const void*)b->q8;
   const size_t esz = f == GT_POOL_F32 ? 4 : f == GT_POOL_BF16 ? 2 : 1;
-  const unsigned char* pool_base = f == GT_POOL_F32 ? (const unsigned char*)ix->master
-                                   : f == GT_POOL_BF16 ? (const unsigned char*)ix->pbf16
-                                                       : (const unsigned char*)ix->pfp8;
+  const unsigned char* pool_base =
+      b->maxpool ? (f == GT_POOL_F32 ? (const unsigned char*)ix->mmax
+                                     : (const unsigned char*)ix->pmax16)
+      : f == GT_POOL_F32  ? (const unsigned char*)ix->master
+      : f == GT_POOL_BF16 ? (const unsigned char*)ix->pbf16
+                          : (const unsigned char*)ix->pfp8;
   uint32_t* bitmap = b->counted ? b->bitmap : nullptr;
   b->frontier_launches = 0;
   b->dense_launches = 0;
   // Subtraction step (bfloat16 pools, score records from a dense step):
   // sparse levels sub_from .. sub_to read only the right children.
   const int ws = ix->walk_subtract < 0 ? 1 : ix->walk_subtract;
-  const bool sub = f == GT_POOL_BF16 && dl >= 0 && ws > 0 && dl <= D - 2;
+  // (sum pools only: a max pool is not its halves' combination)
+  const bool sub = f == GT_POOL_BF16 && !b->maxpool && dl >= 0 && ws > 0 && dl <= D - 2;
   const int sub_to = !sub ? -1 : (ws == 2 ? D - 3 : D - 2);
   if (sub && sub_to >= dl) {
     const int64_t need = (int64_t)nt * b->fr_cap;
@@ -573,11 +579,16 @@ gt_status check_query_args(const Index* ix, const float* q, int nq, const double
 gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const double* rho,
                  int fmt, hipStream_t s) {
   if (b->pending) return fail(GT_ERR_INVALID_ARG, "the workspace has a call in flight");
+  // max pools run the kernels of their storage format on the max tree
+  const int user_fmt = fmt;
+  const bool maxp = kind == 1 && (fmt == GT_POOL_MAX_F32 || fmt == GT_POOL_MAX_BF16);
+  if (maxp) fmt = fmt == GT_POOL_MAX_F32 ? GT_POOL_F32 : GT_POOL_BF16;
   const int tq = kind == 1 ? tq_of(fmt) : gt::kQueriesPerTile16;
   if (kind == 1) {
     if (fmt != GT_POOL_F32 && fmt != GT_POOL_BF16 && fmt != GT_POOL_FP8E4M3)
       return fail(GT_ERR_INVALID_ARG, "unknown pool format");
-    if (!(ix->formats & (uint32_t)fmt)) return fail(GT_ERR_INVALID_ARG, "pool format was not built");
+    if (!(ix->formats & (uint32_t)user_fmt))
+      return fail(GT_ERR_INVALID_ARG, "pool format was not built");
     if (ix->dp > maxdp_of(fmt))
       return fail(GT_ERR_INVALID_ARG, "d too large for this pool format (padded d <= " +
                                           std::to_string(maxdp_of(fmt)) + ")");
@@ -593,6 +604,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   b->kind = kind;
   b->stream = s;
   b->fmt = fmt;
+  b->maxpool = maxp;
   b->nq = nq;
   b->nq_pad = nq_pad;
   b->nt = nt;
@@ -655,7 +667,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   b->pending = true;
   b->last_nq = nq;
   b->last_nt = nt;
-  b->last_fmt = kind == 1 ? fmt : 0;
+  b->last_fmt = kind == 1 ? user_fmt : 0;
   b->last_head = b->head;
   return GT_OK;
 }
@@ -741,7 +753,8 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   if (n > 0 && !feats_dev) return fail(GT_ERR_INVALID_ARG, "feats_dev is NULL");
   if (dtype != GT_F32 && dtype != GT_F16 && dtype != GT_BF16)
     return fail(GT_ERR_INVALID_ARG, "unknown dtype");
-  if (pool_formats & ~(uint32_t)(GT_POOL_F32 | GT_POOL_BF16 | GT_POOL_FP8E4M3))
+  if (pool_formats & ~(uint32_t)(GT_POOL_F32 | GT_POOL_BF16 | GT_POOL_FP8E4M3 | GT_POOL_MAX_F32 |
+                                 GT_POOL_MAX_BF16))
     return fail(GT_ERR_INVALID_ARG, "unknown pool format bits");
   if (capacity == 0) {
     capacity = 2;
@@ -787,6 +800,8 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   while ((int64_t(1) << ix->depth) < capacity) ++ix->depth;
   ix->dtype = dtype;
   ix->formats = pool_formats | GT_POOL_F32;
+  // max pools keep a float32 tree whenever a max format is asked for
+  if (ix->formats & GT_POOL_MAX_BF16) ix->formats |= GT_POOL_MAX_F32;
 
   const size_t cap = (size_t)capacity, dp = (size_t)ix->dp, tree = (cap - 1) * dp;
   BTRY(dalloc(ix, &ix->leaves, cap * dp));
@@ -797,6 +812,8 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   BTRY(dalloc(ix, &ix->master, tree));
   if (ix->formats & GT_POOL_BF16) BTRY(dalloc(ix, &ix->pbf16, tree));
   if (ix->formats & GT_POOL_FP8E4M3) BTRY(dalloc(ix, &ix->pfp8, tree));
+  if (ix->formats & GT_POOL_MAX_F32) BTRY(dalloc(ix, &ix->mmax, tree));
+  if (ix->formats & GT_POOL_MAX_BF16) BTRY(dalloc(ix, &ix->pmax16, tree));
   BTRY(dalloc(ix, &ix->d_lexp, GT_MAX_LEVELS));
   BTRY(dalloc(ix, &ix->d_levelmax, GT_MAX_LEVELS));
   BTRY(dalloc(ix, &ix->d_flags, GT_MAX_LEVELS));
@@ -805,6 +822,7 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   BHIP(hipMemsetAsync(ix->ff, 0, cap * 8, s));
   BHIP(hipMemsetAsync(ix->nf, 0, cap * 4, s));
   BHIP(hipMemsetAsync(ix->master, 0, tree * 4, s));
+  if (ix->mmax) BHIP(hipMemsetAsync(ix->mmax, 0, tree * 4, s));
   BHIP(hipMemsetAsync(ix->d_flags, 0, GT_MAX_LEVELS * 4, s));
   BHIP(hipMemsetAsync(ix->d_lexp, 0, GT_MAX_LEVELS * 4, s));
   const double inf = INFINITY;
@@ -824,9 +842,14 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
     const float* child = (l == ix->depth - 1) ? ix->leaves : ix->master + level_row(l + 1) * dp;
     const int64_t span = int64_t(1) << (ix->depth - l);
     const int64_t nodes = (n + span - 1) / span;
-    BHIP(gt::launch_build_level(child, ix->master + level_row(l) * dp, nodes, ix->dp, 0, s));
+    BHIP(gt::launch_build_level(child, ix->master + level_row(l) * dp, nodes, ix->dp, 0, s, false));
+    if (ix->mmax) {
+      const float* mchild = (l == ix->depth - 1) ? ix->leaves : ix->mmax + level_row(l + 1) * dp;
+      BHIP(gt::launch_build_level(mchild, ix->mmax + level_row(l) * dp, nodes, ix->dp, 0, s, true));
+    }
   }
   if (ix->pbf16) BHIP(gt::launch_quant_bf16(ix->master, ix->pbf16, (int64_t)tree, s));
+  if (ix->pmax16) BHIP(gt::launch_quant_bf16(ix->mmax, ix->pmax16, (int64_t)tree, s));
   if (ix->pfp8) {
     BHIP(hipMemsetAsync(ix->d_levelmax, 0, GT_MAX_LEVELS * 4, s));
     for (int l = 0; l < ix->depth; ++l)
@@ -897,7 +920,15 @@ gt_status gt_insert(gt_index* ix, const void* feats_dev, int64_t n_new, void* st
     const int64_t a = lo >> sh, b = (hi - 1) >> sh;
     const float* child = (l == ix->depth - 1) ? ix->leaves : ix->master + level_row(l + 1) * dp;
     float* par = ix->master + level_row(l) * dp;
-    HIPCHK(gt::launch_build_level(child, par, b - a + 1, ix->dp, a, s));
+    HIPCHK(gt::launch_build_level(child, par, b - a + 1, ix->dp, a, s, false));
+    if (ix->mmax) {
+      const float* mchild = (l == ix->depth - 1) ? ix->leaves : ix->mmax + level_row(l + 1) * dp;
+      float* mpar = ix->mmax + level_row(l) * dp;
+      HIPCHK(gt::launch_build_level(mchild, mpar, b - a + 1, ix->dp, a, s, true));
+      if (ix->pmax16)
+        HIPCHK(gt::launch_quant_bf16(mpar + a * dp, ix->pmax16 + (level_row(l) + a) * dp,
+                                     (b - a + 1) * ix->dp, s));
+    }
     if (ix->pbf16)
       HIPCHK(gt::launch_quant_bf16(par + a * dp, ix->pbf16 + (level_row(l) + a) * dp,
                                    (b - a + 1) * ix->dp, s));
@@ -1081,14 +1112,19 @@ gt_status gt_read_pools(const gt_index* ix, int32_t level, int64_t first, int64_
   if (first < 0 || count < 0 || first + count > rows)
     return fail(GT_ERR_INVALID_ARG, "row range out of the level");
   const int f = (int)fmt;
-  if (!(ix->formats & (uint32_t)f) || (level == ix->depth && f != GT_POOL_F32))
+  if (!(ix->formats & (uint32_t)f) ||
+      (level == ix->depth && f != GT_POOL_F32 && f != GT_POOL_MAX_F32))
     return fail(GT_ERR_INVALID_ARG, "format not available for this level");
-  const size_t esz = f == GT_POOL_F32 ? 4 : f == GT_POOL_BF16 ? 2 : 1;
+  const size_t esz = (f == GT_POOL_F32 || f == GT_POOL_MAX_F32) ? 4
+                     : (f == GT_POOL_BF16 || f == GT_POOL_MAX_BF16) ? 2 : 1;
+  const size_t off = (size_t)level_row(level) * ix->dp;
   const unsigned char* base =
-      level == ix->depth ? (const unsigned char*)ix->leaves
-      : f == GT_POOL_F32 ? (const unsigned char*)(ix->master + level_row(level) * ix->dp)
-      : f == GT_POOL_BF16 ? (const unsigned char*)(ix->pbf16 + level_row(level) * ix->dp)
-                          : (const unsigned char*)(ix->pfp8 + level_row(level) * ix->dp);
+      level == ix->depth     ? (const unsigned char*)ix->leaves
+      : f == GT_POOL_F32     ? (const unsigned char*)(ix->master + off)
+      : f == GT_POOL_BF16    ? (const unsigned char*)(ix->pbf16 + off)
+      : f == GT_POOL_MAX_F32 ? (const unsigned char*)(ix->mmax + off)
+      : f == GT_POOL_MAX_BF16 ? (const unsigned char*)(ix->pmax16 + off)
+                              : (const unsigned char*)(ix->pfp8 + off);
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipMemcpy(host_out, base + (size_t)first * ix->dp * esz, (size_t)count * ix->dp * esz,
                    hipMemcpyDeviceToHost));

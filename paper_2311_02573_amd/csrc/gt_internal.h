@@ -149,6 +149,7 @@ struct Batch {
   uint32_t* fr_node[2] = {nullptr, nullptr};
   uint64_t* fr_mask[2] = {nullptr, nullptr};
   uint16_t* fr_rec[2] = {nullptr, nullptr};  // score records (64 per entry)
+  bool maxpool = false;      // the call walks the max-pool tree
   float* sabs = nullptr;                     // [nq_pad] lower-bound absolute terms
   int64_t fr_cap = 0;        // entries per tile per buffer
   int64_t rec_len = 0;       // entries of each fr_rec buffer
@@ -241,6 +242,8 @@ struct Index {
   float* master = nullptr;   // levels 0..depth-1, level l at row (2^l - 1)
   uint16_t* pbf16 = nullptr;
   uint8_t* pfp8 = nullptr;
+  float* mmax = nullptr;     // element-wise max pools (Our-Max), same layout as master
+  uint16_t* pmax16 = nullptr;  // their bfloat16 copy, rounded up
   int* d_lexp = nullptr;     // float8 scale exponents per level
   int lexp[GT_MAX_LEVELS] = {0};
   float* d_levelmax = nullptr;
@@ -255,7 +258,7 @@ hipError_t launch_ingest(const void* src, int dtype, int64_t rows, int d, int dp
                          double* ff, float* invn, float* nf, double* mmin, unsigned int* err,
                          hipStream_t s);
 hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, int dp,
-                              int64_t first, hipStream_t s);
+                              int64_t first, hipStream_t s, bool max_pool);
 hipError_t launch_level_max(const float* rows, int64_t nrows, int dp, float* out_max, hipStream_t s);
 hipError_t launch_quant_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
 hipError_t launch_quant_fp8(const float* src, uint8_t* dst, int64_t count, int lexp,

@@ -77,6 +77,10 @@ __global__ __launch_bounds__(64) void k_ingest(const void* src, int dtype, int64
 }
 
 // parent = children summed with upward rounding, 4 columns per thread.
+// Parent pools of `nodes` nodes from their two children: the element-wise sum
+// rounded up (sum pooling, paper Sec. 2) or the element-wise maximum, which is
+// exact (Our-Max pooling, Sec. 3).
+template <bool MAXP>
 __global__ void k_build_level(const float* __restrict__ child, float* __restrict__ parent,
                               int64_t first, int64_t nodes, int dp) {
   const int q = dp / 4;
@@ -88,10 +92,17 @@ __global__ void k_build_level(const float* __restrict__ child, float* __restrict
     const float4 a = *reinterpret_cast<const float4*>(child + (2 * j) * dp + k);
     const float4 b = *reinterpret_cast<const float4*>(child + (2 * j + 1) * dp + k);
     float4 s;
-    s.x = add_up(a.x, b.x);
-    s.y = add_up(a.y, b.y);
-    s.z = add_up(a.z, b.z);
-    s.w = add_up(a.w, b.w);
+    if (MAXP) {
+      s.x = fmaxf(a.x, b.x);
+      s.y = fmaxf(a.y, b.y);
+      s.z = fmaxf(a.z, b.z);
+      s.w = fmaxf(a.w, b.w);
+    } else {
+      s.x = add_up(a.x, b.x);
+      s.y = add_up(a.y, b.y);
+      s.z = add_up(a.z, b.z);
+      s.w = add_up(a.w, b.w);
+    }
     *reinterpret_cast<float4*>(parent + j * dp + k) = s;
   }
 }
@@ -246,10 +257,14 @@ hipError_t launch_ingest(const void* src, int dtype, int64_t rows, int d, int dp
 }
 
 hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, int dp,
-                              int64_t first, hipStream_t s) {
+                              int64_t first, hipStream_t s, bool max_pool) {
   if (nodes <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_level, dim3(grid_for(nodes * (dp / 4), 256)), dim3(256), 0, s, child,
-                     parent, first, nodes, dp);
+  if (max_pool)
+    hipLaunchKernelGGL(k_build_level<true>, dim3(grid_for(nodes * (dp / 4), 256)), dim3(256), 0, s,
+                       child, parent, first, nodes, dp);
+  else
+    hipLaunchKernelGGL(k_build_level<false>, dim3(grid_for(nodes * (dp / 4), 256)), dim3(256), 0, s,
+                       child, parent, first, nodes, dp);
   return hipGetLastError();
 }
 

@@ -21,8 +21,9 @@ STATUS_NAMES = {0: "GT_OK", 1: "GT_ERR_INVALID_ARG", 2: "GT_ERR_INVALID_INPUT",
                 3: "GT_ERR_OUT_OF_MEMORY", 4: "GT_ERR_CAPACITY", 5: "GT_ERR_RESULT_OVERFLOW",
                 6: "GT_ERR_DEVICE"}
 GT_F32, GT_F16, GT_BF16 = 0, 1, 2
-POOL_F32, POOL_BF16, POOL_FP8 = 1, 2, 4
-POOLS = {"f32": POOL_F32, "bf16": POOL_BF16, "fp8": POOL_FP8}
+POOL_F32, POOL_BF16, POOL_FP8, POOL_MAX_F32, POOL_MAX_BF16 = 1, 2, 4, 8, 16
+POOLS = {"f32": POOL_F32, "bf16": POOL_BF16, "fp8": POOL_FP8,
+         "max_f32": POOL_MAX_F32, "max_bf16": POOL_MAX_BF16}
 GT_MAX_LEVELS = 40
 
 EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_exhaustive", "gt_batch_create",
@@ -228,7 +229,8 @@ class GTIndex:
         st = self.stats()
         if count is None:
             count = (1 << level) - first
-        dt = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}[pool]
+        dt = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8,
+              "max_f32": np.float32, "max_bf16": np.uint16}[pool]
         out = np.empty((count, st["d_pad"]), dtype=dt)
         _check(lib().gt_read_pools(self._h, level, first, count, POOLS[pool],
                                    ctypes.c_void_p(out.ctypes.data)))

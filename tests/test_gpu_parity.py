@@ -383,3 +383,96 @@ def test_subtraction_step_agrees(gtmod, ws):
                         f"walk_subtract={ws} after insert rho={rho}")
     finally:
         idx.close()
+
+
+# ------------------------------------------------------------ Our-Max pools
+MAX_POOLS = ("f32", "bf16", "max_f32", "max_bf16")
+
+
+def test_max_pool_tree_is_the_elementwise_maximum(gtmod):
+    """Our-Max pools (paper Sec. 3): every stored float32 max pool equals the
+    element-wise maximum of its members (the oracle's max tree, exactly), and
+    the bfloat16 copy is the least bfloat16 >= it (values below 2^-126
+    raised to 2^-126, as for sum pools)."""
+    w = synth.workload_small(3000, 72, 4, temp=0.25, seed_offset=20)
+    F = np.asarray(w.feats)
+    idx = gtmod.GTIndex(_dev(F), pools=MAX_POOLS)
+    st = idx.stats()
+    D = st["depth"]
+    lv = pools.max_pool_tree(F)
+    bvals, _ = formats.bf16_nonneg_values()
+    for level in range(D + 1):
+        say(f"max pools level {level}")
+        m = idx.read_pools(level, pool="max_f32")[:, :72]
+        np.testing.assert_array_equal(m.astype(np.float64), lv[level])
+        if level == D:
+            continue
+        mf = idx.read_pools(level, pool="max_f32")
+        b = idx.read_pools(level, pool="max_bf16").astype(np.uint32)
+        bv = (b << 16).view(np.float32).astype(np.float64)
+        want = np.maximum(mf.astype(np.float64), np.where(mf > 0, 2.0 ** -126, 0.0))
+        np.testing.assert_array_equal(bv, bvals[formats.least_geq(want, bvals)])
+    idx.close()
+
+
+@pytest.mark.parametrize("dense_last", [-2, -1, "deepest"])
+def test_max_pool_walk_agrees(gtmod, dense_last):
+    """The walk over Our-Max pools returns the oracle's set for float32 and
+    bfloat16 max pools, with and without dense steps, on softmax data with
+    planted neighbours, a ragged row count and per-query thresholds."""
+    w = synth.workload_small(20077, 300, 203, temp=0.2, seed_offset=21)
+    F = np.asarray(w.feats)
+    idx = gtmod.GTIndex(_dev(F), pools=MAX_POOLS)
+    depth = idx.stats()["depth"]
+    idx.set_option("dense_last", depth - 1 if dense_last == "deepest" else dense_last)
+    q = _dev(w.queries)
+    try:
+        rhos = [0.6, 0.9, np.linspace(0.7, 0.97, len(w.queries))]
+        for rho in rhos:
+            ora = ob.range_search(F, w.queries, rho)
+            for f in ("max_f32", "max_bf16"):
+                say(f"max pools {f} dense_last={dense_last}")
+                assert_same(idx.query(q, rho, pool=f).to_lists(), ora, f"{f} dense_last={dense_last}")
+                assert idx.stats()["last_format"] == gtmod.POOLS[f]
+    finally:
+        idx.close()
+
+
+def test_max_pool_inserts_equal_rebuild(gtmod):
+    """Inserts update the max pools on the new rows' root-to-leaf paths: the
+    tree equals a fresh build and queries match the oracle."""
+    w = synth.workload_small(5000, 80, 20, temp=0.25, seed_offset=22)
+    F = np.asarray(w.feats)
+    idx = gtmod.GTIndex(_dev(F[:1700]), capacity=8192, pools=MAX_POOLS)
+    lo = 1700
+    for g in (1, 333, 2966):
+        idx.insert(_dev(F[lo:lo + g]))
+        lo += g
+    fresh = gtmod.GTIndex(_dev(F), capacity=8192, pools=MAX_POOLS)
+    for level in range(idx.stats()["depth"]):
+        np.testing.assert_array_equal(idx.read_pools(level, pool="max_f32"),
+                                      fresh.read_pools(level, pool="max_f32"))
+        np.testing.assert_array_equal(idx.read_pools(level, pool="max_bf16"),
+                                      fresh.read_pools(level, pool="max_bf16"))
+    q = _dev(w.queries)
+    ora = ob.range_search(F, w.queries, 0.85)
+    for f in ("max_f32", "max_bf16"):
+        say(f"max insert {f}")
+        assert_same(idx.query(q, 0.85, pool=f).to_lists(), ora, f"max insert {f}")
+    idx.close()
+    fresh.close()
+
+
+def test_max_pools_clustered_near_duplicates(gtmod):
+    """The clustered stress workload (thousands of neighbours per query for a
+    tenth of the queries, per-query thresholds) through the max-pool walk."""
+    w = synth.workload4()
+    ora = ob.range_search(w.feats, w.queries, w.rho)
+    idx = gtmod.GTIndex(_dev(w.feats), pools=MAX_POOLS)
+    q = _dev(w.queries, torch.float32)
+    try:
+        for f in ("max_f32", "max_bf16"):
+            say(f"clusters {f}")
+            assert_same(idx.query(q, w.rho, pool=f).to_lists(), ora, f"clusters {f}")
+    finally:
+        idx.close()
