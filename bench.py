@@ -273,6 +273,35 @@ def main():
         "unique_rows_per_level": {l: uniq[l] for l in range(h + 1, D + 1)},
     }
 
+    # ---- the TNE cost model (paper Sec. 5, Eq. 3) against the walk: lambda
+    # fitted to a sample of this workload's similarities, predicted pools per
+    # query surviving each level vs the walk's own counts
+    from paper_2311_02573_amd import costmodel as cm
+
+    rs = np.random.default_rng(0)
+    rows = rs.choice(w.n, size=min(w.n, 65536), replace=False)
+    sims = (np.asarray(w.feats[np.sort(rows)], np.float64) @ np.asarray(w.queries[:16], np.float64).T).ravel()
+    lam_m = cm.fit_lambda(np.clip(sims, 0.0, 1.0))
+    lam_h = cm.fit_lambda_loghist(sims)
+    pm = cm.level_survivors(w.n, args.rho, lam_m, D)
+    ph = cm.level_survivors(w.n, args.rho, lam_h, D)
+    meas = {l: su["pairs"][l + 1] / (2.0 * args.nq) for l in range(first_sparse, D - 1)}
+    meas[D - 1] = su["leaf_pairs"] / args.nq
+    meas[D] = su["results"] / args.nq
+    cost_model = {
+        "sample": "16 queries x 65,536 random rows of this workload",
+        "lambda_moment_fit": round(lam_m, 2),
+        "lambda_loghist_fit": round(lam_h, 2),
+        "E_rho_eq3": {"moment": round(cm.expected_tests(w.n, args.rho, lam_m), 1),
+                      "loghist": round(cm.expected_tests(w.n, args.rho, lam_h), 1)},
+        "survivors_per_query": {l: {"moment": round(pm[l], 1), "loghist": round(ph[l], 1),
+                                    "measured": round(meas[l], 1)} for l in sorted(meas)},
+    }
+    log(f"cost model: lambda {lam_m:.1f} (moments) / {lam_h:.1f} (log histogram); survivors "
+        "per query predicted/predicted/measured " +
+        ", ".join(f"L{l} {v['moment']}/{v['loghist']}/{v['measured']}"
+                  for l, v in cost_model["survivors_per_query"].items()))
+
     sweep = None
     if args.sweep_dense:
         sweep = {}
@@ -395,6 +424,7 @@ def main():
         "comparators": comparators,
         "cpu_baseline": cpu,
     }
+    out["cost_model"] = cost_model
     if sweep is not None:
         out["dense_last_sweep_ms"] = sweep
     if sub_sweep is not None:
