@@ -286,7 +286,7 @@ def main():
     pm = cm.level_survivors(w.n, args.rho, lam_m, D)
     ph = cm.level_survivors(w.n, args.rho, lam_h, D)
     meas = {l: su["pairs"][l + 1] / (2.0 * args.nq) for l in range(first_sparse, D - 1)}
-    meas[D - 1] = su["leaf_pairs"] / args.nq
+    meas[D - 1] = su["leaf_pairs"] / (2.0 * args.nq)   # two vectors tested per pool
     meas[D] = su["results"] / args.nq
     cost_model = {
         "sample": "16 queries x 65,536 random rows of this workload",

@@ -495,9 +495,10 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
 // bounds too.  Halves the pool rows read per level.
 constexpr int kSubGroup = 32;  // entries per wave step
 constexpr int kSubPipe = 4;   // 64-byte steps of a lane's two rows fetched ahead
+constexpr int kSubThreads = kWalkThreads;  // threads per workgroup
 
 template <int NSTEPS, int PIPE>
-__global__ __launch_bounds__(kWalkThreads, 1) void k_walk_sub(WalkLevelArgs a) {
+__global__ __launch_bounds__(kSubThreads, 1) void k_walk_sub(WalkLevelArgs a) {
   constexpr int FMT = GT_POOL_BF16;
   using F = WalkFmt<FMT>;
   constexpr int TQ = F::TQ;
@@ -584,18 +585,18 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_sub(WalkLevelArgs a) {
           reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)t * TQ * rowbytes;
       const int vec_per_row = rowbytes / 16;
       const int nvec = TQ * vec_per_row;
-      for (int v0 = 0; v0 < nvec; v0 += 8 * kWalkThreads) {
+      for (int v0 = 0; v0 < nvec; v0 += 8 * kSubThreads) {
         uint4 buf[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const int v = v0 + k * kWalkThreads + tid;
+          const int v = v0 + k * kSubThreads + tid;
           const int vv = v < nvec ? v : nvec - 1;
           const int row = vv / vec_per_row, col = vv - row * vec_per_row;
           buf[k] = *reinterpret_cast<const uint4*>(src + (size_t)row * rowbytes + col * 16);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const int v = v0 + k * kWalkThreads + tid;
+          const int v = v0 + k * kSubThreads + tid;
           if (v < nvec) {
             const int row = v / vec_per_row, col = v - row * vec_per_row;
             *reinterpret_cast<uint4*>(qlds + row * rs + col * 16) = buf[k];
@@ -1609,9 +1610,9 @@ hipError_t launch_walk_sub(const WalkLevelArgs& a, int grid, hipStream_t s) {
       a.level + 1 >= a.depth || a.depth > 32)
     return hipErrorInvalidValue;
   if (a.dp * 2 / 64 == 32)
-    hipLaunchKernelGGL((k_walk_sub<32, kSubPipe>), dim3(grid), dim3(kWalkThreads), 0, s, a);
+    hipLaunchKernelGGL((k_walk_sub<32, kSubPipe>), dim3(grid), dim3(kSubThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((k_walk_sub<0, kSubPipe>), dim3(grid), dim3(kWalkThreads), 0, s, a);
+    hipLaunchKernelGGL((k_walk_sub<0, kSubPipe>), dim3(grid), dim3(kSubThreads), 0, s, a);
   return hipGetLastError();
 }
 
