@@ -524,7 +524,7 @@ gt_status enqueue_place(Batch* b, int64_t lim, int64_t* ids, float* sims) {
 gt_status enqueue_tail(Index* ix, Batch* b) {
   hipStream_t s = b->stream;
   HIPCHK(gt::launch_recheck(b->hits, b->band_idx, &b->ctr->nband, (unsigned long long)b->hit_cap,
-                            b->qf, ix->leaves, ix->d, ix->dp, b->qq, ix->ff, b->rho, b->qcount,
+                            b->qf, ix->leaves, ix->d, ix->dp, ix->ff, b->rho, b->qcount,
                             b->ctr, s));
   ev_mark(b, 4);
   HIPCHK(gt::launch_scan_offsets(b->qcount, b->nq, b->offs, nullptr, b->ctr, s));

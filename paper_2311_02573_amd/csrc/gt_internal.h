@@ -274,7 +274,7 @@ hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s);
 hipError_t launch_dense_level(int fmt, const DenseLevelArgs& a, hipStream_t s);
 hipError_t launch_recheck(Hit* hits, const uint32_t* band_idx, const unsigned long long* nband,
                           unsigned long long cap, const float* qf, const float* leaves, int d,
-                          int dp, const double* qq, const double* ff, const double* rho,
+                          int dp, const double* ff, const double* rho,
                           unsigned int* qcount, DevCounters* ctr, hipStream_t s);
 hipError_t launch_scan_offsets(const unsigned int* qcount, int nq, int64_t* offs_internal,
                                int64_t* offs_out, DevCounters* ctr, hipStream_t s);

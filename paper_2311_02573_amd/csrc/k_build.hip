@@ -146,8 +146,7 @@ __global__ __launch_bounds__(256) void k_query_prep(
     const float* __restrict__ root, float* sabs, unsigned int* err) {
   __shared__ float qs[4096];
   __shared__ float red[4];
-  __shared__ double l1red[4];
-  __shared__ double qq_s;
+  __shared__ double l1red[4], l2red[4];
   const int b = blockIdx.x, t = threadIdx.x;
   const bool real = b < nq;
   float mx = 0.0f;
@@ -164,22 +163,23 @@ __global__ __launch_bounds__(256) void k_query_prep(
   for (int k = t; k < d; k += blockDim.x) l1 += (double)qs[k];
   if (root)
     for (int k = t; k < dp; k += blockDim.x) l1 += (double)root[k];
+  // |q|^2 by a fixed-order parallel sum (deterministic, relative error below
+  // 2^-40 for d <= 4096; the thresholds' slack covers far more).  The
+  // canonical sequential sum, which the float64 recheck needs bit for bit,
+  // is formed there for the few candidates that reach it.
+  double l2 = 0.0;
+  for (int k = t; k < d; k += blockDim.x) l2 = __fma_rn((double)qs[k], (double)qs[k], l2);
   for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
   for (int o = 32; o >= 1; o >>= 1) l1 += __shfl_xor(l1, o, 64);
+  for (int o = 32; o >= 1; o >>= 1) l2 += __shfl_xor(l2, o, 64);
   if ((t & 63) == 0) {
     red[t >> 6] = mx;
     l1red[t >> 6] = l1;
+    l2red[t >> 6] = l2;
   }
   __syncthreads();
-  if (t == 0) {
-    double acc = 0.0;
-    for (int k = 0; k < d; ++k) acc = __dadd_rn(acc, __dmul_rn((double)qs[k], (double)qs[k]));
-    qq_s = acc;
-    red[0] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-  }
-  __syncthreads();
-  const double qq = qq_s;
-  const float qmax = red[0];
+  const double qq = (l2red[0] + l2red[1]) + (l2red[2] + l2red[3]);
+  const float qmax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
   // float8 query scale 2^e with qmax / 2^e in (224, 448]
   int e = 0;
   if (qmax > 0.0f) {

@@ -1326,15 +1326,15 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
 }
 
 // Candidates within 1e-5 of rho are re-decided with the canonical float64
-// cosine, bit-identical to the oracle: the sum runs sequentially over k, lane
-// by lane (lane l holds elements [16 l, 16 l + 16) of each 1024-chunk, so lane
-// order is k order), one wave per candidate.
+// cosine, bit-identical to the oracle: the dot product and the query's squared
+// norm run sequentially over k, lane by lane (lane l holds elements
+// [16 l, 16 l + 16) of each 1024-chunk, so lane order is k order), one wave
+// per candidate; the rows' squared norms are the canonical ones of ingest.
 __global__ __launch_bounds__(256) void k_recheck(Hit* hits, const uint32_t* band_idx,
                                                  const unsigned long long* nband,
                                                  unsigned long long cap,
                                                  const float* __restrict__ qf,
                                                  const float* __restrict__ leaves, int d, int dp,
-                                                 const double* __restrict__ qq,
                                                  const double* __restrict__ ff,
                                                  const double* __restrict__ rho,
                                                  unsigned int* qcount, DevCounters* ctr) {
@@ -1346,7 +1346,9 @@ __global__ __launch_bounds__(256) void k_recheck(Hit* hits, const uint32_t* band
     Hit x = hits[hi];
     const float* q = qf + (size_t)x.q * dp;
     const float* f = leaves + (size_t)x.id * dp;
-    double s = 0.0;
+    // dot = sum q_k f_k and qq = sum q_k^2, both sequential over k (two
+    // independent chains in step)
+    double s = 0.0, sq = 0.0;
     for (int c = 0; c * 1024 < dp; ++c) {
       const int base = c * 1024 + 16 * lane;
       float qv[16], fv[16];
@@ -1355,17 +1357,22 @@ __global__ __launch_bounds__(256) void k_recheck(Hit* hits, const uint32_t* band
         qv[j] = base + j < d ? q[base + j] : 0.0f;
         fv[j] = base + j < d ? f[base + j] : 0.0f;
       }
+      // (values past d are zero: fma(0, 0, s) = s, so no branch splits the
+      // two chains)
       for (int L = 0; L < 64; ++L) {
         if (lane == L) {
 #pragma unroll
-          for (int j = 0; j < 16; ++j)
-            if (base + j < d) s = __fma_rn((double)qv[j], (double)fv[j], s);
+          for (int j = 0; j < 16; ++j) {
+            s = __fma_rn((double)qv[j], (double)fv[j], s);
+            sq = __fma_rn((double)qv[j], (double)qv[j], sq);
+          }
         }
         s = __shfl(s, L, 64);
+        sq = __shfl(sq, L, 64);
       }
     }
     if (lane == 0) {
-      const double cs = __ddiv_rn(s, __dmul_rn(__dsqrt_rn(qq[x.q]), __dsqrt_rn(ff[x.id])));
+      const double cs = __ddiv_rn(s, __dmul_rn(__dsqrt_rn(sq), __dsqrt_rn(ff[x.id])));
       atomicAdd(&ctr->rechecked, 1ull);
       if (cs >= rho[x.q]) {
         x.flag = HIT_ACCEPT | accept_slot(&qcount[x.q], ctr);
@@ -1649,10 +1656,10 @@ hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s) {
 
 hipError_t launch_recheck(Hit* hits, const uint32_t* band_idx, const unsigned long long* nband,
                           unsigned long long cap, const float* qf, const float* leaves, int d,
-                          int dp, const double* qq, const double* ff, const double* rho,
+                          int dp, const double* ff, const double* rho,
                           unsigned int* qcount, DevCounters* ctr, hipStream_t s) {
   hipLaunchKernelGGL(k_recheck, dim3(64), dim3(256), 0, s, hits, band_idx, nband, cap, qf, leaves, d,
-                     dp, qq, ff, rho, qcount, ctr);
+                     dp, ff, rho, qcount, ctr);
   return hipGetLastError();
 }
 
