@@ -643,10 +643,14 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   if (nq > 0) {
     memcpy(b->h_rho, rho, (size_t)nq * 8);
     HIPCHK(hipMemcpyAsync(b->rho, b->h_rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(gt::launch_query_prep(q, nq, ix->d, ix->dp, tq, b->rho, ix->d_mmin, b->qf, b->qbf,
-                                 b->q8, b->qexp, b->invn_q, b->qq, b->thr, b->thr_gemm,
-                                 b->tile_mask, ix->master + level_row(0) * ix->dp, b->sabs,
-                                 &b->ctr->err, nq_pad, s));
+    // reduced query copies only for the call's pool format; the absolute
+    // terms of the subtraction step only for bfloat16 sum pools
+    const bool w16 = kind == 1 && fmt == GT_POOL_BF16, w8 = kind == 1 && fmt == GT_POOL_FP8E4M3;
+    HIPCHK(gt::launch_query_prep(q, nq, ix->d, ix->dp, tq, b->rho, ix->d_mmin, b->qf,
+                                 w16 ? b->qbf : nullptr, w8 ? b->q8 : nullptr, b->qexp, b->invn_q,
+                                 b->qq, b->thr, b->thr_gemm, b->tile_mask,
+                                 w16 && !maxp ? ix->master + level_row(0) * ix->dp : nullptr,
+                                 w16 && !maxp ? b->sabs : nullptr, &b->ctr->err, nq_pad, s));
   }
   ev_mark(b, 1);
   if (nq > 0 && ix->n > 0) {

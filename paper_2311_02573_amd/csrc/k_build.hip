@@ -190,8 +190,8 @@ __global__ __launch_bounds__(256) void k_query_prep(
   for (int k = t; k < dp; k += blockDim.x) {
     const float v = k < d ? qs[k] : 0.0f;
     qf[(int64_t)b * dp + k] = v;
-    qbf[(int64_t)b * dp + k] = bf16_up(v);
-    q8[(int64_t)b * dp + k] = (uint8_t)e4m3_up(ldexp((double)v, -e));
+    if (qbf) qbf[(int64_t)b * dp + k] = bf16_up(v);
+    if (q8) q8[(int64_t)b * dp + k] = (uint8_t)e4m3_up(ldexp((double)v, -e));
   }
   if (t == 0) {
     const bool live = real && qq > 0.0 && !bad;
