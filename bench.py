@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--walk-subtract", type=int, default=-1,
                     help="subtraction step of the bfloat16 walk: 0 off, 1 every sparse level, "
                          "2 all but the last, -1 automatic")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="headline: 1 = two workspaces on one stream; N > 1 = N workspaces, "
+                         "one stream each")
     ap.add_argument("--sweep-subtract", action="store_true",
                     help="also time the walk with each subtraction setting")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
@@ -151,21 +154,27 @@ def main():
         wall = time.perf_counter() - t_start
         return res, wall, lat
 
-    def run_pipelined(pool, steps, warmup):
-        # Two workspaces on one stream: batch k+1 is enqueued before the host
-        # waits for batch k, so the host's per-call work overlaps the device's
-        # and the device runs the batches back to back, in order.
-        ws = [gt.Workspace(idx, args.nq, stream=torch.cuda.current_stream()) for _ in range(2)]
+    def run_pipelined(pool, steps, warmup, streams=1):
+        # W = max(2, streams) workspaces: batch k is enqueued before the host
+        # waits for batch k - W + 1, so the host's per-call work overlaps the
+        # device's.  On one stream the device runs the batches back to back,
+        # in order; with a stream per workspace a batch's first kernels may
+        # also run while the previous batches' last ones finish.
+        W = max(2, streams)
+        ws = [gt.Workspace(idx, args.nq, stream=torch.cuda.current_stream() if streams == 1 else None)
+              for _ in range(W)]
 
         def go(n):
-            ws[0].submit(q, args.rho, pool=pool)
             r = None
-            for k in range(1, n):
-                ws[k % 2].submit(q, args.rho, pool=pool)
-                r = ws[(k - 1) % 2].finish()
-            return ws[(n - 1) % 2].finish()
+            for k in range(n):
+                ws[k % W].submit(q, args.rho, pool=pool)
+                if k >= W - 1:
+                    r = ws[(k - W + 1) % W].finish()
+            for k in range(max(0, n - W + 1), n):
+                r = ws[k % W].finish()
+            return r
 
-        go(max(2, warmup))
+        go(max(W, warmup))
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         r = go(steps)
@@ -176,7 +185,7 @@ def main():
         return r, wall
 
     # ---- headline: the walk on the chosen pool format, batches back to back
-    res_p, wall = run_pipelined(args.pool, args.steps, args.warmup)
+    res_p, wall = run_pipelined(args.pool, args.steps, args.warmup, args.streams)
     ms_step = wall / args.steps * 1e3
     qps = args.nq * args.steps / wall
     log(f"{args.pool} walk: {ms_step:.3f} ms/batch, {qps:.0f} queries/s, {res_p.total} results")
@@ -417,6 +426,7 @@ def main():
         "latency_ms": {"p50": round(pct(lat, 50), 4), "p99": round(pct(lat, 99), 4)},
         "one_call_at_a_time_qps": round(qps_sync, 1),
         "pipelined_results_identical": bool(same_p),
+        "pipeline": {"workspaces": max(2, args.streams), "streams": args.streams},
         "results_per_batch": res.total,
         "recall_vs_exhaustive": recall,
         "index_build_ms": round(build_s * 1e3, 1),
