@@ -103,7 +103,7 @@ def main():
                     help="length of each loaded serving run (0: no serving leg)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU (this build has no multi-GPU path); use --gpus 1",
+        print("bench.py runs on exactly one GPU (the library has no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
