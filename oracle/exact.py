@@ -15,6 +15,10 @@ Everything here works on Python Fractions, so no rounding is involved:
   zero padding, testing both children of every surviving pool directly.
 * `levelwise_walk_max`: that walk with Our-Max pools (Sec. 3), each pool the
   element-wise maximum of its members.
+* `levelwise_walk_signed`: the extension of Our-Max to descriptors with
+  negative values (Sec. 3): a pool keeps the element-wise maximum and minimum
+  of its members and is scored with the maximum where the query component is
+  non-negative and the minimum where it is negative.
 
 The binary-splitting and level-wise walks are the paper's method, kept here to
 show that it returns exactly the brute-force set; the GPU path is compared with
@@ -194,3 +198,60 @@ def levelwise_walk_max(F, q, rho, capacity: int | None = None):
         frontier = nxt
     return sorted(i for i in frontier if i < N), tests
 
+
+
+def signed_pool_score(q, mx, mn):
+    """Score of a max/min pool (Sec. 3, negative descriptors): sum over k of
+    q_k * max_k where q_k >= 0 and q_k * min_k where q_k < 0.  Each term is the
+    largest value q_k * f_k takes over the members, so the score bounds every
+    member's q.f from above."""
+    s = Fraction(0)
+    for x, hi, lo in zip(q, mx, mn):
+        s += x * (hi if x >= 0 else lo)
+    return s
+
+
+def levelwise_walk_signed(F, q, rho, capacity: int | None = None):
+    """The level-by-level walk over max/min pools of vectors of any sign (Sec.
+    3, negative descriptors), over a power-of-two capacity.  A pool holds the
+    element-wise maximum and minimum over its members; padding slots past N
+    are not members, and a pool with no member is never tested positive.  Both
+    children of each surviving pool are tested with `signed_pool_score`; a leaf
+    (one vector: its own maximum and minimum) is a member iff q.f >= rho.
+    Returns (ids, tests per level)."""
+    N = len(F)
+    if N == 0:
+        return [], []
+    cap = capacity or 1 << max(0, (N - 1).bit_length())
+    assert cap >= N and cap & (cap - 1) == 0
+    qf = [Fraction(float(x)) for x in q]
+    rows = [[Fraction(float(x)) for x in f] for f in F]
+    # each level: list of (max, min) per node, None for a node with no member
+    levels = [[(r, r) for r in rows] + [None] * (cap - N)]
+    while len(levels[0]) > 1:
+        below = levels[0]
+        up = []
+        for j in range(len(below) // 2):
+            a, b = below[2 * j], below[2 * j + 1]
+            if a is None or b is None:
+                up.append(a if b is None else b)
+            else:
+                up.append(([max(x, y) for x, y in zip(a[0], b[0])],
+                           [min(x, y) for x, y in zip(a[1], b[1])]))
+        levels.insert(0, up)
+    r = Fraction(float(rho))
+
+    def live(node):
+        return node is not None and signed_pool_score(qf, node[0], node[1]) >= r
+
+    frontier = [0] if live(levels[0][0]) else []
+    tests = [1]
+    for lvl in range(1, len(levels)):
+        nxt = []
+        for p in frontier:
+            for c in (2 * p, 2 * p + 1):
+                if live(levels[lvl][c]):
+                    nxt.append(c)
+        tests.append(2 * len(frontier))
+        frontier = nxt
+    return sorted(frontier), tests

@@ -68,3 +68,39 @@ def max_pool_tree(feats, capacity: int | None = None):
         levels.insert(0, np.maximum(below[0::2], below[1::2]))
     return levels
 
+
+
+def max_min_pool_tree(feats, capacity: int | None = None):
+    """Max/min pools for vectors of any sign (Sec. 3, negative descriptors):
+    (maxes, mins), each a list of float64 levels [2^l, d] like `pool_tree`;
+    node j holds the element-wise maximum / minimum over its members (exact).
+    Padding slots past N are not members: a node without members holds -inf
+    in `maxes` and +inf in `mins`."""
+    f = np.asarray(feats, dtype=np.float64)
+    n, d = f.shape
+    cap = capacity or 1 << max(0, (n - 1).bit_length())
+    assert cap >= n and cap & (cap - 1) == 0
+    hi = np.full((cap, d), -np.inf)
+    lo = np.full((cap, d), np.inf)
+    hi[:n] = f
+    lo[:n] = f
+    maxes, mins = [hi], [lo]
+    while maxes[0].shape[0] > 1:
+        maxes.insert(0, np.maximum(maxes[0][0::2], maxes[0][1::2]))
+        mins.insert(0, np.minimum(mins[0][0::2], mins[0][1::2]))
+    return maxes, mins
+
+
+def signed_pool_scores(maxes, mins, q):
+    """Per level, the max/min pool score of every node for query q (float64):
+    sum_k q_k max_k over q_k >= 0 plus q_k min_k over q_k < 0 (-inf for a node
+    without members)."""
+    qv = np.asarray(q, dtype=np.float64)
+    pos, neg = np.maximum(qv, 0.0), np.minimum(qv, 0.0)
+    out = []
+    for hi, lo in zip(maxes, mins):
+        with np.errstate(invalid="ignore"):
+            a = np.where(pos > 0, hi, 0.0) @ pos + np.where(neg < 0, lo, 0.0) @ neg
+        a[np.isinf(hi).all(axis=1)] = -np.inf
+        out.append(a)
+    return out

@@ -207,6 +207,114 @@ def test_max_pool_tree_invariants_on_softmax_data():
             assert np.all(mx[level] @ q >= leaf.reshape(-1, span).max(axis=1) * (1 - 1e-12))
 
 
+def _rand_signed(rng, n, d, zero_frac=0.2):
+    a = (rng.random((n, d)) * 2.0 - 1.0).astype(np.float32)
+    a[rng.random((n, d)) < zero_frac] = 0.0
+    return a
+
+
+def _signed_brute(F, q, rho):
+    qf = [Fraction(float(x)) for x in q]
+    return [i for i in range(len(F))
+            if exact.dot(qf, [Fraction(float(x)) for x in F[i]]) >= Fraction(float(rho))]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16])
+def test_signed_walk_equals_brute_force(n):
+    """Sec. 3, negative descriptors: with max/min pools scored by the maximum
+    where q_k >= 0 and the minimum where q_k < 0, every member's q.f is at most
+    its pool's score, so the walk returns exactly {i : q.f_i >= rho} for
+    vectors and thresholds of any sign."""
+    rng = np.random.default_rng(500 + n)
+    for trial in range(5):
+        d = 1 + trial % 4
+        F = _rand_signed(rng, n, d)
+        q = _rand_signed(rng, 1, d, 0.1)[0]
+        for rho in (-0.3, 0.0, 0.1, 0.4, 0.8):
+            got, tests = exact.levelwise_walk_signed(F, q, rho)
+            assert got == _signed_brute(F, q, rho), (n, trial, rho)
+            assert tests[0] == 1 and all(t % 2 == 0 for t in tests[1:])
+
+
+@pytest.mark.parametrize("n", [2, 5, 8, 13])
+def test_signed_walk_reduces_to_max_walk_on_nonnegative_data(n):
+    """For non-negative vectors and queries the minimum is never used, so the
+    signed walk is the Our-Max walk: same ids and the same tests per level
+    (rho > 0, where a zero-padded max pool and a pool without members are both
+    pruned)."""
+    rng = np.random.default_rng(600 + n)
+    for trial in range(4):
+        d = 1 + trial % 3
+        F = _rand_nonneg(rng, n, d, 0.25)
+        q = _rand_nonneg(rng, 1, d, 0.1)[0]
+        for rho in (0.05, 0.3, 0.7):
+            assert exact.levelwise_walk_signed(F, q, rho) == exact.levelwise_walk_max(F, q, rho)
+
+
+def test_signed_walk_worked_example():
+    """A hand-worked case in R^2 (sim = q.f): f0 = (0, 1), f1 = (0, -1),
+    f2 = (3/5, -4/5), f3 = (-4/5, 3/5), q = (3/5, -4/5).  Member scores -0.8,
+    0.8, 1, -0.96.  Halves: {f0, f1} has max (0, 1) and min (0, -1), score
+    (3/5) 0 + (-4/5)(-1) = 0.8; {f2, f3} has max (3/5, 3/5) and min (-4/5,
+    -4/5), score 0.36 + 0.64 = 1.  At rho = 0.75 both halves survive and the
+    neighbours are f1 and f2 (tests 1, 2, 4); at rho = 0.9 the first half is
+    pruned (tests 1, 2, 2).  Scoring pools by their maxima alone would lose
+    both neighbours: the root's maximum (3/5, 1) scores 0.36 - 0.8 < 0."""
+    F = np.array([[0.0, 1.0], [0.0, -1.0], [0.6, -0.8], [-0.8, 0.6]])
+    q = np.array([0.6, -0.8])
+    assert exact.levelwise_walk_signed(F, q, 0.75) == ([1, 2], [1, 2, 4])
+    assert exact.levelwise_walk_signed(F, q, 0.9) == ([2], [1, 2, 2])
+    assert exact.levelwise_walk_max(F, q, 0.75) == ([], [1, 0, 0])
+    mx, mn = pools.max_min_pool_tree(F)
+    assert np.array_equal(mx[1], [[0.0, 1.0], [0.6, 0.6]])
+    assert np.array_equal(mn[1], [[0.0, -1.0], [-0.8, -0.8]])
+    sc = pools.signed_pool_scores(mx, mn, q)
+    assert np.allclose(sc[1], [0.8, 1.0]) and np.allclose(sc[0], [0.36 + 0.8])
+
+
+def test_signed_walk_without_the_minimum_is_caught(monkeypatch):
+    """Planted mistake: scoring a pool by its maximum alone (dropping the
+    minimum where q_k < 0) makes the brute-force pin fail."""
+    def max_only(q, mx, mn):
+        return exact.dot(q, mx)
+
+    monkeypatch.setattr(exact, "signed_pool_score", max_only)
+    with pytest.raises(AssertionError):
+        for n in (5, 8, 13, 16):
+            test_signed_walk_equals_brute_force(n)
+
+
+def test_max_min_tree_invariants_on_signed_data():
+    """Every max/min pool equals the element-wise maximum / minimum of its
+    members taken directly; its score bounds the largest member score; on
+    non-negative data the maxima of full nodes are the Our-Max pools."""
+    rng = np.random.default_rng(41)
+    F = _rand_signed(rng, 700, 12).astype(np.float64)
+    mx, mn = pools.max_min_pool_tree(F)
+    D = len(mx) - 1
+    for level in range(D + 1):
+        span = 1 << (D - level)
+        for j in range(0, 1 << level, max(1, (1 << level) // 7)):
+            a, b = j * span, min(len(F), (j + 1) * span)
+            if a < b:
+                assert np.array_equal(mx[level][j], F[a:b].max(axis=0))
+                assert np.array_equal(mn[level][j], F[a:b].min(axis=0))
+            else:
+                assert np.all(np.isneginf(mx[level][j])) and np.all(np.isposinf(mn[level][j]))
+    for q in _rand_signed(rng, 3, 12, 0.0).astype(np.float64):
+        sc = pools.signed_pool_scores(mx, mn, q)
+        leaf = np.full(1 << D, -np.inf)
+        leaf[:len(F)] = F @ q
+        for level in range(D):
+            span = 1 << (D - level)
+            assert np.all(sc[level] >= leaf.reshape(-1, span).max(axis=1) - 1e-12)
+    P = np.abs(F[:512])
+    mxp, _ = pools.max_min_pool_tree(P)
+    ref = pools.max_pool_tree(P)
+    for level in range(len(ref)):
+        assert np.array_equal(mxp[level], ref[level])
+
+
 def test_prefix_sum_pool_identity():
     """Sec. 2, Eq. 1: with cumulative sums C, the right half-pool of N rows is
     C_N - C_{floor(N/2)}; the explicit tree's node (level 1, index 1) equals it."""
