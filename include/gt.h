@@ -40,7 +40,10 @@ typedef enum {
   GT_OK = 0,
   GT_ERR_INVALID_ARG = 1,      /* bad size, pointer, dtype or format */
   GT_ERR_INVALID_INPUT = 2,    /* a NaN, infinite or negative value (the prune
-                                  rule needs non-negative vectors, Sec. 2) */
+                                  rule needs non-negative vectors, Sec. 2); for an
+                                  index built with GT_POOL_SIGNED, a NaN or
+                                  infinite value, or an inserted value beyond
+                                  the index's shift bound */
   GT_ERR_OUT_OF_MEMORY = 3,
   GT_ERR_CAPACITY = 4,         /* insert beyond the capacity given at build */
   GT_ERR_RESULT_OVERFLOW = 5,  /* more results than max_results; see queries */
@@ -56,13 +59,30 @@ typedef enum { GT_F32 = 0, GT_F16 = 1, GT_BF16 = 2 } gt_dtype; /* feature storag
  * (paper Sec. 3, Our-Max: a query scores a max pool at least as high as any
  * member, so the same prune rule holds), float32 (exact) and a bfloat16 copy
  * rounded upward; asking for GT_POOL_MAX_BF16 also builds GT_POOL_MAX_F32.
- * Bit mask at build time, one value per query call. */
+ * Bit mask at build time, one value per query call.
+ *
+ * GT_POOL_SIGNED (build-time flag only): vectors and queries may have values
+ * of any sign (paper Sec. 3, negative descriptors: a pool keeps the
+ * element-wise maximum and minimum of its members and a query scores it with
+ * the maximum where its component is >= 0 and the minimum where it is < 0,
+ * which bounds every member's dot product from above).  Sums no longer bound
+ * anything, so such an index keeps only the MAX formats (GT_POOL_MAX_F32
+ * always, GT_POOL_MAX_BF16 if asked; asking for a sum format is INVALID_ARG).
+ * Their rows are 2 x d_pad wide: pool row [max_k + B | B - min_k] over the
+ * members (columns k < d; zero past d and for a pool without members), B the
+ * smallest power of two >= the largest |value| at build (1 for an all-zero
+ * build), the additions rounded up.  A query q is walked as [max(q,0) |
+ * max(-q,0)] against the threshold tau + B |q|_1: the same test as the
+ * max/min score against tau, with every operand non-negative.  Limits: d <=
+ * 512; every rho > 0 (also for gt_exhaustive on such an index); inserted
+ * values must lie in [-B, B]. */
 typedef enum {
   GT_POOL_F32 = 1,
   GT_POOL_BF16 = 2,
   GT_POOL_FP8E4M3 = 4,
   GT_POOL_MAX_F32 = 8,
-  GT_POOL_MAX_BF16 = 16
+  GT_POOL_MAX_BF16 = 16,
+  GT_POOL_SIGNED = 32
 } gt_pool;
 
 #define GT_MAX_LEVELS 40
@@ -96,18 +116,23 @@ typedef struct {
   int64_t unique_rows[GT_MAX_LEVELS];
   int32_t dense_launches;  /* dense level steps of the last gt_query_batch */
   double ms_dense;         /* their device time (profiling on) */
+  int32_t pool_width;      /* row length of the MAX pools: d_pad, or 2 d_pad with
+                            * GT_POOL_SIGNED */
+  float shift_bound;       /* B of a GT_POOL_SIGNED index, else 0 */
 } gt_stats;
 
 /* Build the index (paper Sec. 2: pools of the binary-splitting tree, created
  * offline; explicit pool sums replace the prefix sums of Eq. 1).
- *   feats_dev  [n x d] features of type `dtype`; every value finite and >= 0.
+ *   feats_dev  [n x d] features of type `dtype`; every value finite and >= 0
+ *              (finite, of any sign, with GT_POOL_SIGNED).
  *   capacity   number of leaves; 0 = smallest power of two >= n, else a power
  *              of two >= n.  Room for later inserts.
  *   pool_formats  bit mask of gt_pool (GT_POOL_F32 is always built).
  * Copies the features; the index owns all its device memory until
  * gt_destroy.  Synchronises `stream` (validation result).  Errors:
  * INVALID_ARG (d < 1 or d > 4096, n < 0, n > capacity, capacity not a power of
- * two, dtype), INVALID_INPUT, OUT_OF_MEMORY, DEVICE. */
+ * two, dtype; with GT_POOL_SIGNED: d > 512 or a sum format asked for),
+ * INVALID_INPUT, OUT_OF_MEMORY, DEVICE. */
 gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dtype,
                         int64_t capacity, uint32_t pool_formats, void* stream,
                         gt_index** out);
@@ -124,8 +149,10 @@ gt_status gt_insert(gt_index* index, const void* feats_dev, int64_t n_new, void*
 
 /* Range query by the level-wise binary-splitting walk (paper Sec. 2, Alg. 1,
  * visited one level per round as analysed in Sec. 5).
- *   q_dev      [nq x d] float32 queries, finite and >= 0.
- *   rho_host   [nq] float64 thresholds.  rho <= 0 returns every non-zero row.
+ *   q_dev      [nq x d] float32 queries, finite and >= 0 (finite, of any
+ *              sign, on a GT_POOL_SIGNED index).
+ *   rho_host   [nq] float64 thresholds.  rho <= 0 returns every non-zero row
+ *              (INVALID_ARG on a GT_POOL_SIGNED index, where it must be > 0).
  *   fmt        pool format for the walk (must have been built).
  *   offsets_dev [nq + 1] int64: query b's results are ids[offsets[b] ..
  *              offsets[b+1]).
@@ -198,8 +225,11 @@ gt_status gt_get_stats(const gt_index* index, gt_stats* out);
  *   GT_POOL_BF16 -> uint16 bfloat16 codes, GT_POOL_FP8E4M3 -> uint8 e4m3 codes
  *   (value = decoded code * 2^fp8_exp[level], see gt_stats),
  *   GT_POOL_MAX_F32 -> float32 element-wise maxima (exact; level == depth gives
- *   the leaf rows), GT_POOL_MAX_BF16 -> their bfloat16 codes, rounded up.
- * host_out must hold count * d_pad elements of that type.  Synchronises the
+ *   the leaf rows), GT_POOL_MAX_BF16 -> their bfloat16 codes, rounded up; on a
+ *   GT_POOL_SIGNED index the MAX rows are the shifted max/min rows described
+ *   at gt_pool, pool_width (= 2 d_pad) values each.
+ * host_out must hold count * d_pad elements of that type (count * pool_width
+ * for MAX rows below the leaves).  Synchronises the
  * device.  Errors: INVALID_ARG (range, format not built), DEVICE. */
 gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int64_t count,
                         gt_pool fmt, void* host_out);

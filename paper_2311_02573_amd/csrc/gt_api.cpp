@@ -145,9 +145,10 @@ gt_status quantize_fp8_level(Index* ix, int level, hipStream_t s, bool recompute
 // ------------------------------------------------------------------ workspaces
 void free_query_arrays(Batch* b) {
   Index* ix = b->ix;
-  const size_t o = (size_t)b->nq_alloc, dp = (size_t)ix->dp;
+  const size_t o = (size_t)b->nq_alloc, dp = (size_t)ix->dp, pw = (size_t)ix->pw;
   dfree(ix, &b->qf, o * dp);
-  dfree(ix, &b->qbf, o * dp);
+  dfree(ix, &b->qw, o * pw);
+  dfree(ix, &b->qbf, o * pw);
   dfree(ix, &b->q8, o * dp);
   dfree(ix, &b->qexp, o);
   dfree(ix, &b->invn_q, o);
@@ -214,8 +215,10 @@ void free_tree(Index* ix) {
   dfree(ix, &ix->master, tree);
   dfree(ix, &ix->pbf16, tree);
   dfree(ix, &ix->pfp8, tree);
-  dfree(ix, &ix->mmax, tree);
-  dfree(ix, &ix->pmax16, tree);
+  const size_t mtree = (cap - 1) * (size_t)ix->pw;
+  dfree(ix, &ix->mmax, mtree);
+  dfree(ix, &ix->pmax16, mtree);
+  dfree(ix, &ix->d_absmax, 1);
   dfree(ix, &ix->d_lexp, GT_MAX_LEVELS);
   dfree(ix, &ix->d_levelmax, GT_MAX_LEVELS);
   dfree(ix, &ix->d_flags, GT_MAX_LEVELS);
@@ -242,7 +245,8 @@ gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
     free_query_arrays(b);
     const size_t nqa = (size_t)nq_pad;
     TRY(dalloc(ix, &b->qf, nqa * dp));
-    TRY(dalloc(ix, &b->qbf, nqa * dp));
+    if (ix->signed_mode) TRY(dalloc(ix, &b->qw, nqa * (size_t)ix->pw));
+    TRY(dalloc(ix, &b->qbf, nqa * (size_t)ix->pw));
     TRY(dalloc(ix, &b->q8, nqa * dp));
     TRY(dalloc(ix, &b->qexp, nqa));
     TRY(dalloc(ix, &b->invn_q, nqa));
@@ -339,8 +343,10 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   hipStream_t s = b->stream;
   const int f = b->fmt, nt = b->nt, D = ix->depth, h = b->head, dl = b->dense_last;
   const int grid = ix->grid > 0 ? ix->grid : ix->n_cu;
-  const size_t dp = (size_t)ix->dp;
-  const void* qtile = f == GT_POOL_F32 ? (const void*)b->qf
+  // pool row length: d_pad, or 2 d_pad for the shifted max/min rows of a
+  // signed index, whose walk queries are [max(q,0) | max(-q,0)]
+  const size_t dp = (size_t)(b->maxpool ? ix->pw : ix->dp);
+  const void* qtile = f == GT_POOL_F32 ? (const void*)(ix->signed_mode ? b->qw : b->qf)
                       : f == GT_POOL_BF16 ? (const void*)b->qbf : (const void*)b->q8;
   const size_t esz = f == GT_POOL_F32 ? 4 : f == GT_POOL_BF16 ? 2 : 1;
   const unsigned char* pool_base =
@@ -388,7 +394,7 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
       a.rows = std::max<int64_t>(1, std::min<int64_t>(int64_t(1) << L,
                                                      (b->n_epoch + (int64_t(1) << (D - L)) - 1) >> (D - L)));
       a.nt = nt;
-      a.dp = ix->dp;
+      a.dp = (int)dp;
       a.nb = b->nb;
       a.bcap = b->fr_cap >> b->nb;
       a.child_rows = pool_base + (size_t)level_row(L) * dp * esz;
@@ -418,7 +424,7 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
     a.level = l;
     a.dense = (l == h);
     a.nt = nt;
-    a.dp = ix->dp;
+    a.dp = (int)dp;
     a.nb = b->nb;
     a.bcap = b->fr_cap >> b->nb;
     a.child_rows = pool_base + (size_t)level_row(l + 1) * dp * esz;
@@ -589,11 +595,15 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
       return fail(GT_ERR_INVALID_ARG, "unknown pool format");
     if (!(ix->formats & (uint32_t)user_fmt))
       return fail(GT_ERR_INVALID_ARG, "pool format was not built");
-    if (ix->dp > maxdp_of(fmt))
+    if ((maxp ? ix->pw : ix->dp) > maxdp_of(fmt))
       return fail(GT_ERR_INVALID_ARG, "d too large for this pool format (padded d <= " +
                                           std::to_string(maxdp_of(fmt)) + ")");
   }
   TRY(check_query_args(ix, q, nq, rho, tq));
+  if (ix->signed_mode)
+    for (int i = 0; i < nq; ++i)
+      if (!(rho[i] > 0.0))
+        return fail(GT_ERR_INVALID_ARG, "rho must be > 0 on an index of signed vectors");
   const int nt = (nq + tq - 1) / tq;
   const int nq_pad = std::max(128, (nq + 127) / 128 * 128);
   if (b->max_queries > 0 && nq > b->max_queries)
@@ -646,11 +656,13 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
     // reduced query copies only for the call's pool format; the absolute
     // terms of the subtraction step only for bfloat16 sum pools
     const bool w16 = kind == 1 && fmt == GT_POOL_BF16, w8 = kind == 1 && fmt == GT_POOL_FP8E4M3;
+    const bool w32s = kind == 1 && fmt == GT_POOL_F32 && ix->signed_mode;
     HIPCHK(gt::launch_query_prep(q, nq, ix->d, ix->dp, tq, b->rho, ix->d_mmin, b->qf,
                                  w16 ? b->qbf : nullptr, w8 ? b->q8 : nullptr, b->qexp, b->invn_q,
                                  b->qq, b->thr, b->thr_gemm, b->tile_mask,
                                  w16 && !maxp ? ix->master + level_row(0) * ix->dp : nullptr,
-                                 w16 && !maxp ? b->sabs : nullptr, &b->ctr->err, nq_pad, s));
+                                 w16 && !maxp ? b->sabs : nullptr, w32s ? b->qw : nullptr, ix->pw,
+                                 ix->signed_mode ? ix->sbound : 0.0f, &b->ctr->err, nq_pad, s));
   }
   ev_mark(b, 1);
   if (nq > 0 && ix->n > 0) {
@@ -692,7 +704,10 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
   for (int attempt = 0;; ++attempt) {
     HIPCHK(hipEventSynchronize(b->done));
     const gt::DevCounters& c = *b->h_ctr;
-    if (c.err) return fail(GT_ERR_INVALID_INPUT, "query contains a NaN, infinite or negative value");
+    if (c.err)
+      return fail(GT_ERR_INVALID_INPUT, ix->signed_mode
+                                            ? "query contains a NaN or infinite value"
+                                            : "query contains a NaN, infinite or negative value");
     if (c.slot_over)
       return fail(GT_ERR_CAPACITY, "a query has more than 2^30 results");
     const bool cand_over = b->kind == 2 && (int64_t)c.ncand > b->cand_cap;
@@ -758,8 +773,12 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   if (dtype != GT_F32 && dtype != GT_F16 && dtype != GT_BF16)
     return fail(GT_ERR_INVALID_ARG, "unknown dtype");
   if (pool_formats & ~(uint32_t)(GT_POOL_F32 | GT_POOL_BF16 | GT_POOL_FP8E4M3 | GT_POOL_MAX_F32 |
-                                 GT_POOL_MAX_BF16))
+                                 GT_POOL_MAX_BF16 | GT_POOL_SIGNED))
     return fail(GT_ERR_INVALID_ARG, "unknown pool format bits");
+  const bool sgn = (pool_formats & GT_POOL_SIGNED) != 0;
+  if (sgn && (pool_formats & (GT_POOL_F32 | GT_POOL_BF16 | GT_POOL_FP8E4M3)))
+    return fail(GT_ERR_INVALID_ARG, "an index of signed vectors keeps max/min pools only");
+  if (sgn && d > 512) return fail(GT_ERR_INVALID_ARG, "d must be <= 512 for signed vectors");
   if (capacity == 0) {
     capacity = 2;
     while (capacity < n) capacity <<= 1;
@@ -803,21 +822,26 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   ix->depth = 0;
   while ((int64_t(1) << ix->depth) < capacity) ++ix->depth;
   ix->dtype = dtype;
-  ix->formats = pool_formats | GT_POOL_F32;
-  // max pools keep a float32 tree whenever a max format is asked for
+  // signed vectors: max/min pools only (a float32 tree always); otherwise the
+  // float32 sums always, and a float32 max tree whenever a max format is asked for
+  ix->signed_mode = sgn;
+  ix->pw = sgn ? 2 * ix->dp : ix->dp;
+  ix->formats = sgn ? (pool_formats | GT_POOL_MAX_F32) : (pool_formats | GT_POOL_F32);
   if (ix->formats & GT_POOL_MAX_BF16) ix->formats |= GT_POOL_MAX_F32;
 
   const size_t cap = (size_t)capacity, dp = (size_t)ix->dp, tree = (cap - 1) * dp;
+  const size_t pw = (size_t)ix->pw, mtree = (cap - 1) * pw;
   BTRY(dalloc(ix, &ix->leaves, cap * dp));
   BTRY(dalloc(ix, &ix->invn, cap));
   BTRY(dalloc(ix, &ix->ff, cap));
   BTRY(dalloc(ix, &ix->nf, cap));
   BTRY(dalloc(ix, &ix->d_mmin, 2));
-  BTRY(dalloc(ix, &ix->master, tree));
+  BTRY(dalloc(ix, &ix->d_absmax, 1));
+  if (ix->formats & GT_POOL_F32) BTRY(dalloc(ix, &ix->master, tree));
   if (ix->formats & GT_POOL_BF16) BTRY(dalloc(ix, &ix->pbf16, tree));
   if (ix->formats & GT_POOL_FP8E4M3) BTRY(dalloc(ix, &ix->pfp8, tree));
-  if (ix->formats & GT_POOL_MAX_F32) BTRY(dalloc(ix, &ix->mmax, tree));
-  if (ix->formats & GT_POOL_MAX_BF16) BTRY(dalloc(ix, &ix->pmax16, tree));
+  if (ix->formats & GT_POOL_MAX_F32) BTRY(dalloc(ix, &ix->mmax, mtree));
+  if (ix->formats & GT_POOL_MAX_BF16) BTRY(dalloc(ix, &ix->pmax16, mtree));
   BTRY(dalloc(ix, &ix->d_lexp, GT_MAX_LEVELS));
   BTRY(dalloc(ix, &ix->d_levelmax, GT_MAX_LEVELS));
   BTRY(dalloc(ix, &ix->d_flags, GT_MAX_LEVELS));
@@ -825,35 +849,54 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   BHIP(hipMemsetAsync(ix->invn, 0, cap * 4, s));
   BHIP(hipMemsetAsync(ix->ff, 0, cap * 8, s));
   BHIP(hipMemsetAsync(ix->nf, 0, cap * 4, s));
-  BHIP(hipMemsetAsync(ix->master, 0, tree * 4, s));
-  if (ix->mmax) BHIP(hipMemsetAsync(ix->mmax, 0, tree * 4, s));
+  if (ix->master) BHIP(hipMemsetAsync(ix->master, 0, tree * 4, s));
+  if (ix->mmax) BHIP(hipMemsetAsync(ix->mmax, 0, mtree * 4, s));
+  BHIP(hipMemsetAsync(ix->d_absmax, 0, 4, s));
   BHIP(hipMemsetAsync(ix->d_flags, 0, GT_MAX_LEVELS * 4, s));
   BHIP(hipMemsetAsync(ix->d_lexp, 0, GT_MAX_LEVELS * 4, s));
   const double inf = INFINITY;
   BHIP(hipMemcpyAsync(ix->d_mmin, &inf, 8, hipMemcpyHostToDevice, s));
   unsigned int* derr = ix->d_flags + (GT_MAX_LEVELS - 1);
   BHIP(gt::launch_ingest(feats_dev, dtype, n, d, ix->dp, ix->leaves, ix->ff, ix->invn, ix->nf,
-                         ix->d_mmin, derr, s));
-  unsigned int herr = 0;
+                         ix->d_mmin, derr, sgn, sgn ? ix->d_absmax : nullptr, s));
+  unsigned int herr = 0, habs = 0;
   BHIP(hipMemcpyAsync(&herr, derr, 4, hipMemcpyDeviceToHost, s));
+  BHIP(hipMemcpyAsync(&habs, ix->d_absmax, 4, hipMemcpyDeviceToHost, s));
   BHIP(hipStreamSynchronize(s));
   if (herr)
-    return bail(fail(GT_ERR_INVALID_INPUT, "features contain a NaN, infinite or negative value"));
+    return bail(fail(GT_ERR_INVALID_INPUT, sgn ? "features contain a NaN or infinite value"
+                                               : "features contain a NaN, infinite or negative value"));
   ix->n = n;
+  if (sgn) {
+    // B: the smallest power of two >= the largest |value| (1 if all are zero)
+    float amax;
+    memcpy(&amax, &habs, 4);
+    int ex = 0;
+    const double m = amax > 0.0f ? frexp((double)amax, &ex) : 0.5;
+    ix->sbound = amax > 0.0f ? (float)ldexp(1.0, m == 0.5 ? ex - 1 : ex) : 1.0f;
+  }
 
   // pools, bottom-up; only pools covering some of the first n leaves are non-zero
   for (int l = ix->depth - 1; l >= 0; --l) {
-    const float* child = (l == ix->depth - 1) ? ix->leaves : ix->master + level_row(l + 1) * dp;
     const int64_t span = int64_t(1) << (ix->depth - l);
     const int64_t nodes = (n + span - 1) / span;
-    BHIP(gt::launch_build_level(child, ix->master + level_row(l) * dp, nodes, ix->dp, 0, s, false));
+    if (ix->master) {
+      const float* child = (l == ix->depth - 1) ? ix->leaves : ix->master + level_row(l + 1) * dp;
+      BHIP(gt::launch_build_level(child, ix->master + level_row(l) * dp, nodes, ix->dp, 0, s,
+                                  false));
+    }
     if (ix->mmax) {
-      const float* mchild = (l == ix->depth - 1) ? ix->leaves : ix->mmax + level_row(l + 1) * dp;
-      BHIP(gt::launch_build_level(mchild, ix->mmax + level_row(l) * dp, nodes, ix->dp, 0, s, true));
+      float* mpar = ix->mmax + level_row(l) * pw;
+      if (sgn && l == ix->depth - 1) {
+        BHIP(gt::launch_signed_bottom(ix->leaves, mpar, 0, nodes, ix->dp, ix->d, n, ix->sbound, s));
+      } else {
+        const float* mchild = (l == ix->depth - 1) ? ix->leaves : ix->mmax + level_row(l + 1) * pw;
+        BHIP(gt::launch_build_level(mchild, mpar, nodes, ix->pw, 0, s, true));
+      }
     }
   }
   if (ix->pbf16) BHIP(gt::launch_quant_bf16(ix->master, ix->pbf16, (int64_t)tree, s));
-  if (ix->pmax16) BHIP(gt::launch_quant_bf16(ix->mmax, ix->pmax16, (int64_t)tree, s));
+  if (ix->pmax16) BHIP(gt::launch_quant_bf16(ix->mmax, ix->pmax16, (int64_t)mtree, s));
   if (ix->pfp8) {
     BHIP(hipMemsetAsync(ix->d_levelmax, 0, GT_MAX_LEVELS * 4, s));
     for (int l = 0; l < ix->depth; ++l)
@@ -890,28 +933,40 @@ gt_status gt_insert(gt_index* ix, const void* feats_dev, int64_t n_new, void* st
     return fail(GT_ERR_CAPACITY, "insert of " + std::to_string(n_new) + " rows exceeds capacity " +
                                      std::to_string(ix->cap));
   hipStream_t s = (hipStream_t)stream;
-  const size_t dp = (size_t)ix->dp;
+  const size_t dp = (size_t)ix->dp, pw = (size_t)ix->pw;
   const int64_t lo = ix->n, hi = ix->n + n_new;
   unsigned int* derr = ix->d_flags + (GT_MAX_LEVELS - 1);
   double* tmp_mmin = ix->d_mmin + 1;
   const double inf = INFINITY;
+  const bool sgn = ix->signed_mode;
   HIPCHK(hipMemsetAsync(derr, 0, 4, s));
+  HIPCHK(hipMemsetAsync(ix->d_absmax, 0, 4, s));
   HIPCHK(hipMemcpyAsync(tmp_mmin, &inf, 8, hipMemcpyHostToDevice, s));
   HIPCHK(gt::launch_ingest(feats_dev, ix->dtype, n_new, ix->d, ix->dp, ix->leaves + lo * dp,
-                           ix->ff + lo, ix->invn + lo, ix->nf + lo, tmp_mmin, derr, s));
-  unsigned int herr = 0;
+                           ix->ff + lo, ix->invn + lo, ix->nf + lo, tmp_mmin, derr, sgn,
+                           sgn ? ix->d_absmax : nullptr, s));
+  unsigned int herr = 0, habs = 0;
   double mnew = inf;
   HIPCHK(hipMemcpyAsync(&herr, derr, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&habs, ix->d_absmax, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&mnew, tmp_mmin, 8, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (herr) {
+  float amax = 0.0f;
+  memcpy(&amax, &habs, 4);
+  // a signed index's shifted rows need every |value| <= B
+  const bool beyond = sgn && amax > ix->sbound;
+  if (herr || beyond) {
     // leave the unused leaf slots zero, as they were
     HIPCHK(hipMemsetAsync(ix->leaves + lo * dp, 0, (size_t)n_new * dp * 4, s));
     HIPCHK(hipMemsetAsync(ix->ff + lo, 0, (size_t)n_new * 8, s));
     HIPCHK(hipMemsetAsync(ix->invn + lo, 0, (size_t)n_new * 4, s));
     HIPCHK(hipMemsetAsync(ix->nf + lo, 0, (size_t)n_new * 4, s));
     HIPCHK(hipStreamSynchronize(s));
-    return fail(GT_ERR_INVALID_INPUT, "inserted rows contain a NaN, infinite or negative value");
+    if (herr)
+      return fail(GT_ERR_INVALID_INPUT, sgn ? "inserted rows contain a NaN or infinite value"
+                                            : "inserted rows contain a NaN, infinite or negative value");
+    return fail(GT_ERR_INVALID_INPUT, "an inserted value exceeds the index's shift bound " +
+                                          std::to_string(ix->sbound) + " in absolute value");
   }
   // A float8 level that must be rescaled is rewritten whole; calls in flight
   // on other streams must not read it meanwhile, so the device is drained
@@ -922,16 +977,23 @@ gt_status gt_insert(gt_index* ix, const void* feats_dev, int64_t n_new, void* st
   for (int l = ix->depth - 1; l >= 0; --l) {
     const int sh = ix->depth - l;
     const int64_t a = lo >> sh, b = (hi - 1) >> sh;
-    const float* child = (l == ix->depth - 1) ? ix->leaves : ix->master + level_row(l + 1) * dp;
-    float* par = ix->master + level_row(l) * dp;
-    HIPCHK(gt::launch_build_level(child, par, b - a + 1, ix->dp, a, s, false));
+    float* par = ix->master ? ix->master + level_row(l) * dp : nullptr;
+    if (par) {
+      const float* child = (l == ix->depth - 1) ? ix->leaves : ix->master + level_row(l + 1) * dp;
+      HIPCHK(gt::launch_build_level(child, par, b - a + 1, ix->dp, a, s, false));
+    }
     if (ix->mmax) {
-      const float* mchild = (l == ix->depth - 1) ? ix->leaves : ix->mmax + level_row(l + 1) * dp;
-      float* mpar = ix->mmax + level_row(l) * dp;
-      HIPCHK(gt::launch_build_level(mchild, mpar, b - a + 1, ix->dp, a, s, true));
+      float* mpar = ix->mmax + level_row(l) * pw;
+      if (sgn && l == ix->depth - 1) {
+        HIPCHK(gt::launch_signed_bottom(ix->leaves, mpar, a, b - a + 1, ix->dp, ix->d, hi,
+                                        ix->sbound, s));
+      } else {
+        const float* mchild = (l == ix->depth - 1) ? ix->leaves : ix->mmax + level_row(l + 1) * pw;
+        HIPCHK(gt::launch_build_level(mchild, mpar, b - a + 1, ix->pw, a, s, true));
+      }
       if (ix->pmax16)
-        HIPCHK(gt::launch_quant_bf16(mpar + a * dp, ix->pmax16 + (level_row(l) + a) * dp,
-                                     (b - a + 1) * ix->dp, s));
+        HIPCHK(gt::launch_quant_bf16(mpar + a * pw, ix->pmax16 + (level_row(l) + a) * pw,
+                                     (b - a + 1) * ix->pw, s));
     }
     if (ix->pbf16)
       HIPCHK(gt::launch_quant_bf16(par + a * dp, ix->pbf16 + (level_row(l) + a) * dp,
@@ -1104,6 +1166,8 @@ gt_status gt_get_stats(const gt_index* ix, gt_stats* out) {
   out->ms_dense = b->ms[7];
   out->frontier_launches = b->frontier_launches;
   out->dense_launches = b->dense_launches;
+  out->pool_width = ix->pw;
+  out->shift_bound = ix->signed_mode ? ix->sbound : 0.0f;
   return GT_OK;
 }
 
@@ -1121,7 +1185,9 @@ gt_status gt_read_pools(const gt_index* ix, int32_t level, int64_t first, int64_
     return fail(GT_ERR_INVALID_ARG, "format not available for this level");
   const size_t esz = (f == GT_POOL_F32 || f == GT_POOL_MAX_F32) ? 4
                      : (f == GT_POOL_BF16 || f == GT_POOL_MAX_BF16) ? 2 : 1;
-  const size_t off = (size_t)level_row(level) * ix->dp;
+  const bool mx = f == GT_POOL_MAX_F32 || f == GT_POOL_MAX_BF16;
+  const size_t w = (mx && level < ix->depth) ? (size_t)ix->pw : (size_t)ix->dp;
+  const size_t off = (size_t)level_row(level) * w;
   const unsigned char* base =
       level == ix->depth     ? (const unsigned char*)ix->leaves
       : f == GT_POOL_F32     ? (const unsigned char*)(ix->master + off)
@@ -1130,7 +1196,7 @@ gt_status gt_read_pools(const gt_index* ix, int32_t level, int64_t first, int64_
       : f == GT_POOL_MAX_BF16 ? (const unsigned char*)(ix->pmax16 + off)
                               : (const unsigned char*)(ix->pfp8 + off);
   HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(host_out, base + (size_t)first * ix->dp * esz, (size_t)count * ix->dp * esz,
+  HIPCHK(hipMemcpy(host_out, base + (size_t)first * w * esz, (size_t)count * w * esz,
                    hipMemcpyDeviceToHost));
   return GT_OK;
 }

@@ -156,7 +156,8 @@ struct Batch {
   uint32_t* lvl_count = nullptr;    // [GT_MAX_LEVELS x kMaxSlots]
   uint64_t* tile_mask = nullptr;    // [kMaxTiles]
   float* qf = nullptr;       // [nq_pad x dp]
-  uint16_t* qbf = nullptr;
+  float* qw = nullptr;       // [nq_pad x pw] walk queries [max(q,0) | max(-q,0)] (signed)
+  uint16_t* qbf = nullptr;   // [nq_pad x pw]
   uint8_t* q8 = nullptr;
   int* qexp = nullptr;
   float* invn_q = nullptr;
@@ -243,7 +244,14 @@ struct Index {
   uint16_t* pbf16 = nullptr;
   uint8_t* pfp8 = nullptr;
   float* mmax = nullptr;     // element-wise max pools (Our-Max), same layout as master
+                             // with rows of pw values
   uint16_t* pmax16 = nullptr;  // their bfloat16 copy, rounded up
+  // Vectors of any sign (GT_POOL_SIGNED): mmax rows are [max + B | B - min]
+  // over the members, pw = 2 dp; no sum trees.
+  bool signed_mode = false;
+  int pw = 0;                // row length of mmax / pmax16 (dp, or 2 dp when signed)
+  float sbound = 0.0f;       // B (power of two >= every |value|), signed only
+  unsigned int* d_absmax = nullptr;  // float bits of the largest |value| of an ingest
   int* d_lexp = nullptr;     // float8 scale exponents per level
   int lexp[GT_MAX_LEVELS] = {0};
   float* d_levelmax = nullptr;
@@ -256,7 +264,9 @@ struct Index {
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_ingest(const void* src, int dtype, int64_t rows, int d, int dp, float* leaves,
                          double* ff, float* invn, float* nf, double* mmin, unsigned int* err,
-                         hipStream_t s);
+                         bool allow_negative, unsigned int* absmax, hipStream_t s);
+hipError_t launch_signed_bottom(const float* leaves, float* parent, int64_t first, int64_t nodes,
+                                int dp, int d, int64_t n, float bound, hipStream_t s);
 hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, int dp,
                               int64_t first, hipStream_t s, bool max_pool);
 hipError_t launch_level_max(const float* rows, int64_t nrows, int dp, float* out_max, hipStream_t s);
@@ -267,6 +277,7 @@ hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, cons
                              const double* mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
                              float* invn_q, double* qq, float* thr, float* thr_gemm,
                              uint64_t* tile_mask, const float* root, float* sabs,
+                             float* qw, int pw, float sbound,
                              unsigned int* err, int nq_pad, hipStream_t s);
 hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStream_t s);
 hipError_t launch_walk_sub(const WalkLevelArgs& a, int grid, hipStream_t s);

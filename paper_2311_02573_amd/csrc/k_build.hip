@@ -32,14 +32,18 @@ __device__ __forceinline__ float load_feature(const void* src, int dtype, int64_
 // One workgroup of 64 threads per 64 rows.  Column tiles of 64 are staged
 // through LDS so that loads and stores are coalesced while each thread still
 // sums its own row sequentially in float64 (the canonical squared norm).
+// Values must be finite and >= 0, or only finite with allow_negative (then
+// the largest |value| is folded into *absmax as float bits).
 __global__ __launch_bounds__(64) void k_ingest(const void* src, int dtype, int64_t rows, int d,
                                                int dp, float* leaves, double* ff, float* invn,
-                                               float* nf, double* mmin, unsigned int* err) {
+                                               float* nf, double* mmin, unsigned int* err,
+                                               int allow_negative, unsigned int* absmax) {
   __shared__ float tile[64][65];
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   double acc = 0.0;
   bool bad = false;
+  float amax = 0.0f;
   for (int c0 = 0; c0 < dp; c0 += 64) {
     const int c = c0 + t;
     for (int r = 0; r < 64; ++r) {
@@ -48,7 +52,12 @@ __global__ __launch_bounds__(64) void k_ingest(const void* src, int dtype, int64
       float v = 0.0f;
       if (c < d) {
         v = load_feature(src, dtype, row * d + c);
-        if (!(v >= 0.0f) || isinf(v)) bad = true;
+        if (allow_negative) {
+          if (!isfinite(v)) bad = true;
+          amax = fmaxf(amax, fabsf(v));
+        } else if (!(v >= 0.0f) || isinf(v)) {
+          bad = true;
+        }
       }
       if (c < dp) leaves[row * dp + c] = v;
       tile[r][t] = v;
@@ -64,6 +73,10 @@ __global__ __launch_bounds__(64) void k_ingest(const void* src, int dtype, int64
     __syncthreads();
   }
   if (bad) atomicOr(err, 1u);
+  if (absmax) {
+    for (int o = 32; o >= 1; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    if (t == 0 && amax > 0.0f) atomicMax(absmax, __float_as_uint(amax));
+  }
   const int64_t row = r0 + t;
   if (row < rows) {
     ff[row] = acc;
@@ -107,6 +120,41 @@ __global__ void k_build_level(const float* __restrict__ child, float* __restrict
   }
 }
 
+// Bottom level of the max/min tree of a signed index (paper Sec. 3, negative
+// descriptors).  Pool j of level depth-1 holds leaves 2j and 2j+1; only leaves
+// below n are members.  Row j gets [max_k + B | B - min_k] over its members in
+// columns k < d, each term rounded up (every term is >= 0 because |f_k| <= B),
+// zero in the padding columns and for a pool without members.  The maximum of
+// the shifted rows is taken term by term, which is the shifted max and min.
+__global__ void k_signed_bottom(const float* __restrict__ leaves, float* __restrict__ parent,
+                                int64_t first, int64_t nodes, int dp, int d, int64_t n,
+                                float bound) {
+  const int pw = 2 * dp, qd = pw / 4;
+  const int64_t total = nodes * qd;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = first + i / qd;
+    const int k = (int)(i % qd) * 4;          // column of the shifted row
+    const bool hi = k >= dp;                  // second half: B - f
+    const int c = hi ? k - dp : k;            // feature column
+    float o[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int m = 0; m < 2; ++m) {
+      const int64_t leaf = 2 * j + m;
+      if (leaf >= n) break;
+      const float4 v = *reinterpret_cast<const float4*>(leaves + leaf * dp + c);
+      const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (c + e < d) {
+          const float t = hi ? add_up(bound, -x[e]) : add_up(x[e], bound);
+          o[e] = fmaxf(o[e], t);
+        }
+      }
+    }
+    *reinterpret_cast<float4*>(parent + j * pw + k) = make_float4(o[0], o[1], o[2], o[3]);
+  }
+}
+
 __global__ void k_level_max(const float* __restrict__ rows, int64_t count, float* out) {
   float m = 0.0f;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
@@ -143,7 +191,8 @@ __global__ __launch_bounds__(256) void k_query_prep(
     const float* __restrict__ q, int nq, int d, int dp, int tq, const double* __restrict__ rho,
     const double* __restrict__ mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
     float* invn_q, double* qq_out, float* thr, float* thr_gemm, uint64_t* tile_mask,
-    const float* __restrict__ root, float* sabs, unsigned int* err) {
+    const float* __restrict__ root, float* sabs, float* qw, int pw, float sbound,
+    unsigned int* err) {
   __shared__ float qs[4096];
   __shared__ float red[4];
   __shared__ double l1red[4], l2red[4];
@@ -151,16 +200,18 @@ __global__ __launch_bounds__(256) void k_query_prep(
   const bool real = b < nq;
   float mx = 0.0f;
   bool bad = false;
+  const bool sgn = sbound > 0.0f;  // signed index: any finite value
   for (int k = t; k < d; k += blockDim.x) {
     const float v = real ? q[(int64_t)b * d + k] : 0.0f;
-    if (!(v >= 0.0f) || isinf(v)) bad = true;
+    if (sgn ? !isfinite(v) : (!(v >= 0.0f) || isinf(v))) bad = true;
     qs[k] = v;
     mx = fmaxf(mx, v);
   }
   if (bad) atomicOr(err, 1u);
-  // |q|_1 + |root pool|_1 (any order: only an upper bound is needed)
+  // |q|_1 + |root pool|_1 (any order: only an upper bound is needed); for a
+  // signed index |q|_1 alone, which sets the threshold's shift B |q|_1
   double l1 = 0.0;
-  for (int k = t; k < d; k += blockDim.x) l1 += (double)qs[k];
+  for (int k = t; k < d; k += blockDim.x) l1 += (double)fabsf(qs[k]);
   if (root)
     for (int k = t; k < dp; k += blockDim.x) l1 += (double)root[k];
   // |q|^2 by a fixed-order parallel sum (deterministic, relative error below
@@ -190,8 +241,21 @@ __global__ __launch_bounds__(256) void k_query_prep(
   for (int k = t; k < dp; k += blockDim.x) {
     const float v = k < d ? qs[k] : 0.0f;
     qf[(int64_t)b * dp + k] = v;
-    if (qbf) qbf[(int64_t)b * dp + k] = bf16_up(v);
-    if (q8) q8[(int64_t)b * dp + k] = (uint8_t)e4m3_up(ldexp((double)v, -e));
+    if (sgn) {
+      // walk query [max(q,0) | max(-q,0)] against rows [max + B | B - min]
+      const float vp = fmaxf(v, 0.0f), vn = fmaxf(-v, 0.0f);
+      if (qw) {
+        qw[(int64_t)b * pw + k] = vp;
+        qw[(int64_t)b * pw + dp + k] = vn;
+      }
+      if (qbf) {
+        qbf[(int64_t)b * pw + k] = bf16_up(vp);
+        qbf[(int64_t)b * pw + dp + k] = bf16_up(vn);
+      }
+    } else {
+      if (qbf) qbf[(int64_t)b * dp + k] = bf16_up(v);
+      if (q8) q8[(int64_t)b * dp + k] = (uint8_t)e4m3_up(ldexp((double)v, -e));
+    }
   }
   if (t == 0) {
     const bool live = real && qq > 0.0 && !bad;
@@ -211,16 +275,31 @@ __global__ __launch_bounds__(256) void k_query_prep(
         // least m_min, so a pool holding a neighbour scores >= tau (reals).
         const double reff = r * (1.0 - 4e-11);
         const double tau = reff * nrm * (*mmin) * (1.0 - 4e-11);
-        const double sl = pool_slack(dp);
-        th = f64_to_f32_down(tau * (1.0 - sl) - 2.0 * dp * 0x1p-126);
-        tg = f64_to_f32_down(reff * nrm * (1.0 - 4e-11) * (1.0 - sl));
+        if (sgn) {
+          // A member's q.f is at most the pool's max/min score U, and the
+          // walk computes [q+ | q-] . [max + B | B - min] = U + B |q|_1 over
+          // pw non-negative products.  The shift is taken slightly low (the
+          // float64 |q|_1 of <= 4096 terms is within 2^-40 of the real one).
+          // Products of mixed sign in the leaf GEMM carry an error relative
+          // to sum |q_k f_k| <= |q| |f|, hence rho - slack there.
+          const double sl = pool_slack(pw);
+          const double l1s = (l1red[0] + l1red[1]) + (l1red[2] + l1red[3]);
+          const double kappa = (double)sbound * l1s * (1.0 - 1e-12);
+          th = f64_to_f32_down((tau + kappa) * (1.0 - sl) - 2.0 * pw * 0x1p-126);
+          const double cg = reff * (1.0 - 4e-11) - pool_slack(dp);
+          tg = cg > 0.0 ? f64_to_f32_down(cg * nrm) : -INFINITY;
+        } else {
+          const double sl = pool_slack(dp);
+          th = f64_to_f32_down(tau * (1.0 - sl) - 2.0 * dp * 0x1p-126);
+          tg = f64_to_f32_down(reff * nrm * (1.0 - 4e-11) * (1.0 - sl));
+        }
       }
       atomicOr(reinterpret_cast<unsigned long long*>(&tile_mask[b / tq]),
                (unsigned long long)(1ull << (b % tq)));
     }
     thr[b] = th;
     thr_gemm[b] = tg;
-    if (sabs) {
+    if (sabs && !sgn) {
       // absolute term of the subtraction step's lower bound: 2^-125 (|S|_1 +
       // |q|_1 + dp 2^-126) + 2^-126, a normal float32 rounded up
       const double l1s = (l1red[0] + l1red[1]) + (l1red[2] + l1red[3]);
@@ -249,10 +328,19 @@ hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
 
 hipError_t launch_ingest(const void* src, int dtype, int64_t rows, int d, int dp, float* leaves,
                          double* ff, float* invn, float* nf, double* mmin, unsigned int* err,
-                         hipStream_t s) {
+                         bool allow_negative, unsigned int* absmax, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ingest, dim3((unsigned)((rows + 63) / 64)), dim3(64), 0, s, src, dtype, rows,
-                     d, dp, leaves, ff, invn, nf, mmin, err);
+                     d, dp, leaves, ff, invn, nf, mmin, err, allow_negative ? 1 : 0, absmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_signed_bottom(const float* leaves, float* parent, int64_t first, int64_t nodes,
+                                int dp, int d, int64_t n, float bound, hipStream_t s) {
+  if (nodes <= 0) return hipSuccess;
+  if (dp % 4 || d > dp || first < 0 || n < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_signed_bottom, dim3(grid_for(nodes * (2 * dp / 4), 256)), dim3(256), 0, s,
+                     leaves, parent, first, nodes, dp, d, n, bound);
   return hipGetLastError();
 }
 
@@ -295,10 +383,13 @@ hipError_t launch_query_prep(const float* q, int nq, int d, int dp, int tq, cons
                              const double* mmin, float* qf, uint16_t* qbf, uint8_t* q8, int* qexp,
                              float* invn_q, double* qq, float* thr, float* thr_gemm,
                              uint64_t* tile_mask, const float* root, float* sabs,
+                             float* qw, int pw, float sbound,
                              unsigned int* err, int nq_pad, hipStream_t s) {
   if (nq_pad <= 0) return hipSuccess;
+  if (sbound > 0.0f && pw != 2 * dp) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_query_prep, dim3(nq_pad), dim3(256), 0, s, q, nq, d, dp, tq, rho, mmin, qf,
-                     qbf, q8, qexp, invn_q, qq, thr, thr_gemm, tile_mask, root, sabs, err);
+                     qbf, q8, qexp, invn_q, qq, thr, thr_gemm, tile_mask, root, sabs, qw, pw,
+                     sbound, err);
   return hipGetLastError();
 }
 

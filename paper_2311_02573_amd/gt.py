@@ -22,8 +22,9 @@ STATUS_NAMES = {0: "GT_OK", 1: "GT_ERR_INVALID_ARG", 2: "GT_ERR_INVALID_INPUT",
                 6: "GT_ERR_DEVICE"}
 GT_F32, GT_F16, GT_BF16 = 0, 1, 2
 POOL_F32, POOL_BF16, POOL_FP8, POOL_MAX_F32, POOL_MAX_BF16 = 1, 2, 4, 8, 16
+POOL_SIGNED = 32  # build-time flag: vectors of any sign, max/min pools
 POOLS = {"f32": POOL_F32, "bf16": POOL_BF16, "fp8": POOL_FP8,
-         "max_f32": POOL_MAX_F32, "max_bf16": POOL_MAX_BF16}
+         "max_f32": POOL_MAX_F32, "max_bf16": POOL_MAX_BF16, "signed": POOL_SIGNED}
 GT_MAX_LEVELS = 40
 
 EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_exhaustive", "gt_batch_create",
@@ -56,6 +57,7 @@ class GTStats(ctypes.Structure):
         ("fp8_exp", ctypes.c_int32 * GT_MAX_LEVELS),
         ("unique_rows", ctypes.c_int64 * GT_MAX_LEVELS),
         ("dense_launches", ctypes.c_int32), ("ms_dense", ctypes.c_double),
+        ("pool_width", ctypes.c_int32), ("shift_bound", ctypes.c_float),
     ]
 
 
@@ -225,13 +227,15 @@ class GTIndex:
         return out
 
     def read_pools(self, level: int, first: int = 0, count: int | None = None, pool: str = "f32"):
-        """Stored pool rows of one level as a numpy array [count, d_pad]."""
+        """Stored pool rows of one level as a numpy array [count, width]: d_pad
+        values, or pool_width for max pools above the leaves."""
         st = self.stats()
         if count is None:
             count = (1 << level) - first
         dt = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8,
               "max_f32": np.float32, "max_bf16": np.uint16}[pool]
-        out = np.empty((count, st["d_pad"]), dtype=dt)
+        w = st["pool_width"] if pool.startswith("max") and level < st["depth"] else st["d_pad"]
+        out = np.empty((count, w), dtype=dt)
         _check(lib().gt_read_pools(self._h, level, first, count, POOLS[pool],
                                    ctypes.c_void_p(out.ctypes.data)))
         return out

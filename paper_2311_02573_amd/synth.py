@@ -43,12 +43,16 @@ def _rng(seed: int, chunk: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, chunk])))
 
 
-def _softmax_unit_rows(z: np.ndarray, temp: float) -> np.ndarray:
-    """float64 logits -> unit-norm softmax rows, rounded to float32."""
+def _softmax_unit_rows(z: np.ndarray, temp: float, centred: bool = False) -> np.ndarray:
+    """float64 logits -> unit-norm softmax rows, rounded to float32.  With
+    `centred`, the uniform mean 1/d is subtracted from the softmax before the
+    normalisation (descriptors with negative values)."""
     x = z / temp
     x -= x.max(axis=1, keepdims=True)
     np.exp(x, out=x)
     x /= x.sum(axis=1, keepdims=True)
+    if centred:
+        x -= 1.0 / x.shape[1]
     x /= np.sqrt(np.einsum("ij,ij->i", x, x))[:, None]
     return x.astype(np.float32)
 
@@ -57,8 +61,10 @@ def _threads() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
 
-def softmax_rows(seed: int, n: int, d: int, temp: float, return_logits: bool = False):
-    """n unit-norm softmax(z/T) rows in float32, z ~ N(0, I_d), chunked streams."""
+def softmax_rows(seed: int, n: int, d: int, temp: float, return_logits: bool = False,
+                 centred: bool = False):
+    """n unit-norm softmax(z/T) rows in float32, z ~ N(0, I_d), chunked streams
+    (centred: softmax(z/T) - 1/d, normalised)."""
     out = np.empty((n, d), dtype=np.float32)
     logits = np.empty((n, d), dtype=np.float64) if return_logits else None
     nchunks = (n + CHUNK_ROWS - 1) // CHUNK_ROWS
@@ -68,7 +74,7 @@ def softmax_rows(seed: int, n: int, d: int, temp: float, return_logits: bool = F
         z = _rng(seed, c).standard_normal((hi - lo, d))
         if logits is not None:
             logits[lo:hi] = z
-        out[lo:hi] = _softmax_unit_rows(z, temp)
+        out[lo:hi] = _softmax_unit_rows(z, temp, centred)
 
     if nchunks == 1:
         work(0)
@@ -105,7 +111,7 @@ class Workload:
     extra: dict = dataclasses.field(default_factory=dict)
 
 
-def _plant(feats32, q_logits, counts, temp, sigma, seed):
+def _plant(feats32, q_logits, counts, temp, sigma, seed, centred=False):
     """Overwrite rows of feats32 with planted neighbours; returns ids per query."""
     n, d = feats32.shape
     total = int(counts.sum())
@@ -113,7 +119,7 @@ def _plant(feats32, q_logits, counts, temp, sigma, seed):
     pos = g.choice(n, size=total, replace=False)
     eps = g.standard_normal((total, d)) * sigma
     owner = np.repeat(np.arange(len(counts)), counts)
-    rows = _softmax_unit_rows(q_logits[owner] + eps, temp)
+    rows = _softmax_unit_rows(q_logits[owner] + eps, temp, centred)
     feats32[pos] = rows
     planted, off = [], 0
     for c in counts:
@@ -205,10 +211,33 @@ def workload_small(n: int, d: int, nq: int, temp: float = 0.25, rho: float = 0.9
                     capacity=capacity or n)
 
 
-def insert_rows(workload: int, n_new: int, d: int, temp: float, offset: int = 0) -> np.ndarray:
+def workload_signed(n: int, d: int, nq: int, temp: float = 0.2, rho: float = 0.9,
+                    max_planted: int = 8, seed_offset: int = 0, dtype: str = "f32",
+                    capacity: int | None = None, geometric_planted: bool = False) -> Workload:
+    """Descriptors with negative values (the paper's extension of max pooling
+    to them has no experiment): centred softmax rows unit(softmax(z/T) - 1/d),
+    queries and planted neighbours drawn the same way (uniform 0..max_planted
+    neighbours per query, or geometric with mean 5)."""
+    wl = 70 + seed_offset
+    feats = softmax_rows(stream_seed(wl, STREAM_DB), n, d, temp, centred=True)
+    queries, qz = softmax_rows(stream_seed(wl, STREAM_QUERY), nq, d, temp, return_logits=True,
+                               centred=True)
+    g = _rng(stream_seed(wl, STREAM_PLANT), 1)
+    counts = g.geometric(1.0 / 6.0, size=nq) - 1 if geometric_planted else \
+        g.integers(0, max_planted + 1, size=nq)
+    counts = np.minimum(counts, max(0, n // max(1, nq)))
+    planted = _plant(feats, qz, counts, temp, 0.05, stream_seed(wl, STREAM_PLANT), True) \
+        if n else [np.zeros(0, np.int64)] * nq
+    return Workload(f"centred softmax N={n} d={d} T={temp} {dtype}", wl, n, d, temp, dtype,
+                    to_storage(feats, dtype), queries, np.full(nq, rho), planted,
+                    capacity=capacity or n)
+
+
+def insert_rows(workload: int, n_new: int, d: int, temp: float, offset: int = 0,
+                centred: bool = False) -> np.ndarray:
     """Vectors to insert, from the insert stream; `offset` selects later chunks."""
     seed = stream_seed(workload, STREAM_INSERT) + 7919 * offset
-    return softmax_rows(seed, n_new, d, temp)
+    return softmax_rows(seed, n_new, d, temp, centred=centred)
 
 
 def poisson_arrivals(workload: int, rate_per_s: float, duration_s: float,
