@@ -365,7 +365,14 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   const bool sub = f == GT_POOL_BF16 && !b->maxpool && dl >= 0 && ws > 0 && dl <= D - 2;
   const int sub_to = !sub ? -1 : (ws == 2 ? D - 3 : D - 2);
   if (sub && sub_to >= dl) {
-    const int64_t need = (int64_t)nt * b->fr_cap;
+    // A workspace with a query limit takes records for its largest call at
+    // once: growing them call by call would free and reallocate gigabytes,
+    // and every free waits for the whole device.
+    const int nt_rec = b->max_queries > 0
+                           ? std::max(nt, (b->max_queries + gt::kQueriesPerTile16 - 1) /
+                                              gt::kQueriesPerTile16)
+                           : nt;
+    const int64_t need = (int64_t)nt_rec * b->fr_cap;
     if (need > b->rec_len) {
       dfree(ix, &b->fr_rec[0], (size_t)b->rec_len * 64);
       dfree(ix, &b->fr_rec[1], (size_t)b->rec_len * 64);
