@@ -494,7 +494,10 @@ gt_status enqueue_leaf(Index* ix, Batch* b) {
   la.ctr = b->ctr;
   la.bitmap = b->counted ? b->bitmap : nullptr;
   la.bit_base = level_row(D);
-  HIPCHK(gt::launch_leaf(la, ix->n_cu * 4, b->stream));
+  // two workgroups (eight waves) per CU: measured faster than one, three,
+  // four or eight per CU on this kernel, whose loads already fill the CU's
+  // outstanding-request budget
+  HIPCHK(gt::launch_leaf(la, ix->n_cu * 2, b->stream));
   return GT_OK;
 }
 
