@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # scaled by a 1 GiB copy), kept in a profile summary together with a hash of
 # the kernel sources it was taken on; reported only while the sources match.
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_walk_bf16_n1m_d1000_b1024_rho0.9.md")
-KERNEL_SOURCES = ["k_walk.hip", "gt_numerics.h", "gt_device.h", "gt_internal.h"]
+KERNEL_SOURCES = ["k_walk.hip", "gt_numerics.h", "gt_device.h", "gt_internal.h", "gt_api.cpp"]
 
 
 def kernel_source_hash():
