@@ -85,6 +85,8 @@ def main():
                     help="queries of the batch the CPU oracle scans (about 10 s on 16 threads)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-side", action="store_true")
+    ap.add_argument("--signed-n", type=int, default=1 << 20,
+                    help="rows of the signed-descriptor comparator (0: skip it)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="end with a 1 GiB device-to-device copy (reference for memory counters)")
     ap.add_argument("--sweep-dense", action="store_true",
@@ -390,20 +392,8 @@ def main():
     # ---- CPU oracle on a bounded sample of the same batch
     cpu = None
     if not args.no_cpu and args.cpu_sample > 0:
-        import oracle.brute as ob
-
-        threads = ob.default_threads()
         ns = min(args.cpu_sample, args.nq)
-        t1 = time.perf_counter()
-        ora = ob.range_search(w.feats, w.queries[:ns], args.rho, nthreads=threads)
-        cpu_s = time.perf_counter() - t1
-        match = all(np.array_equal(walk_lists[b][0], ora[b][0]) for b in range(ns))
-        cpu = {"value": round(ns / cpu_s, 3), "unit": "queries/s", "cores": threads,
-               "kind": "oracle",
-               "sample": f"first {ns} of the {args.nq} queries against the full database "
-                         f"(N={w.n}, d={w.d}); canonical float64 scan, {cpu_s:.1f} s",
-               "ids_match_gpu": bool(match)}
-        log(f"oracle: {ns} queries in {cpu_s:.1f}s on {threads} threads, match={match}")
+        cpu = cpu_baseline(w, ns, args.nq, args.rho, walk_lists)
 
     out = {
         "metric": METRIC,
@@ -442,6 +432,9 @@ def main():
     idx.close()
     del idx, q
     torch.cuda.empty_cache()
+    if args.signed_n > 0 and not args.no_side:
+        out["signed"] = signed_leg(args, torch, gt, synth, dev)
+        torch.cuda.empty_cache()
     if args.serve_seconds > 0:
         out["serving"] = serving_leg(args.serve_seconds, torch, gt, synth, dev)
     print(json.dumps(out), flush=True)
@@ -452,6 +445,94 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log("copy reference: 1 GiB read + 1 GiB written")
+
+
+def cpu_baseline(w, ns, nq, rho, walk_lists):
+    """The CPU oracle (canonical float64 scan) timed on the first ns queries of
+    a batch against the full database, and its ids compared with the GPU's."""
+    import oracle.brute as ob
+
+    threads = ob.default_threads()
+    t1 = time.perf_counter()
+    ora = ob.range_search(w.feats, w.queries[:ns], rho, nthreads=threads)
+    cpu_s = time.perf_counter() - t1
+    match = all(np.array_equal(walk_lists[b][0], ora[b][0]) for b in range(ns))
+    log(f"oracle: {ns} queries in {cpu_s:.1f}s on {threads} threads, match={match}")
+    return {"value": round(ns / cpu_s, 3), "unit": "queries/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {ns} of the {nq} queries against the full database "
+                      f"(N={w.n}, d={w.d}); canonical float64 scan, {cpu_s:.1f} s",
+            "ids_match_gpu": bool(match)}
+
+
+def signed_leg(args, torch, gt, synth, dev):
+    """Descriptors with negative values (paper Sec. 3: max/min pools): centred
+    softmax rows unit(softmax(z/0.2) - 1/d), N = signed_n, d = 512 (the signed
+    index's limit), 1024 queries with planted neighbours, rho = args.rho.  The
+    max/min walk over bfloat16 and float32 rows and the exhaustive path on the
+    same index, timed per call; its leaf and walk against the HBM roofline from
+    the distinct rows they read; the CPU oracle on a sample."""
+    nq, d = 1024, 512
+    w = synth.workload_signed(args.signed_n, d, nq, rho=args.rho, geometric_planted=True)
+    F = torch.from_numpy(w.feats).to(dev)
+    t0 = time.perf_counter()
+    idx = gt.GTIndex(F, pools=("max_f32", "max_bf16", "signed"))
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    del F
+    q = torch.from_numpy(w.queries).to(dev)
+    st0 = idx.stats()
+    D, dp, pw = st0["depth"], st0["d_pad"], st0["pool_width"]
+    out = {"workload": f"centred softmax unit(softmax(z/0.2) - 1/d) N={w.n} d={d} float32, "
+                       f"{nq} queries with planted neighbours, rho={args.rho}, max/min pools",
+           "shift_bound": st0["shift_bound"], "pool_width": pw, "index_build_ms": round(build_ms, 1)}
+    ref = None
+    for pool in ("max_bf16", "max_f32", "exh"):
+        call = (lambda: idx.exhaustive(q, args.rho)) if pool == "exh" else \
+            (lambda: idx.query(q, args.rho, pool=pool))
+        for _ in range(2):
+            r = call()
+        torch.cuda.synchronize()
+        steps = 10
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            r = call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) / steps * 1e3
+        lists = r.to_lists()
+        if ref is None:
+            ref = lists
+        same = all(np.array_equal(a[0], b[0]) for a, b in zip(lists, ref))
+        key = "exhaustive_f32" if pool == "exh" else f"walk_{pool}"
+        out[key] = {"ms_per_call": round(ms, 3), "queries_per_s": round(nq / ms * 1e3, 1),
+                    "results": r.total, "ids_identical_to_max_bf16": bool(same)}
+        if pool != "exh":
+            idx.set_option("profile", 1)
+            idx.query(q, args.rho, pool=pool)
+            sp = idx.stats()
+            idx.set_option("profile", 0)
+            idx.set_option("count_unique", 1)
+            idx.query(q, args.rho, pool=pool)
+            su = idx.stats()
+            idx.set_option("count_unique", 0)
+            esz = 2 if pool == "max_bf16" else 4
+            walk_b = sum(su["unique_rows"][l] for l in range(1, D)) * pw * esz
+            leaf_b = su["unique_rows"][D] * dp * 4
+            ms_walk = sp["ms_dense"] + sp["ms_frontier"]
+            out[key].update({
+                "stage_ms": {k[3:]: round(sp[k], 4)
+                             for k in ("ms_prep", "ms_dense", "ms_frontier", "ms_leaf", "ms_total")},
+                "tests_per_level": {l: sp["pairs"][l] for l in range(D) if sp["pairs"][l]},
+                "leaf_pairs": sp["leaf_pairs"],
+                "leaf_GBps": round(leaf_b / (sp["ms_leaf"] * 1e-3) / 1e9, 1) if sp["ms_leaf"] else None,
+                "leaf_frac_of_8TBps": round(leaf_b / (sp["ms_leaf"] * 1e-3) / 8e12, 4) if sp["ms_leaf"] else None,
+                "walk_GBps": round(walk_b / (ms_walk * 1e-3) / 1e9, 1) if ms_walk else None,
+                "algorithmic_bytes": {"walk_rows": walk_b, "leaf_rows": leaf_b}})
+        log(f"signed {pool}: {ms:.3f} ms/call, {r.total} results, same={same}")
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, 64, nq, args.rho, ref)
+    idx.close()
+    return out
 
 
 def serving_leg(seconds, torch, gt, synth, dev):
