@@ -1178,6 +1178,12 @@ __device__ __forceinline__ void leaf_norms(const LeafArgs& a, LeafEntry& x) {
 // [x R, x R + R) (slots are bucket-major, so they are contiguous); the XCD's
 // workgroups sweep its entries in slot order, so the tiles' copies of a leaf
 // pair are tested close together in time and share the XCD's L2.
+// NV: 16-byte slices per lane and 1024-column chunk that can be non-zero, 4
+// in general and 2 for rows of at most 512 columns (whose other two slices
+// would only reload the row's last slice).  Each dot product is summed in the
+// same order either way: a slice past dp is zero and adds nothing to
+// chunk_sum4.
+template <int NV>
 __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
   __shared__ uint32_t epre[kMaxSlotsPerXcd + 1];
   __shared__ Hit hstage[4][kHitStage];
@@ -1255,6 +1261,11 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
         float sv[8][4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
+          if (v >= NV) {
+#pragma unroll
+            for (int vi = 0; vi < 8; ++vi) sv[vi][v] = 0.0f;
+            continue;
+          }
           bool ok;
           const int ec = slice_index(c, v, lane, a.dp, ok);
           float4 qx[2][2], fx[2][2];
@@ -1650,7 +1661,15 @@ hipError_t launch_leaf(const LeafArgs& a, int grid, hipStream_t s) {
   if (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
       a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_leaf, dim3(grid), dim3(256), 0, s, a);
+  // rows of at most 512 columns: two slices per lane, fewer registers
+  // (three waves per SIMD instead of two), so three workgroups per CU
+  // (the grid stays a multiple of the XCD count: every XCD's workgroups
+  // split its entries by blockIdx / 8)
+  if (a.dp <= 512)
+    hipLaunchKernelGGL(k_leaf<2>, dim3(kXcds * ((grid / 2 * 3 + kXcds - 1) / kXcds)), dim3(256),
+                       0, s, a);
+  else
+    hipLaunchKernelGGL(k_leaf<4>, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
