@@ -364,15 +364,16 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   // (sum pools only: a max pool is not its halves' combination)
   const bool sub = f == GT_POOL_BF16 && !b->maxpool && dl >= 0 && ws > 0 && dl <= D - 2;
   const int sub_to = !sub ? -1 : (ws == 2 ? D - 3 : D - 2);
+  // A workspace with a query limit takes its score records and dense masks
+  // for its largest call at once: growing them call by call would free and
+  // reallocate (gigabytes, for the records), and every free waits for the
+  // whole device.
+  const int nt_res = b->max_queries > 0
+                         ? std::max(nt, (b->max_queries + gt::kQueriesPerTile16 - 1) /
+                                            gt::kQueriesPerTile16)
+                         : nt;
   if (sub && sub_to >= dl) {
-    // A workspace with a query limit takes records for its largest call at
-    // once: growing them call by call would free and reallocate gigabytes,
-    // and every free waits for the whole device.
-    const int nt_rec = b->max_queries > 0
-                           ? std::max(nt, (b->max_queries + gt::kQueriesPerTile16 - 1) /
-                                              gt::kQueriesPerTile16)
-                           : nt;
-    const int64_t need = (int64_t)nt_rec * b->fr_cap;
+    const int64_t need = (int64_t)nt_res * b->fr_cap;
     if (need > b->rec_len) {
       dfree(ix, &b->fr_rec[0], (size_t)b->rec_len * 64);
       dfree(ix, &b->fr_rec[1], (size_t)b->rec_len * 64);
@@ -384,7 +385,7 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   }
   const bool use_rec = sub && sub_to >= dl;
   if (dl >= 0) {
-    const size_t need = ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt;
+    const size_t need = ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt_res;
     if ((int64_t)need > b->dmask_len) {
       dfree(ix, &b->dmask[0], (size_t)b->dmask_len);
       dfree(ix, &b->dmask[1], (size_t)b->dmask_len);

@@ -88,3 +88,29 @@ def test_inserts_between_steps(gt):
             if len(gs):
                 assert np.max(np.abs(gs.astype(np.float64) - os_)) <= 1e-6
     idx.close()
+
+
+def test_workspace_memory_is_reserved_once(gt):
+    """A workspace with a query limit allocates its score records for its
+    largest call on first use: later calls of other sizes neither grow nor
+    reallocate device memory (growing per call used to free and reallocate
+    buffers while other calls ran), and their results equal the oracle's."""
+    w = synth.workload_small(40000, 128, 256, temp=0.2, seed_offset=33)
+    F = np.asarray(w.feats)
+    idx = gt.GTIndex(torch.from_numpy(F).cuda(), pools=("f32", "bf16"))
+    ws = gt.Workspace(idx, 256)
+    Q = torch.from_numpy(w.queries).cuda()
+    sizes = (3, 70, 256, 1, 129)
+    seen = []
+    for k in sizes:
+        say(f"workspace call of {k} queries")
+        ws.submit(Q[:k], 0.9, pool="bf16")
+        res = ws.finish()
+        torch.cuda.synchronize()
+        seen.append(idx.stats()["bytes_device"])
+        ora = ob.range_search(F, w.queries[:k], 0.9)
+        for (gi, _), (oi, _) in zip(res.to_lists(), ora):
+            assert np.array_equal(gi, oi)
+    assert len(set(seen)) == 1, seen
+    ws.close()
+    idx.close()
