@@ -241,7 +241,13 @@ gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int
  *                 steps only the last dense level is tested)
  *   "grid"        workgroups of the persistent walk kernels (0 = one per CU)
  *   "dense_last"  last level tested with dense steps, every pool against every
- *                 query (-2 = automatic, -1 = none; bf16 and fp8 pools only)
+ *                 query (-2 = automatic, -1 = none; bf16 and fp8 pools only).
+ *                 Automatic: the level whose pools hold about 16 populated
+ *                 rows; for rows of 512 or more columns each workspace then
+ *                 moves it from call to call by the frontier density its last
+ *                 call of the same format met (deeper while the entries of a
+ *                 level fill more than 4.6e-4 x row length of its populated
+ *                 (pool, query tile) pairs)
  *   "walk_subtract" subtraction step of the bf16 walk after a dense step (paper
  *                 Sec. 2, Alg. 1: one dot product per split, the other half
  *                 bounded by the pool's score minus it): 0 off, 1 every sparse

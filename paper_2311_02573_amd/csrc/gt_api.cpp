@@ -95,6 +95,36 @@ int dense_last_of(const Index* ix, int fmt, int h) {
   return dl > h ? dl : -1;
 }
 
+// Automatic dense level, per workspace, from its last walk (same format): a
+// dense step at level L + 1 costs in proportion to its pools x tiles x d_pad,
+// a sparse step in proportion to the entries of level L.  Measured on this
+// chip (d_pad 512 and 1024), the dense step is the cheaper one while the
+// entries of level L fill more than 4.6e-4 d_pad of level L's populated
+// (pool, tile) pairs.  The last call counted the entries of every level from
+// its own dense level down, so the level moves down while that holds; it
+// moves up one level when the density at the last dense level is below half
+// the threshold (the level above has about twice the density: its pools are
+// half as many and the entries about as many).  Only for rows of 512
+// columns or more, where the costs were measured.  Results never depend on it.
+int adapt_dense_last(const Index* ix, const Batch* b, int fmt, bool maxp, int dl, int h) {
+  const int width = maxp ? ix->pw : ix->dp;
+  if (ix->dense_last != -2 || dl < 0 || width < 512 || !b->have_last || b->last_dl < 0 ||
+      b->last_walk_fmt != fmt || b->last_maxpool != maxp || b->last_walk_nt <= 0)
+    return dl;
+  const int D = ix->depth;
+  const double thr = 4.6e-4 * width;
+  auto density = [&](int L) {
+    const int64_t span = int64_t(1) << (D - L);
+    const int64_t pop =
+        std::min<int64_t>(int64_t(1) << L, (b->last_n_epoch + span - 1) / span);
+    return pop > 0 ? (double)b->last_entries[L] / ((double)pop * b->last_walk_nt) : 0.0;
+  };
+  int L = std::min(b->last_dl, D - 1);
+  while (L + 1 <= D - 1 && density(L) > thr) ++L;
+  if (L == b->last_dl && L - 1 > h && density(L) < 0.5 * thr) --L;
+  return L > h ? L : dl;
+}
+
 // Bucket bits of a call's sparse frontier: subtrees of level nb, at most
 // 2^7 of them and at most kMaxSlots (bucket, tile) slots, never deeper than
 // the level where the sparse frontier starts.
@@ -633,6 +663,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   b->n_epoch = ix->n;
   b->head = head_of(ix);
   b->dense_last = kind == 1 ? dense_last_of(ix, fmt, b->head) : -1;
+  if (kind == 1) b->dense_last = adapt_dense_last(ix, b, fmt, maxp, b->dense_last, b->head);
   // A dense step computes every pool of its level against every query, and
   // a pool's score never exceeds its parent's (non-negative rows, sums
   // rounded up), so a chain of dense steps keeps the same (pool, query) pairs
@@ -681,6 +712,8 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
       TRY(enqueue_walk(ix, b));
       ev_mark(b, 2);
       TRY(enqueue_leaf(ix, b));
+      if (ix->dense_last == -2 && b->dense_last >= 0)
+        HIPCHK(gt::launch_level_entries(b->lvl_count, ix->depth, b->ctr, s));
     } else {
       TRY(enqueue_exhaustive(ix, b));
       ev_mark(b, 2);
@@ -734,6 +767,16 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
     }
     if (hit_over) TRY(grow_hits(b, (int64_t)c.nhits));
     TRY(redo_candidates(ix, b));
+  }
+  if (b->kind == 1) {
+    // state for the next call's automatic dense level
+    b->have_last = true;
+    b->last_dl = b->dense_last;
+    b->last_walk_fmt = b->fmt;
+    b->last_maxpool = b->maxpool;
+    b->last_walk_nt = b->nt;
+    b->last_n_epoch = b->n_epoch;
+    memcpy(b->last_entries, b->h_ctr->entries, sizeof(b->last_entries));
   }
   const int64_t total = (int64_t)b->h_ctr->total;
   *total_out = total;

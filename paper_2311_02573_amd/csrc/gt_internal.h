@@ -57,6 +57,7 @@ struct DevCounters {
   unsigned int err;                 // invalid query input seen
   unsigned int slot_over;           // a query reached kMaxResultsPerQuery results
   unsigned long long pairs[GT_MAX_LEVELS];
+  unsigned long long entries[GT_MAX_LEVELS];  // frontier (pool, tile) entries per level
 };
 
 // Arguments of one level step of the frontier walk (parents at `level`,
@@ -150,6 +151,11 @@ struct Batch {
   uint64_t* fr_mask[2] = {nullptr, nullptr};
   uint16_t* fr_rec[2] = {nullptr, nullptr};  // score records (64 per entry)
   bool maxpool = false;      // the call walks the max-pool tree
+  // the last finished walk of this workspace (automatic dense level)
+  bool have_last = false, last_maxpool = false;
+  int last_dl = -1, last_walk_fmt = 0, last_walk_nt = 0;
+  int64_t last_n_epoch = 0;
+  unsigned long long last_entries[GT_MAX_LEVELS] = {};
   float* sabs = nullptr;                     // [nq_pad] lower-bound absolute terms
   int64_t fr_cap = 0;        // entries per tile per buffer
   int64_t rec_len = 0;       // entries of each fr_rec buffer
@@ -269,6 +275,8 @@ hipError_t launch_signed_bottom(const float* leaves, float* parent, int64_t firs
                                 int dp, int d, int64_t n, float bound, hipStream_t s);
 hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, int dp,
                               int64_t first, hipStream_t s, bool max_pool);
+hipError_t launch_level_entries(const uint32_t* lvl_count, int levels, DevCounters* ctr,
+                                hipStream_t s);
 hipError_t launch_level_max(const float* rows, int64_t nrows, int dp, float* out_max, hipStream_t s);
 hipError_t launch_quant_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
 hipError_t launch_quant_fp8(const float* src, uint8_t* dst, int64_t count, int lexp,

@@ -155,6 +155,20 @@ __global__ void k_signed_bottom(const float* __restrict__ leaves, float* __restr
   }
 }
 
+// Frontier entries per level of a call: the sum of the level's per-slot
+// counters (one workgroup per level).
+__global__ __launch_bounds__(256) void k_level_entries(const uint32_t* __restrict__ counts,
+                                                       DevCounters* ctr) {
+  __shared__ unsigned long long part[4];
+  const int l = blockIdx.x, t = threadIdx.x;
+  unsigned long long sum = 0;
+  for (int k = t; k < kMaxSlots; k += blockDim.x) sum += counts[(size_t)l * kMaxSlots + k];
+  for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if ((t & 63) == 0) part[t >> 6] = sum;
+  __syncthreads();
+  if (t == 0) ctr->entries[l] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
 __global__ void k_level_max(const float* __restrict__ rows, int64_t count, float* out) {
   float m = 0.0f;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
@@ -353,6 +367,14 @@ hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, 
   else
     hipLaunchKernelGGL(k_build_level<false>, dim3(grid_for(nodes * (dp / 4), 256)), dim3(256), 0, s,
                        child, parent, first, nodes, dp);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_entries(const uint32_t* lvl_count, int levels, DevCounters* ctr,
+                                hipStream_t s) {
+  if (levels <= 0) return hipSuccess;
+  if (levels > GT_MAX_LEVELS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_level_entries, dim3(levels), dim3(256), 0, s, lvl_count, ctr);
   return hipGetLastError();
 }
 
