@@ -713,7 +713,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
       ev_mark(b, 2);
       TRY(enqueue_leaf(ix, b));
       if (ix->dense_last == -2 && b->dense_last >= 0)
-        HIPCHK(gt::launch_level_entries(b->lvl_count, ix->depth, b->ctr, s));
+        HIPCHK(gt::launch_level_entries(b->lvl_count, b->dense_last, ix->depth, b->ctr, s));
     } else {
       TRY(enqueue_exhaustive(ix, b));
       ev_mark(b, 2);

@@ -275,8 +275,8 @@ hipError_t launch_signed_bottom(const float* leaves, float* parent, int64_t firs
                                 int dp, int d, int64_t n, float bound, hipStream_t s);
 hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, int dp,
                               int64_t first, hipStream_t s, bool max_pool);
-hipError_t launch_level_entries(const uint32_t* lvl_count, int levels, DevCounters* ctr,
-                                hipStream_t s);
+hipError_t launch_level_entries(const uint32_t* lvl_count, int first, int levels,
+                                DevCounters* ctr, hipStream_t s);
 hipError_t launch_level_max(const float* rows, int64_t nrows, int dp, float* out_max, hipStream_t s);
 hipError_t launch_quant_bf16(const float* src, uint16_t* dst, int64_t count, hipStream_t s);
 hipError_t launch_quant_fp8(const float* src, uint8_t* dst, int64_t count, int lexp,

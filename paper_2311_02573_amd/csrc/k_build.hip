@@ -156,17 +156,25 @@ __global__ void k_signed_bottom(const float* __restrict__ leaves, float* __restr
 }
 
 // Frontier entries per level of a call: the sum of the level's per-slot
-// counters (one workgroup per level).
-__global__ __launch_bounds__(256) void k_level_entries(const uint32_t* __restrict__ counts,
-                                                       DevCounters* ctr) {
-  __shared__ unsigned long long part[4];
-  const int l = blockIdx.x, t = threadIdx.x;
+// counters (one workgroup per level, levels first .. levels-1; 16-byte loads).
+__global__ __launch_bounds__(1024) void k_level_entries(const uint32_t* __restrict__ counts,
+                                                        int first, DevCounters* ctr) {
+  __shared__ unsigned long long part[16];
+  const int l = first + blockIdx.x, t = threadIdx.x;
+  const uint4* c4 = reinterpret_cast<const uint4*>(counts + (size_t)l * kMaxSlots);
   unsigned long long sum = 0;
-  for (int k = t; k < kMaxSlots; k += blockDim.x) sum += counts[(size_t)l * kMaxSlots + k];
+  for (int k = t; k < kMaxSlots / 4; k += blockDim.x) {
+    const uint4 v = c4[k];
+    sum += (unsigned long long)v.x + v.y + v.z + v.w;
+  }
   for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
   if ((t & 63) == 0) part[t >> 6] = sum;
   __syncthreads();
-  if (t == 0) ctr->entries[l] = (part[0] + part[1]) + (part[2] + part[3]);
+  if (t == 0) {
+    unsigned long long tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += part[w];
+    ctr->entries[l] = tot;
+  }
 }
 
 __global__ void k_level_max(const float* __restrict__ rows, int64_t count, float* out) {
@@ -370,11 +378,12 @@ hipError_t launch_build_level(const float* child, float* parent, int64_t nodes, 
   return hipGetLastError();
 }
 
-hipError_t launch_level_entries(const uint32_t* lvl_count, int levels, DevCounters* ctr,
-                                hipStream_t s) {
-  if (levels <= 0) return hipSuccess;
-  if (levels > GT_MAX_LEVELS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_level_entries, dim3(levels), dim3(256), 0, s, lvl_count, ctr);
+hipError_t launch_level_entries(const uint32_t* lvl_count, int first, int levels,
+                                DevCounters* ctr, hipStream_t s) {
+  if (first < 0 || levels > GT_MAX_LEVELS) return hipErrorInvalidValue;
+  if (first >= levels) return hipSuccess;
+  hipLaunchKernelGGL(k_level_entries, dim3(levels - first), dim3(1024), 0, s, lvl_count, first,
+                     ctr);
   return hipGetLastError();
 }
 
