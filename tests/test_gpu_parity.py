@@ -476,3 +476,28 @@ def test_max_pools_clustered_near_duplicates(gtmod):
             assert_same(idx.query(q, w.rho, pool=f).to_lists(), ora, f"clusters {f}")
     finally:
         idx.close()
+
+
+def test_adaptive_dense_level_keeps_results(gtmod):
+    """The automatic dense level moves from call to call with the frontier
+    density of the previous call (rows of 512+ columns): on a clustered index
+    with thousands of neighbours for some queries, every call, whatever level
+    it chose, returns the oracle's set."""
+    w = synth.workload4(n=1 << 15, d=512, nq=64, clusters=4, per_cluster=2000)
+    ora = ob.range_search(w.feats, w.queries, w.rho)
+    idx = gtmod.GTIndex(_dev(w.feats), pools=("f32", "bf16"))
+    q = _dev(w.queries, torch.float32)
+    heads = []
+    try:
+        for call in range(4):
+            say(f"adaptive dense level, call {call}")
+            assert_same(idx.query(q, w.rho, pool="bf16").to_lists(), ora, f"adaptive call {call}")
+            heads.append(idx.stats()["head_level"])
+        say(f"dense levels chosen: {[h + 1 for h in heads]}")
+        assert all(0 <= h < idx.stats()["depth"] for h in heads)
+        # the first call uses the fixed rule; its dense frontier moves the
+        # following calls' dense level down (entry counts are exact, so this
+        # is deterministic for the seeded workload: levels 11 -> 14)
+        assert heads[1] > heads[0] and heads[2] == heads[1]
+    finally:
+        idx.close()
