@@ -354,7 +354,7 @@ def main():
             comparators[f"walk_{pool}_qps"] = round(args.nq * args.side_steps / wall2, 1)
             comparators[f"walk_{pool}_ms"] = round(wall2 / args.side_steps * 1e3, 3)
             if pool == "max_bf16":
-                # Our-Max pools (paper Sec. 3): same result set, other pruning
+                # Our-Max pools (paper Sec. 2): same result set, other pruning
                 comparators["walk_max_bf16_results_identical"] = r2.total == res.total and all(
                     np.array_equal(a[0], b[0]) for a, b in zip(r2.to_lists(), res.to_lists()))
                 idx.set_option("profile", 1)
@@ -466,7 +466,7 @@ def cpu_baseline(w, ns, nq, rho, walk_lists):
 
 
 def signed_leg(args, torch, gt, synth, dev):
-    """Descriptors with negative values (paper Sec. 3: max/min pools): centred
+    """Descriptors with negative values (paper Sec. 2: max/min pools): centred
     softmax rows unit(softmax(z/0.2) - 1/d), N = signed_n, d = 512 (the signed
     index's limit), 1024 queries with planted neighbours, rho = args.rho.  The
     max/min walk over bfloat16 and float32 rows and the exhaustive path on the

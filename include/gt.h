@@ -56,13 +56,13 @@ typedef enum { GT_F32 = 0, GT_F16 = 1, GT_BF16 = 2 } gt_dtype; /* feature storag
  * upward; the reduced formats are upward-rounded copies (bfloat16, and float8
  * e4m3 with one power-of-two scale per tree level).  The MAX formats are a
  * second tree whose pools are the element-wise maximum of their members
- * (paper Sec. 3, Our-Max: a query scores a max pool at least as high as any
+ * (paper Sec. 2, Our-Max: a query scores a max pool at least as high as any
  * member, so the same prune rule holds), float32 (exact) and a bfloat16 copy
  * rounded upward; asking for GT_POOL_MAX_BF16 also builds GT_POOL_MAX_F32.
  * Bit mask at build time, one value per query call.
  *
  * GT_POOL_SIGNED (build-time flag only): vectors and queries may have values
- * of any sign (paper Sec. 3, negative descriptors: a pool keeps the
+ * of any sign (paper Sec. 2, negative descriptors: a pool keeps the
  * element-wise maximum and minimum of its members and a query scores it with
  * the maximum where its component is >= 0 and the minimum where it is < 0,
  * which bounds every member's dot product from above).  Sums no longer bound
@@ -148,7 +148,7 @@ gt_status gt_insert(gt_index* index, const void* feats_dev, int64_t n_new, void*
                     int64_t* first_id_out);
 
 /* Range query by the level-wise binary-splitting walk (paper Sec. 2, Alg. 1,
- * visited one level per round as analysed in Sec. 5).
+ * visited one level per round as analysed in Sec. 4).
  *   q_dev      [nq x d] float32 queries, finite and >= 0 (finite, of any
  *              sign, on a GT_POOL_SIGNED index).
  *   rho_host   [nq] float64 thresholds.  rho <= 0 returns every non-zero row

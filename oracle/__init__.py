@@ -8,10 +8,10 @@ Contents (each function cites the passage of the paper it follows):
   brute    canonical float64 brute-force cosine range scan, in C (range_oracle.c)
   exact    the same decision in exact rational arithmetic; the paper's iterative
            binary-splitting algorithm (Sec. 2, Alg. 1) and its level-wise order
-           (Sec. 5), run in rationals, for tiny inputs; the same walk over
-           Our-Max pools and over max/min pools of vectors of any sign (Sec. 3)
+           (Sec. 4), run in rationals, for tiny inputs; the same walk over
+           Our-Max pools and over max/min pools of vectors of any sign (Sec. 2)
   pools    explicit pool-sum tree in float64 with error bounds (Sec. 2, Eq. 1),
-           Our-Max and max/min trees (Sec. 3)
+           Our-Max and max/min trees (Sec. 2)
   formats  bfloat16 / float8 e4m3 value tables and the least representable
            value >= x, from the formats' definitions
 

@@ -46,7 +46,6 @@ def _load(path: str | None = None):
         lib.oracle_result_copy.argtypes = [vp, i32, vp, vp]
         lib.oracle_result_free.argtypes = [vp]
         lib.oracle_pair_cos.argtypes = [vp, ctypes.c_int, i32, vp, vp, vp, i64, vp]
-        lib.oracle_row_sqnorms.argtypes = [vp, ctypes.c_int, i64, i32, vp]
         _libs[path] = lib
     return _libs[path]
 
@@ -107,11 +106,3 @@ def pair_cos(feats, queries, qidx, rows, lib_path: str | None = None):
                         len(qi), out.ctypes.data)
     return out
 
-
-def row_sqnorms(feats):
-    lib = _load()
-    f, code = _feats_view(feats)
-    n, d = f.shape
-    out = np.empty(n, np.float64)
-    lib.oracle_row_sqnorms(f.ctypes.data, code, n, d, out.ctypes.data)
-    return out

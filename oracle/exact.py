@@ -6,17 +6,18 @@ Everything here works on Python Fractions, so no rounding is involved:
   of the problem statement (Sec. 1; cosine of non-negative vectors, Sec. 2),
   decided without square roots: for rho >= 0 it is dot >= 0 and
   dot^2 >= rho^2 * qq * ff; for rho < 0 it is dot >= 0 or dot^2 <= rho^2 qq ff.
-* `binary_splitting`: the paper's iterative binary splitting (Sec. 2, Alg. 1),
-  driven by a stack of (start, end, score) triples over the cumulative sums of
-  Eq. 1, with the right half tested directly and the left half's score obtained
-  by subtraction.  Similarity is the dot product q.f as in Sec. 2.
+* `binary_splitting`: the paper's binary splitting (Sec. 2, Eq. 1; Alg. 1 is
+  the same procedure run with a stack), as a recursion over index ranges whose
+  pools are differences of cumulative sums, with the right half tested
+  directly and the left half's score obtained by subtraction.  Similarity is
+  the dot product q.f as in Sec. 2.
 * `levelwise_walk`: the same implicit tree visited one level ("round") at a
-  time (Sec. 5 analyses pruning per round), over a power-of-two capacity with
+  time (Sec. 4 analyses pruning per round), over a power-of-two capacity with
   zero padding, testing both children of every surviving pool directly.
-* `levelwise_walk_max`: that walk with Our-Max pools (Sec. 3), each pool the
+* `levelwise_walk_max`: that walk with Our-Max pools (Sec. 2), each pool the
   element-wise maximum of its members.
 * `levelwise_walk_signed`: the extension of Our-Max to descriptors with
-  negative values (Sec. 3): a pool keeps the element-wise maximum and minimum
+  negative values (Sec. 2): a pool keeps the element-wise maximum and minimum
   of its members and is scored with the maximum where the query component is
   non-negative and the minimum where it is negative.
 
@@ -86,56 +87,48 @@ def prefix_sums(F):
 
 
 def binary_splitting(F, q, rho):
-    """Sec. 2, Alg. 1, in exact arithmetic with sim = q.f.  Returns the sorted
-    list of flagged (neighbour) indices, 0-based, and the number of dot products.
+    """Binary splitting over cumulative sums (Sec. 2 and Eq. 1), in exact
+    arithmetic with sim = q.f.  Returns the sorted 0-based neighbour ids and
+    the number of dot products taken.
 
-    A pool is a contiguous index range [si, ei].  A pool whose score is below
-    rho is dropped whole.  Otherwise a pool of more than two members is split
-    with floor(n/2) members on the left; the right half is tested with one dot
-    product against a difference of cumulative sums, and the left half's score
-    is the parent's score minus the right half's.  Two-member pools test the
-    right member and derive the left; a single member is flagged directly.
+    Definition followed: the pool of all N vectors is tested first; a pool
+    scoring below rho holds no neighbour and is dropped; a pool that reaches
+    rho and has more than one member is split into its first floor(n/2)
+    members and the rest, and both halves are treated the same way; a
+    single-member pool is a neighbour iff its own score reaches rho.  A pool
+    of rows [a, b) is C[b] - C[a] with the cumulative sums C of Eq. 1, so only
+    the right half of a split costs a dot product; the left half's score is
+    the parent's minus the right half's (pools are sums, so scores add).
     """
     N = len(F)
     if N == 0:
         return [], 0
     qf = [Fraction(float(x)) for x in q]
-    F = [[Fraction(float(x)) for x in f] for f in F]
-    C = prefix_sums(F)
+    C = prefix_sums([[Fraction(float(x)) for x in f] for f in F])
     r = Fraction(float(rho))
 
-    def pool_score(a, b):  # rows a..b inclusive
-        return dot(qf, [hi - lo for hi, lo in zip(C[b + 1], C[a])])
+    def score(a, b):  # q . (f_a + ... + f_{b-1})
+        return dot(qf, [hi - lo for hi, lo in zip(C[b], C[a])])
 
-    flags = [0] * N
-    ndots = 1
-    stack = [(0, N - 1, pool_score(0, N - 1))]
-    while stack:
-        si, ei, sim = stack.pop()
-        if sim < r:
-            continue
-        n = ei - si + 1
-        if n > 2:
-            half = n // 2
-            rsim = pool_score(si + half, ei)
-            ndots += 1
-            stack.append((si + half, ei, rsim))
-            stack.append((si, si + half - 1, sim - rsim))
-        elif n == 2:
-            rsim = pool_score(ei, ei)
-            ndots += 1
-            if rsim >= r:
-                flags[ei] = 1
-            if sim - rsim >= r:
-                flags[si] = 1
-        else:
-            flags[si] = 1
-    return [i for i in range(N) if flags[i]], ndots
+    def neighbours(a, b, s):
+        """(ids of neighbours among rows [a, b), dot products spent below)."""
+        if s < r:
+            return set(), 0
+        if b - a == 1:
+            return {a}, 0
+        m = a + (b - a) // 2
+        s_right = score(m, b)
+        left, n_left = neighbours(a, m, s - s_right)
+        right, n_right = neighbours(m, b, s_right)
+        return left | right, 1 + n_left + n_right
+
+    ids, spent = neighbours(0, N, score(0, N))
+    return sorted(ids), 1 + spent
 
 
 def levelwise_walk(F, q, rho, capacity: int | None = None):
     """Level-by-level walk of an explicit pool-sum tree (Sec. 2 pools, visited
-    per round as in Sec. 5) over a power-of-two capacity, zero-padded; both
+    per round as in Sec. 4) over a power-of-two capacity, zero-padded; both
     children of each surviving pool are tested directly, and a leaf is a
     member iff its own score reaches rho.  Returns (ids, tests per level)."""
     N = len(F)
@@ -166,7 +159,7 @@ def levelwise_walk(F, q, rho, capacity: int | None = None):
 
 
 def levelwise_walk_max(F, q, rho, capacity: int | None = None):
-    """The same level-by-level walk with Our-Max pools (Sec. 3): a pool is the
+    """The same level-by-level walk with Our-Max pools (Sec. 2): a pool is the
     element-wise maximum of its members.  For non-negative q and members,
     q.max >= q.f_i for every member i, so a pool scoring below rho holds no
     neighbour.  Both children of each surviving pool are tested directly; a
@@ -201,7 +194,7 @@ def levelwise_walk_max(F, q, rho, capacity: int | None = None):
 
 
 def signed_pool_score(q, mx, mn):
-    """Score of a max/min pool (Sec. 3, negative descriptors): sum over k of
+    """Score of a max/min pool (Sec. 2, negative descriptors): sum over k of
     q_k * max_k where q_k >= 0 and q_k * min_k where q_k < 0.  Each term is the
     largest value q_k * f_k takes over the members, so the score bounds every
     member's q.f from above."""

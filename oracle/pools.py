@@ -46,14 +46,8 @@ def pool_scores(levels, q):
     return [lv @ qv for lv in levels]
 
 
-def members(level: int, node: int, depth: int):
-    """Row range [lo, hi) covered by node `node` of `level` in a depth-`depth` tree."""
-    span = 1 << (depth - level)
-    return node * span, (node + 1) * span
-
-
 def max_pool_tree(feats, capacity: int | None = None):
-    """Our-Max pools (Sec. 3): levels[l] = float64 [2^l, d], node j the
+    """Our-Max pools (Sec. 2): levels[l] = float64 [2^l, d], node j the
     element-wise maximum of its members (exact: a maximum of float32 values is
     one of them); levels[D] are the (zero-padded) leaves."""
     f = np.asarray(feats, dtype=np.float64)
@@ -71,7 +65,7 @@ def max_pool_tree(feats, capacity: int | None = None):
 
 
 def max_min_pool_tree(feats, capacity: int | None = None):
-    """Max/min pools for vectors of any sign (Sec. 3, negative descriptors):
+    """Max/min pools for vectors of any sign (Sec. 2, negative descriptors):
     (maxes, mins), each a list of float64 levels [2^l, d] like `pool_tree`;
     node j holds the element-wise maximum / minimum over its members (exact).
     Padding slots past N are not members: a node without members holds -inf

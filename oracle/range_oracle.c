@@ -198,15 +198,3 @@ void oracle_pair_cos(const void* feats, int dtype, int32_t d, const float* q,
     out[p] = dot / (sqrt(qq) * sqrt(ff));
   }
 }
-
-/* Canonical sequential float64 squared norms of rows. */
-void oracle_row_sqnorms(const void* feats, int dtype, int64_t n, int32_t d, double* out) {
-  for (int64_t i = 0; i < n; ++i) {
-    double acc = 0.0;
-    for (int32_t k = 0; k < d; ++k) {
-      double x = load_elem(feats, dtype, i * (int64_t)d + k);
-      acc = acc + x * x;
-    }
-    out[i] = acc;
-  }
-}

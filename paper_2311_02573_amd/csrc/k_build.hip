@@ -92,7 +92,7 @@ __global__ __launch_bounds__(64) void k_ingest(const void* src, int dtype, int64
 // parent = children summed with upward rounding, 4 columns per thread.
 // Parent pools of `nodes` nodes from their two children: the element-wise sum
 // rounded up (sum pooling, paper Sec. 2) or the element-wise maximum, which is
-// exact (Our-Max pooling, Sec. 3).
+// exact (Our-Max pooling, Sec. 2).
 template <bool MAXP>
 __global__ void k_build_level(const float* __restrict__ child, float* __restrict__ parent,
                               int64_t first, int64_t nodes, int dp) {
@@ -120,7 +120,7 @@ __global__ void k_build_level(const float* __restrict__ child, float* __restrict
   }
 }
 
-// Bottom level of the max/min tree of a signed index (paper Sec. 3, negative
+// Bottom level of the max/min tree of a signed index (paper Sec. 2, negative
 // descriptors).  Pool j of level depth-1 holds leaves 2j and 2j+1; only leaves
 // below n are members.  Row j gets [max_k + B | B - min_k] over its members in
 // columns k < d, each term rounded up (every term is >= 0 because |f_k| <= B),

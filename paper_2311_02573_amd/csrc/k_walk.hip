@@ -1,5 +1,5 @@
 // The level-wise binary-splitting walk (paper Sec. 2, Alg. 1; one level per
-// round as in the pruning analysis of Sec. 5), the exact leaf test, the
+// round as in the pruning analysis of Sec. 4), the exact leaf test, the
 // float64 recheck and the result compaction.
 //
 // Frontier representation.  Queries are grouped in tiles of TQ (64 for bf16 /

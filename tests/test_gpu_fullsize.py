@@ -1,11 +1,16 @@
-"""Full-size parity: N = 2^20 softmax vectors, d = 1000, 1024 queries per batch
-(the benchmark's workload and launch configuration).
+"""Full-size parity: N = 2^20 softmax vectors, d = 1000 (the benchmark's
+database), in the two launch shapes the benchmark times: 1024-query batches
+(every pool format and the exhaustive GEMM) and 4096-query batches (bfloat16
+and float8 pools, the precision variant).
 
-The oracle cannot scan all 1024 queries in test time, so it checks a sample of
-queries one by one; for the whole batch, the properties that hold at any size
-are checked: every walk format and the exhaustive GEMM return identical id sets
-and identical similarities, planted neighbours whose cosine reaches rho are
-returned, and every returned id is a valid row.
+The oracle cannot scan whole batches in test time, so it checks a sample of
+64 queries of each batch element by element, for every rho and every path
+(one float64 scan at the lowest rho; the sets at higher rho are its
+sub-sets, the canonical cosine being the same).  For the whole batch the
+properties that hold at any size are checked: every walk format and the
+exhaustive GEMM return identical id sets and identical similarities, planted
+neighbours whose cosine reaches rho are returned, and every returned id is a
+valid row.
 """
 import numpy as np
 import pytest
@@ -15,6 +20,9 @@ import oracle.brute as ob
 from paper_2311_02573_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+RHOS = (0.8, 0.9, 0.95)
+SAMPLE = 64
 
 
 def say(msg):
@@ -27,47 +35,88 @@ def setup():
         pytest.fail("no GPU visible")
     from paper_2311_02573_amd import gt
 
-    say("generate N=2^20 d=1000")
-    w = synth.workload1(nq=1024)
+    say("generate N=2^20 d=1000, 4096 queries")
+    w = synth.workload1(nq=4096)
     idx = gt.GTIndex(torch.from_numpy(w.feats).cuda())
     q = torch.from_numpy(w.queries).cuda()
     yield gt, w, idx, q
     idx.close()
 
 
-def test_fullsize_sampled_oracle_and_cross_path_identity(setup):
+def _sample(lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    return np.sort(np.concatenate([np.arange(lo, lo + 4),
+                                   rng.choice(np.arange(lo + 4, hi), SAMPLE - 4, replace=False)]))
+
+
+def _check_sample(lists, ora, sample, rho, label):
+    for j, b in enumerate(sample):
+        oi, os_ = ora[j]
+        keep = os_ >= rho
+        np.testing.assert_array_equal(lists[b][0], oi[keep], err_msg=f"{label} oracle q{b} rho={rho}")
+        if keep.any():
+            err = np.max(np.abs(lists[b][1].astype(np.float64) - os_[keep]))
+            assert err <= 1e-6, f"{label} q{b} rho={rho}: similarity error {err}"
+
+
+def _check_identical(runs, nq, rho, n):
+    ref = next(iter(runs.values()))
+    for name, lists in runs.items():
+        for b in range(nq):
+            np.testing.assert_array_equal(lists[b][0], ref[b][0], err_msg=f"{name} q{b} rho={rho}")
+            np.testing.assert_array_equal(lists[b][1], ref[b][1], err_msg=f"{name} q{b} rho={rho}")
+    assert all(len(x[0]) == 0 or (x[0].min() >= 0 and x[0].max() < n) for x in ref)
+    return sum(len(x[0]) for x in ref)
+
+
+def test_fullsize_1024_every_path_against_oracle_sample(setup):
     gt, w, idx, q = setup
-    rng = np.random.default_rng(5)
-    sample = np.concatenate([np.arange(4), rng.choice(np.arange(4, 1024), 6, replace=False)])
-    say("oracle sample at rho=0.8")
-    ora = ob.range_search(w.feats, w.queries[sample], 0.8)
-    for rho in (0.8, 0.9, 0.95):
+    nq = 1024
+    sample = _sample(0, nq, 5)
+    say(f"oracle: {SAMPLE} queries of the 1024 batch at rho={RHOS[0]}")
+    ora = ob.range_search(w.feats, w.queries[sample], RHOS[0])
+    for rho in RHOS:
         runs = {}
         for f in ("bf16", "f32", "fp8"):
-            say(f"walk {f} rho={rho}")
-            runs[f] = idx.query(q, rho, pool=f).to_lists()
-        say(f"exhaustive rho={rho}")
-        runs["exh"] = idx.exhaustive(q, rho).to_lists()
-        ref = runs["bf16"]
+            say(f"1024 queries, walk {f} rho={rho}")
+            runs[f] = idx.query(q[:nq], rho, pool=f).to_lists()
+        say(f"1024 queries, exhaustive rho={rho}")
+        runs["exh"] = idx.exhaustive(q[:nq], rho).to_lists()
         for name, lists in runs.items():
-            for b in range(1024):
-                np.testing.assert_array_equal(lists[b][0], ref[b][0], err_msg=f"{name} q{b} rho={rho}")
-                np.testing.assert_array_equal(lists[b][1], ref[b][1], err_msg=f"{name} q{b} rho={rho}")
-        for j, b in enumerate(sample):
-            oi, os_ = ora[j]
-            keep = os_ >= rho
-            np.testing.assert_array_equal(ref[b][0], oi[keep], err_msg=f"oracle q{b} rho={rho}")
-            if keep.any():
-                assert np.max(np.abs(ref[b][1].astype(np.float64) - os_[keep])) <= 1e-6
-        nres = sum(len(x[0]) for x in ref)
-        assert all(len(x[0]) == 0 or (x[0].min() >= 0 and x[0].max() < w.n) for x in ref)
+            _check_sample(lists, ora, sample, rho, name)
+        nres = _check_identical(runs, nq, rho, w.n)
         say(f"rho={rho}: {nres} results")
         assert nres > 0
 
 
+def test_fullsize_4096_precision_variant(setup):
+    """4096-query batches (64 tiles of 64 queries: more tiles than walk
+    workgroups per XCD on 256 CUs) with bfloat16 and float8 pools."""
+    gt, w, idx, q = setup
+    nq = 4096
+    sample = _sample(0, nq, 6)
+    say(f"oracle: {SAMPLE} queries of the 4096 batch at rho={RHOS[0]}")
+    ora = ob.range_search(w.feats, w.queries[sample], RHOS[0])
+    for rho in RHOS:
+        runs = {}
+        for f in ("bf16", "fp8"):
+            say(f"4096 queries, walk {f} rho={rho}")
+            runs[f] = idx.query(q, rho, pool=f).to_lists()
+            st = idx.stats()
+            assert st["last_nq"] == nq and st["last_tiles"] == 64
+            _check_sample(runs[f], ora, sample, rho, f"4096 {f}")
+        nres = _check_identical(runs, nq, rho, w.n)
+        say(f"4096 queries rho={rho}: {nres} results")
+        # the first 1024 queries of the batch give what they give alone
+        alone = idx.query(q[:1024], rho, pool="bf16").to_lists()
+        for b in range(1024):
+            np.testing.assert_array_equal(alone[b][0], runs["bf16"][b][0])
+            np.testing.assert_array_equal(alone[b][1], runs["bf16"][b][1])
+
+
 def test_fullsize_planted_neighbours_found(setup):
     gt, w, idx, q = setup
-    res = idx.query(q, 0.9, pool="bf16").to_lists()
+    res = idx.query(q[:1024], 0.9, pool="bf16").to_lists()
     found = total = 0
     for b in range(1024):
         p = w.planted[b]

@@ -390,7 +390,7 @@ MAX_POOLS = ("f32", "bf16", "max_f32", "max_bf16")
 
 
 def test_max_pool_tree_is_the_elementwise_maximum(gtmod):
-    """Our-Max pools (paper Sec. 3): every stored float32 max pool equals the
+    """Our-Max pools (paper Sec. 2): every stored float32 max pool equals the
     element-wise maximum of its members (the oracle's max tree, exactly), and
     the bfloat16 copy is the least bfloat16 >= it (values below 2^-126
     raised to 2^-126, as for sum pools)."""
@@ -501,3 +501,57 @@ def test_adaptive_dense_level_keeps_results(gtmod):
         assert heads[1] > heads[0] and heads[2] == heads[1]
     finally:
         idx.close()
+
+
+# ------------------------------------------------- launch shapes and big segments
+@pytest.mark.parametrize("grid", [8, 16, 24])
+def test_more_tiles_than_workgroups_per_xcd(gtmod, grid):
+    """The persistent walk kernels split the query tiles over the workgroups
+    of each XCD; with fewer workgroups per XCD than tiles (grid / 8 < tiles)
+    each workgroup walks several tiles in turn.  A small grid reaches that
+    branch with a few hundred queries: every pool format, the subtraction step
+    on and off, dense steps on and off, against the oracle."""
+    w = synth.workload_small(12000, 200, 300, temp=0.2, seed_offset=30)
+    F = np.asarray(w.feats)
+    idx = gtmod.GTIndex(_dev(F))
+    idx.set_option("grid", grid)
+    q = _dev(w.queries)
+    rho = np.linspace(0.7, 0.95, len(w.queries))
+    ora = ob.range_search(F, w.queries, rho)
+    try:
+        for dl, ws in ((-2, -1), (-2, 0), (-1, 0), (9, 2)):
+            idx.set_option("dense_last", dl)
+            idx.set_option("walk_subtract", ws)
+            for f in FORMATS:
+                say(f"grid={grid} dense_last={dl} walk_subtract={ws} {f}")
+                assert_same(idx.query(q, rho, pool=f).to_lists(), ora,
+                            f"grid={grid} dense_last={dl} walk_subtract={ws} {f}")
+                st = idx.stats()
+                assert st["last_tiles"] * 8 > grid  # tiles outnumber workgroups per XCD
+    finally:
+        idx.close()
+
+
+def test_result_segments_beyond_4096(gtmod):
+    """Queries with more than 4096 results each take the radix-sort branch of
+    the per-query sort: rho <= 0 on 6500 rows (every non-zero row), and a
+    cluster of 6000 near-duplicates of one query at rho = 0.9 (walked down to
+    the leaves through thousands of live pools).  Ids and similarities
+    against the oracle, element by element."""
+    n, d = 9000, 96
+    w = synth.workload_small(n, d, 6, temp=0.25, seed_offset=31)
+    F = np.asarray(w.feats).copy()
+    Q = w.queries.copy()
+    g = np.random.default_rng(31)
+    # near-duplicates of query 0: its logits' softmax plus a small perturbation
+    pos = g.choice(n, size=6000, replace=False)
+    noise = np.exp(g.normal(0.0, 0.02, size=(6000, d)))
+    dup = Q[0][None, :].astype(np.float64) * noise
+    dup /= np.linalg.norm(dup, axis=1, keepdims=True)
+    F[pos] = dup.astype(np.float32)
+    F[[17, 4000]] = 0.0
+    rho = np.array([0.9, 0.0, -0.25, 0.9, 0.5, 0.95])
+    ora = ob.range_search(F, Q, rho)
+    sizes = [len(o[0]) for o in ora]
+    assert sizes[0] > 4096 and sizes[1] > 4096 and sizes[2] > 4096, sizes
+    run_all(gtmod, F, Q, rho, label="segments > 4096")

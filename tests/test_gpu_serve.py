@@ -114,3 +114,46 @@ def test_workspace_memory_is_reserved_once(gt):
     assert len(set(seen)) == 1, seen
     ws.close()
     idx.close()
+
+
+def test_serving_shape_against_oracle(gt):
+    """The serving index at its full shape: N0 = 2^22 float16 rows, d = 512,
+    capacity 2^23 (depth 23), bfloat16 pools; requests of 512, 300, 77 and 1
+    queries admitted between inserts of 100 rows, so they see three epochs.
+    A sample of every request's queries against the oracle over the rows of
+    its epoch, ids element by element, similarities within 1e-6."""
+    say("generate N0=2^22 d=512 float16")
+    w = synth.workload3()
+    idx = gt.GTIndex(w.feats.cuda(), capacity=w.capacity, pools=("f32", "bf16"))
+    Q = torch.from_numpy(w.queries).cuda()
+    srv = serve.Server(serve.GpuBackend(idx), n_workspaces=2, max_queries=512, pool="bf16")
+    added = []
+    reqs, off = [], 0
+    for i, k in enumerate((512, 300, 77, 1)):
+        r = serve.Request(i, Q[off:off + k], np.full(k, 0.9), arrival=srv.now())
+        off += k
+        srv.submit(r)
+        reqs.append(r)
+        srv.step()
+        if i < 2:
+            rows = synth.insert_rows(3, 100, w.d, w.temp, offset=500 + i)
+            rt = torch.from_numpy(rows).to(torch.float16)
+            idx.insert(rt.cuda())
+            added.append(rt)
+    srv.drain(timeout_s=120)
+    assert len({r.epoch_n for r in reqs}) == 3
+    F = torch.cat([w.feats] + added, 0)
+    rng = np.random.default_rng(40)
+    for r in reqs:
+        pick = np.sort(rng.choice(r.nq, size=min(r.nq, 24), replace=False))
+        say(f"request {r.rid}: {r.nq} queries, epoch {r.epoch_n}, oracle on {len(pick)}")
+        qs = r.queries.cpu().numpy()[pick]
+        ora = ob.range_search(F[:r.epoch_n], qs, r.rho[pick])
+        for j, b in enumerate(pick):
+            gi, gs = r.results[b]
+            oi, os_ = ora[j]
+            np.testing.assert_array_equal(gi, oi, err_msg=f"request {r.rid} query {b}")
+            if len(gs):
+                assert np.max(np.abs(gs.astype(np.float64) - os_)) <= 1e-6
+    assert sum(len(x[0]) for r in reqs for x in r.results) > 0
+    idx.close()

@@ -1,4 +1,4 @@
-"""GPU parity for vectors of any sign (paper Sec. 3, negative descriptors):
+"""GPU parity for vectors of any sign (paper Sec. 2, negative descriptors):
 max/min pools, walked through the C ABI, against the CPU oracle.
 
 Id sets must be bit-identical to the float64 brute-force oracle and reported

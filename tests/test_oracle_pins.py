@@ -108,8 +108,13 @@ def test_brute_sims_match_high_precision():
 # ------------------------------------------- the paper's algorithm, exactly
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 7, 8, 13, 16, 31])
 def test_alg1_binary_splitting_equals_brute_force(n):
-    """Sec. 2, Alg. 1 (stack-driven splitting with the subtraction for the left
-    half) returns exactly {i : q.f_i >= rho}; at most 2n - 1 dot products."""
+    """Sec. 2, binary splitting over the cumulative sums of Eq. 1 (Alg. 1 runs
+    it with a stack), with the subtraction for the left half, returns exactly
+    {i : q.f_i >= rho}; at most 2n - 1 dot products.  For a power-of-two n its
+    tree is the level-wise walk's, which tests both children of every
+    surviving pool: the splitting then takes one dot product for the root plus
+    one per split, i.e. half the pools the level-wise walk tests below the root
+    (Sec. 5: tests are half the pools)."""
     rng = np.random.default_rng(100 + n)
     for trial in range(6):
         d = 1 + trial % 4
@@ -124,6 +129,8 @@ def test_alg1_binary_splitting_equals_brute_force(n):
             assert ndots <= 2 * n - 1
             lw, tests = exact.levelwise_walk(F, q, rho)
             assert lw == want, (n, trial, rho)
+            if n & (n - 1) == 0:
+                assert ndots == 1 + sum(tests[1:]) // 2, (n, trial, rho, ndots, tests)
 
 
 def test_toy_pool_example():
@@ -145,7 +152,7 @@ def test_toy_pool_example():
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16])
 def test_max_pool_walk_equals_brute_force_and_tests_no_more_than_sums(n):
-    """Sec. 3, Our-Max: a pool is the element-wise maximum of its members; with
+    """Sec. 2, Our-Max: a pool is the element-wise maximum of its members; with
     non-negative vectors q.max >= q.f for every member, so the walk returns
     exactly {i : q.f_i >= rho}.  A max pool never scores above the sum pool of
     the same members, so at every level the max walk keeps a subset of the
@@ -221,7 +228,7 @@ def _signed_brute(F, q, rho):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 16])
 def test_signed_walk_equals_brute_force(n):
-    """Sec. 3, negative descriptors: with max/min pools scored by the maximum
+    """Sec. 2, negative descriptors: with max/min pools scored by the maximum
     where q_k >= 0 and the minimum where q_k < 0, every member's q.f is at most
     its pool's score, so the walk returns exactly {i : q.f_i >= rho} for
     vectors and thresholds of any sign."""

@@ -1,7 +1,7 @@
 """The shifted max/min rows of a signed index never prune a neighbour, under
 the worst rounding the device arithmetic allows (no GPU).
 
-Paper Sec. 3 (negative descriptors): a pool keeps the element-wise maximum and
+Paper Sec. 2 (negative descriptors): a pool keeps the element-wise maximum and
 minimum of its members, and a query scores it with the maximum where q_k >= 0
 and the minimum where q_k < 0; that score U bounds every member's q.f.  The
 index stores R = [max + B | B - min] (B >= every |value|, each entry rounded
