@@ -180,6 +180,28 @@ gt_status gt_exhaustive(gt_index* index, const float* q_dev, int32_t nq, const d
                         int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
                         float* sims_dev, int64_t* total_out, void* stream);
 
+/* gt_query_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, results and errors as gt_query_batch, but every per-call
+ * buffer (query copies, frontiers, counters, candidates, result staging) is
+ * carved out of one fixed device array of 256 MiB that the library holds per
+ * device until the process ends; the call makes no hipMalloc or hipFree.  The
+ * frontier is reserved for its worst case (every pool of the deepest level
+ * for every query tile: 24 * 2^(depth-1) bytes per tile of 64 queries, 32 for
+ * float32 pools), so a call that does not fit, or whose candidates or results
+ * outgrow the rest of the array, fails with GT_ERR_CAPACITY and a message
+ * naming the limit (use fewer queries per call).  Without room for the
+ * subtraction step's score records the bfloat16 walk tests both children
+ * directly (same results).  Every call on a device shares the array, which
+ * keeps the last call's contents (a call clears what must start at zero):
+ * calls that overlap on one device, from several threads or streams, race.
+ * The index's device must be current.  Synchronises `stream` before
+ * returning.  No profiling or count_unique counters. */
+gt_status gt_query_batch_noalloc(gt_index* index, const float* q_dev, int32_t nq,
+                                 const double* rho_host, gt_pool fmt, int64_t max_results,
+                                 int64_t* offsets_dev, int64_t* ids_dev, float* sims_dev,
+                                 int64_t* total_out, void* stream);
+
 /* Device workspace for one query call at a time, so that several calls can
  * be in flight on different streams (continuous batching: a server admits
  * newly arrived requests into a free workspace while others are still on the

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libgt.so")
-SOURCES = ["k_build.hip", "k_walk.hip", "k_exhaustive.hip", "gt_api.cpp"]
+SOURCES = ["k_build.hip", "k_walk.hip", "k_exhaustive.hip", "gt_noalloc.hip", "gt_api.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gt.h"
@@ -271,6 +272,12 @@ gt_status batch_init(Batch* b) {
 gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
   Index* ix = b->ix;
   const size_t dp = (size_t)ix->dp;
+  if (b->fixed) {
+    if (nq_pad > b->nq_alloc || nt > b->nt_alloc ||
+        b->fr_cap != (int64_t(1) << std::max(0, ix->depth - 1)))
+      return fail(GT_ERR_CAPACITY, "the call does not fit the buffers carved for it");
+    return GT_OK;
+  }
   if (nq_pad > b->nq_alloc) {
     free_query_arrays(b);
     const size_t nqa = (size_t)nq_pad;
@@ -305,6 +312,10 @@ gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
 
 gt_status grow_hits(Batch* b, int64_t need) {
   Index* ix = b->ix;
+  if (b->fixed)
+    return fail(GT_ERR_CAPACITY, "the call's " + std::to_string(need) +
+                                     " leaf candidates exceed the fixed scratch (room for " +
+                                     std::to_string(b->hit_cap) + "); use fewer queries per call");
   dfree(ix, &b->hits, (size_t)b->hit_cap);
   dfree(ix, &b->band_idx, (size_t)b->hit_cap);
   b->hit_cap = 0;
@@ -318,6 +329,10 @@ gt_status grow_hits(Batch* b, int64_t need) {
 
 gt_status ensure_out(Batch* b, int64_t need) {
   if (need <= b->out_cap && b->out_id) return GT_OK;
+  if (b->fixed)
+    return fail(GT_ERR_CAPACITY, "the call's " + std::to_string(need) +
+                                     " results exceed the fixed scratch (room for " +
+                                     std::to_string(b->out_cap) + "); use fewer queries per call");
   Index* ix = b->ix;
   const size_t o = (size_t)b->out_cap;
   dfree(ix, &b->out_id, o);
@@ -392,8 +407,8 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   // sparse levels sub_from .. sub_to read only the right children.
   const int ws = ix->walk_subtract < 0 ? 1 : ix->walk_subtract;
   // (sum pools only: a max pool is not its halves' combination)
-  const bool sub = f == GT_POOL_BF16 && !b->maxpool && dl >= 0 && ws > 0 && dl <= D - 2;
-  const int sub_to = !sub ? -1 : (ws == 2 ? D - 3 : D - 2);
+  bool sub = f == GT_POOL_BF16 && !b->maxpool && dl >= 0 && ws > 0 && dl <= D - 2;
+  int sub_to = !sub ? -1 : (ws == 2 ? D - 3 : D - 2);
   // A workspace with a query limit takes its score records and dense masks
   // for its largest call at once: growing them call by call would free and
   // reallocate (gigabytes, for the records), and every free waits for the
@@ -402,6 +417,12 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
                          ? std::max(nt, (b->max_queries + gt::kQueriesPerTile16 - 1) /
                                             gt::kQueriesPerTile16)
                          : nt;
+  if (sub && sub_to >= dl && b->fixed && (int64_t)nt_res * b->fr_cap > b->rec_len) {
+    // no room for score records in the fixed buffers: direct tests (same
+    // results, both children read)
+    sub = false;
+    sub_to = -1;
+  }
   if (sub && sub_to >= dl) {
     const int64_t need = (int64_t)nt_res * b->fr_cap;
     if (need > b->rec_len) {
@@ -415,7 +436,11 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   }
   const bool use_rec = sub && sub_to >= dl;
   if (dl >= 0) {
-    const size_t need = ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt_res;
+    // per-(pool, tile) masks only pass between chained dense steps (an
+    // explicit head more than one level above the last dense level)
+    const size_t need = h + 1 < dl ? ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt_res : 0;
+    if ((int64_t)need > b->dmask_len && b->fixed)
+      return fail(GT_ERR_CAPACITY, "chained dense steps need dense masks the fixed buffers lack");
     if ((int64_t)need > b->dmask_len) {
       dfree(ix, &b->dmask[0], (size_t)b->dmask_len);
       dfree(ix, &b->dmask[1], (size_t)b->dmask_len);
@@ -577,11 +602,13 @@ gt_status enqueue_tail(Index* ix, Batch* b) {
   HIPCHK(gt::launch_scan_offsets(b->qcount, b->nq, b->offs, nullptr, b->ctr, s));
   TRY(ensure_out(b, 1));
   b->spec_direct = b->tgt_ids != nullptr;
-  b->spec_lim = b->spec_direct ? std::min(b->out_cap, b->tgt_max) : b->out_cap;
+  // (a fixed batch has no staging of its own for the sorted results: without
+  // caller buffers nothing is placed)
+  b->spec_lim = b->spec_direct ? std::min(b->out_cap, b->tgt_max) : b->fixed ? 0 : b->out_cap;
   TRY(enqueue_place(b, b->spec_lim, b->spec_direct ? b->tgt_ids : b->fin_id,
                     b->spec_direct ? b->tgt_sims : b->fin_sim));
   HIPCHK(hipMemcpyAsync(b->h_ctr, b->ctr, sizeof(gt::DevCounters), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipEventRecord(b->done, s));
+  if (b->done) HIPCHK(hipEventRecord(b->done, s));
   ev_mark(b, 5);
   return GT_OK;
 }
@@ -619,6 +646,105 @@ gt_status check_query_args(const Index* ix, const float* q, int nq, const double
   if (nq > 0 && (!q || !rho)) return fail(GT_ERR_INVALID_ARG, "NULL query argument");
   for (int i = 0; i < nq; ++i)
     if (isnan(rho[i])) return fail(GT_ERR_INVALID_ARG, "rho is NaN");
+  return GT_OK;
+}
+
+// ------------------------------------------------------ fixed (carved) batches
+void* arena_take(Batch* b, size_t bytes) {
+  const size_t off = (b->arena_used + 255) & ~size_t(255);
+  if (off > b->arena_size || bytes > b->arena_size - off) return nullptr;
+  b->arena_used = off + bytes;
+  return b->arena + off;
+}
+
+// Carves every buffer of one walk call of nq queries in pool format fmt out of
+// [base, base + bytes): counters, query copies, the frontier at its worst case
+// (every pool of the deepest level for every tile, so no level can overflow),
+// dense masks if chained dense steps are configured, score records of the
+// subtraction step if they fit beside at least 2^20 candidates, and the rest
+// split between candidates and result staging.  GT_ERR_CAPACITY if the
+// frontier alone does not fit.
+gt_status carve_fixed(Index* ix, Batch* b, void* base, size_t bytes, int nq, int fmt) {
+  constexpr size_t kPerPair = sizeof(gt::Hit) + 4 + 4 * 4;  // hit, band index, 4 staging words
+  constexpr size_t kMinPairs = size_t(1) << 20;
+  b->ix = ix;
+  b->fixed = true;
+  b->arena = static_cast<unsigned char*>(base);
+  b->arena_size = bytes;
+  b->arena_used = 0;
+  b->max_queries = std::max(nq, 1);
+  const bool maxp = fmt == GT_POOL_MAX_F32 || fmt == GT_POOL_MAX_BF16;
+  const int wf = maxp ? (fmt == GT_POOL_MAX_F32 ? GT_POOL_F32 : GT_POOL_BF16) : fmt;
+  const int tq = tq_of(wf);
+  const int nt = std::max(1, (nq + tq - 1) / tq);
+  const int nq_pad = std::max(128, (nq + 127) / 128 * 128);
+  const size_t dp = (size_t)ix->dp, pw = (size_t)ix->pw, nqa = (size_t)nq_pad;
+  const int64_t fr_cap = int64_t(1) << std::max(0, ix->depth - 1);
+  bool ok = true;
+  auto take = [&](auto*& p, size_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+    p = static_cast<T*>(arena_take(b, std::max<size_t>(count, 1) * sizeof(T)));
+    ok = ok && p != nullptr;
+  };
+  take(b->ctr, 1);
+  take(b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots);
+  take(b->tile_mask, gt::kMaxTiles);
+  take(b->qf, nqa * dp);
+  if (ix->signed_mode) take(b->qw, nqa * pw);
+  take(b->qbf, nqa * pw);
+  take(b->q8, nqa * dp);
+  take(b->qexp, nqa);
+  take(b->invn_q, nqa);
+  take(b->qq, nqa);
+  take(b->rho, nqa);
+  take(b->thr, nqa);
+  take(b->thr_gemm, nqa);
+  take(b->sabs, nqa);
+  take(b->qcount, nqa);
+  take(b->offs, nqa + 1);
+  b->nq_alloc = nq_pad;
+  for (int k = 0; k < 2; ++k) {
+    take(b->fr_node[k], (size_t)nt * fr_cap);
+    take(b->fr_mask[k], (size_t)nt * fr_cap);
+  }
+  b->nt_alloc = nt;
+  b->fr_cap = fr_cap;
+  const int h = head_of(ix);
+  const int dl = dense_last_of(ix, wf, h);
+  if (dl >= 0 && ix->head_level >= 0 && h + 1 < dl) {
+    const size_t need = ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt;
+    take(b->dmask[0], need);
+    take(b->dmask[1], need);
+    b->dmask_len = (int64_t)need;
+  }
+  if (!ok)
+    return fail(GT_ERR_CAPACITY,
+                "a call of " + std::to_string(nq) + " queries on an index of depth " +
+                    std::to_string(ix->depth) + " needs more than the " +
+                    std::to_string(bytes >> 20) + " MiB of fixed scratch for its frontier; " +
+                    "use fewer queries per call");
+  const size_t rec = (size_t)nt * (size_t)fr_cap * 64 * sizeof(uint16_t);
+  const bool want_rec = wf == GT_POOL_BF16 && !maxp && dl >= 0 && ix->walk_subtract != 0;
+  const size_t left0 = bytes - b->arena_used;
+  if (want_rec && left0 > 2 * rec + 2 * 256 + kMinPairs * kPerPair + 8 * 256) {
+    take(b->fr_rec[0], rec / 2);
+    take(b->fr_rec[1], rec / 2);
+    b->rec_len = (int64_t)nt * fr_cap;
+  }
+  const size_t left = bytes - b->arena_used;
+  const size_t pairs = left > 8 * 256 ? (left - 8 * 256) / kPerPair : 0;
+  if (pairs < 1024)
+    return fail(GT_ERR_CAPACITY, "no room for candidates in the fixed scratch beside a call of " +
+                                     std::to_string(nq) + " queries; use fewer queries per call");
+  take(b->hits, pairs);
+  take(b->band_idx, pairs);
+  take(b->out_id, pairs);
+  take(b->out_sim, pairs);
+  take(b->tmp_id, pairs);
+  take(b->tmp_sim, pairs);
+  if (!ok) return fail(GT_ERR_CAPACITY, "fixed scratch carve failed");
+  b->hit_cap = (int64_t)pairs;
+  b->out_cap = (int64_t)pairs;
   return GT_OK;
 }
 
@@ -671,7 +797,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   // automatic head only the last dense level is tested.
   if (b->dense_last >= 0 && ix->head_level < 0) b->head = b->dense_last - 1;
   b->nb = bucket_bits_of(b->dense_last >= 0 ? b->dense_last : b->head, nt);
-  b->profile = ix->profile;
+  b->profile = ix->profile && !b->fixed;
   b->nw = 0;
   if (b->profile && !b->events) {
     for (auto& e : b->ev) HIPCHK(hipEventCreate(&e));
@@ -683,7 +809,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   TRY(zero_dev(b->qcount, (size_t)nq_pad * 4, s));
   TRY(zero_dev(b->tile_mask, (size_t)gt::kMaxTiles * 8, s));
   if (kind == 1) TRY(zero_dev(b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots * 4, s));
-  b->counted = ix->count_unique && kind == 1;
+  b->counted = ix->count_unique && kind == 1 && !b->fixed;
   if (b->counted) {
     const int64_t words = (int64_t(2) << ix->depth) / 32 + 1;
     if (!b->bitmap) {
@@ -693,8 +819,12 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
     TRY(zero_dev(b->bitmap, (size_t)words * 4, s));
   }
   if (nq > 0) {
-    memcpy(b->h_rho, rho, (size_t)nq * 8);
-    HIPCHK(hipMemcpyAsync(b->rho, b->h_rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    if (b->h_rho) {
+      memcpy(b->h_rho, rho, (size_t)nq * 8);
+      HIPCHK(hipMemcpyAsync(b->rho, b->h_rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    } else {
+      HIPCHK(hipMemcpyAsync(b->rho, rho, (size_t)nq * 8, hipMemcpyHostToDevice, s));
+    }
     // reduced query copies only for the call's pool format; the absolute
     // terms of the subtraction step only for bfloat16 sum pools
     const bool w16 = kind == 1 && fmt == GT_POOL_BF16, w8 = kind == 1 && fmt == GT_POOL_FP8E4M3;
@@ -746,7 +876,10 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
   hipStream_t s = b->stream;
   *total_out = 0;
   for (int attempt = 0;; ++attempt) {
-    HIPCHK(hipEventSynchronize(b->done));
+    if (b->done)
+      HIPCHK(hipEventSynchronize(b->done));
+    else
+      HIPCHK(hipStreamSynchronize(s));
     const gt::DevCounters& c = *b->h_ctr;
     if (c.err)
       return fail(GT_ERR_INVALID_INPUT, ix->signed_mode
@@ -867,6 +1000,9 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   } while (0)
 
   BHIP(hipGetDevice(&ix->device));
+  // the device scratch of gt_query_batch_noalloc, once per device
+  ix->scratch_err = gt::scratch_setup(ix->device);
+  if (ix->scratch_err != hipSuccess) (void)hipGetLastError();
   hipDeviceProp_t prop;
   BHIP(hipGetDeviceProperties(&prop, ix->device));
   ix->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -1102,6 +1238,38 @@ gt_status gt_exhaustive(gt_index* ix, const float* q_dev, int32_t nq, const doub
   set_targets(ix->def, max_results, ids_dev, sims_dev);
   TRY(submit(ix, ix->def, 2, q_dev, nq, rho_host, 0, (hipStream_t)stream));
   return finish(ix, ix->def, max_results, offsets_dev, ids_dev, sims_dev, total_out, false);
+}
+
+gt_status gt_query_batch_noalloc(gt_index* ix, const float* q_dev, int32_t nq,
+                                 const double* rho_host, gt_pool fmt, int64_t max_results,
+                                 int64_t* offsets_dev, int64_t* ids_dev, float* sims_dev,
+                                 int64_t* total_out, void* stream) {
+  g_err.clear();
+  if (!ix) return fail(GT_ERR_INVALID_ARG, "index is NULL");
+  if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
+  if (!offsets_dev) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
+  if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
+  if (max_results > 0 && (!ids_dev || !sims_dev)) return fail(GT_ERR_INVALID_ARG, "NULL output buffer");
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != ix->device) return fail(GT_ERR_INVALID_ARG, "the index's device must be current");
+  void* base = gt::scratch_of(ix->device);
+  if (!base)
+    return fail(GT_ERR_DEVICE, std::string("device scratch was not set up: ") +
+                                   hipGetErrorString(ix->scratch_err));
+  if (nq < 0) return fail(GT_ERR_INVALID_ARG, "nq < 0");
+  // buffers carved from the device's scratch; the host copy of the counters
+  // lives on this stack frame (pageable)
+  Batch fb;
+  gt::DevCounters host_ctr;
+  TRY(carve_fixed(ix, &fb, base, gt::kScratchBytes, nq, (int)fmt));
+  fb.h_ctr = &host_ctr;
+  set_targets(&fb, max_results, ids_dev, sims_dev);
+  TRY(submit(ix, &fb, 1, q_dev, nq, rho_host, (int)fmt, (hipStream_t)stream));
+  const gt_status st = finish(ix, &fb, max_results, offsets_dev, ids_dev, sims_dev, total_out, false);
+  // the copies out of the scratch are done before the next call may reuse it
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return st;
 }
 
 gt_status gt_batch_create(gt_index* ix, int32_t max_queries, gt_batch** out) {

@@ -32,6 +32,11 @@ constexpr int kMaxBucketsPerXcd = (1 << kMaxBucketBits) / kXcds;
 // Largest padded dimension each walk format supports (query tile in LDS).
 constexpr int kMaxDpBf16 = 1152, kMaxDpFp8 = 2304, kMaxDpF32 = 1152;
 
+// Device scratch of the allocation-free query entry point (one array per
+// device, in gt_noalloc.hip).
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+
 enum : uint32_t { HIT_ACCEPT = 1u, HIT_BAND = 2u, HIT_REJECT = 3u };
 
 // One candidate (query, vector) pair.  flag: kind in bits 0-1 (HIT_*); an
@@ -145,6 +150,13 @@ struct Index;
 struct Batch {
   Index* ix = nullptr;
   int max_queries = 0;       // 0: grows on demand (the index's own workspace)
+  // Carved out of a caller's fixed device buffer (the scratch of the
+  // allocation-free entry point): nothing is ever allocated or freed; a call
+  // that would need more than the carve holds fails with GT_ERR_CAPACITY.
+  // No events (the host waits on the stream) and no pinned staging.
+  bool fixed = false;
+  unsigned char* arena = nullptr;  // the fixed buffer and how much of it is used
+  size_t arena_size = 0, arena_used = 0;
   int nt_alloc = 0;
   int nq_alloc = 0;
   uint32_t* fr_node[2] = {nullptr, nullptr};
@@ -264,6 +276,7 @@ struct Index {
   unsigned int* d_flags = nullptr;  // float8 overflow flags per level; last: input error
 
   Batch* def = nullptr;      // workspace of gt_query_batch / gt_exhaustive
+  hipError_t scratch_err = hipSuccess;  // set-up of the device scratch at build
 };
 
 // ---- launch wrappers (kernels in k_build.hip, k_walk.hip, k_exhaustive.hip) ----
@@ -314,6 +327,11 @@ hipError_t launch_pair_check(const uint2* cand, const unsigned long long* ncand,
                              const float* invn_q, const float* invn_f, const double* rho, int dp,
                              Hit* hits, unsigned long long hit_cap, uint32_t* band_idx,
                              unsigned int* qcount, DevCounters* ctr, int grid, hipStream_t s);
+// Scratch of the allocation-free entry point (gt_noalloc.hip): taken once per
+// device at set-up (index build), with that device current.
+hipError_t scratch_setup(int device);
+void* scratch_of(int device);  // NULL until scratch_setup succeeded on the device
+
 hipError_t launch_insert_paths(float* master, const float* leaves, int depth, int dp, int64_t lo,
                                int64_t hi, uint16_t* pbf16, uint8_t* pfp8, const int* lexp,
                                unsigned int* flags, hipStream_t s);

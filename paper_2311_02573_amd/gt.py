@@ -27,7 +27,8 @@ POOLS = {"f32": POOL_F32, "bf16": POOL_BF16, "fp8": POOL_FP8,
          "max_f32": POOL_MAX_F32, "max_bf16": POOL_MAX_BF16, "signed": POOL_SIGNED}
 GT_MAX_LEVELS = 40
 
-EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_exhaustive", "gt_batch_create",
+EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_query_batch_noalloc",
+           "gt_exhaustive", "gt_batch_create",
            "gt_batch_submit", "gt_batch_poll", "gt_batch_finish", "gt_batch_destroy",
            "gt_get_stats", "gt_read_pools", "gt_set_option", "gt_destroy", "gt_last_error"]
 
@@ -75,6 +76,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gt_query_batch.restype = st
     lib.gt_query_batch.argtypes = [vp, vp, i32, vp, ctypes.c_int, i64, vp, vp, vp,
                                    ctypes.POINTER(i64), vp]
+    lib.gt_query_batch_noalloc.restype = st
+    lib.gt_query_batch_noalloc.argtypes = [vp, vp, i32, vp, ctypes.c_int, i64, vp, vp, vp,
+                                           ctypes.POINTER(i64), vp]
     lib.gt_exhaustive.restype = st
     lib.gt_exhaustive.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp]
     lib.gt_batch_create.restype = st
@@ -211,6 +215,14 @@ class GTIndex:
     def query(self, q: torch.Tensor, rho, pool: str = "bf16", max_results=None, stream=None):
         """Level-wise group-testing walk.  rho: float or per-query sequence."""
         return self._run(lambda h, qp, nq, r, fmt, *rest: lib().gt_query_batch(h, qp, nq, r, fmt, *rest),
+                         q, rho, max_results, stream, POOLS[pool])
+
+    def query_noalloc(self, q: torch.Tensor, rho, pool: str = "bf16", max_results=None,
+                      stream=None):
+        """The walk run in the library's fixed device scratch (no allocation by
+        the library; the output tensors are allocated here, by the caller)."""
+        return self._run(lambda h, qp, nq, r, fmt, *rest:
+                         lib().gt_query_batch_noalloc(h, qp, nq, r, fmt, *rest),
                          q, rho, max_results, stream, POOLS[pool])
 
     def exhaustive(self, q: torch.Tensor, rho, max_results=None, stream=None):
