@@ -28,9 +28,13 @@ HBM_PEAK_GBS = 8000.0
 
 
 # Counter-measured HBM traffic per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE,
-# scaled by a 1 GiB copy), kept in a profile summary together with a hash of
-# the kernel sources it was taken on; reported only while the sources match.
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_walk_bf16_n1m_d1000_b1024_rho0.9.md")
+# scaled by a 1 GiB copy), kept in a profile summary per pool format and batch
+# size together with a hash of the kernel sources it was taken on; reported
+# only while the sources match.
+def counter_summary(pool, nq):
+    return os.path.join(ROOT, "profiles", f"counters_walk_{pool}_n1m_d1000_b{nq}_rho0.9.md")
+
+
 KERNEL_SOURCES = ["k_walk.hip", "gt_numerics.h", "gt_device.h", "gt_internal.h", "gt_api.cpp"]
 
 
@@ -44,11 +48,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic():
-    """{kernel: bytes per launch} from the counter summary, or {} if it is
-    missing or was taken on other kernel sources."""
+def stored_traffic(pool, nq):
+    """{kernel: bytes per launch} from the counter summary of this pool format
+    and batch size, or {} if it is missing or was taken on other kernel
+    sources."""
     try:
-        text = open(COUNTER_SUMMARY).read()
+        text = open(counter_summary(pool, nq)).read()
     except OSError:
         return {}
     vals, src = {}, None
@@ -68,6 +73,110 @@ def log(msg):
 
 def pct(a, p):
     return float(np.percentile(np.asarray(a), p))
+
+
+def measure_roofline(idx, q, rho, pool, nq, walk_subtract, d, side_steps):
+    """Per-kernel-group device time (HIP events on the call's stream, median
+    over profiled calls) and algorithmic bytes (each distinct row a kernel
+    must read, once: pool rows at d_pad x element size, leaf rows at d x 4,
+    plus the subtraction step's 128-byte score records), and the roofline of
+    the group with the largest share of the call.  Returns (roofline dict,
+    stats of the counting call, first sparse level)."""
+    idx.set_option("profile", 1)
+    prof = []
+    for _ in range(max(3, side_steps)):
+        idx.query(q, rho, pool=pool)
+        prof.append(idx.stats())
+    idx.set_option("profile", 0)
+    med = lambda k: float(np.median([p[k] for p in prof]))
+    ms_dense, ms_sparse, ms_leaf = med("ms_dense"), med("ms_frontier"), med("ms_leaf")
+    n_dense, n_sparse = prof[-1]["dense_launches"], prof[-1]["frontier_launches"]
+
+    idx.set_option("count_unique", 1)
+    idx.query(q, rho, pool=pool)
+    su = idx.stats()
+    idx.set_option("count_unique", 0)
+    esz = {"bf16": 2, "fp8": 1, "f32": 4}[pool]
+    dp = su["d_pad"]
+    h, D = su["head_level"], su["depth"]
+    first_sparse = h + n_dense          # dense steps test levels h+1 .. h+n_dense
+    uniq = su["unique_rows"]
+    dense_bytes = sum(uniq[l] for l in range(h + 1, first_sparse + 1)) * dp * esz
+    sparse_bytes = sum(uniq[l] for l in range(first_sparse + 1, D)) * dp * esz
+    leaf_bytes = uniq[D] * d * 4
+    entries = list(su["entries"])
+    # subtraction step (bf16 after a dense step): sparse levels first_sparse ..
+    # sub_to read one child row per entry plus the entry's 128-byte score
+    # record, and write records for outputs that a subtraction step reads next
+    ws = 1 if walk_subtract == -1 else walk_subtract
+    sub_to = -1
+    if pool == "bf16" and n_dense > 0 and ws > 0 and first_sparse <= D - 2:
+        sub_to = D - 2 if ws == 1 else D - 3
+    sub_levels = [l for l in range(first_sparse, D - 1) if l <= sub_to]
+    rec_bytes = 128 * (sum(entries[l] for l in sub_levels)
+                       + sum(entries[l + 1] for l in sub_levels if l + 1 <= sub_to))
+    dense_rec_bytes = 128 * entries[first_sparse] if sub_levels else 0
+    dense_bytes += dense_rec_bytes
+    sparse_bytes += rec_bytes
+    raw_sparse = sum(entries[l] * (1 if l in sub_levels else 2)
+                     for l in range(first_sparse, D - 1)) * dp * esz
+    if n_dense == 0:
+        raw_sparse += ((1 << h) * su["last_tiles"] - entries[h]) * 2 * dp * esz
+    raw_leaf = entries[D - 1] * 2 * dp * 4
+    n_sub = len(sub_levels)
+    walk_name = (f"k_walk_level<{pool}>" if n_sub == 0 else
+                 "k_walk_sub<bf16>" if n_sub == n_sparse else "k_walk_sub+k_walk_level<bf16>")
+    groups = {
+        f"k_dense_level<{pool}>": (dense_bytes, ms_dense, n_dense),
+        walk_name: (sparse_bytes, ms_sparse, n_sparse),
+        "k_leaf": (leaf_bytes, ms_leaf, 1),
+    }
+    gbps = lambda b, ms: round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
+    dom = max(groups, key=lambda k: groups[k][1])
+    b, ms, nl = groups[dom]
+    achieved = gbps(b, ms)
+    roofline = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": stored_traffic(pool, nq).get(dom),
+        "algorithmic_bytes_per_launch": b / max(1, nl),
+        "launches_per_batch": nl,
+        "avg_launch_ms": ms / max(1, nl),
+        "kernels": {k: {"bytes": v[0], "ms": round(v[1], 4), "launches": v[2], "GBps": gbps(v[0], v[1])}
+                    for k, v in groups.items()},
+        # per-stage device time of one call (HIP events, median over the profiled calls)
+        "stage_ms": {k[3:]: round(med(k), 4) for k in ("ms_prep", "ms_dense", "ms_frontier", "ms_leaf",
+                                                      "ms_recheck", "ms_compact", "ms_total")},
+        "walk_all_levels": {"bytes": dense_bytes + sparse_bytes, "ms": round(ms_dense + ms_sparse, 4),
+                            "GBps": gbps(dense_bytes + sparse_bytes, ms_dense + ms_sparse)},
+        "sparse_raw_bytes": raw_sparse,
+        "score_record_bytes": {"dense_writes": dense_rec_bytes, "walk_reads_writes": rec_bytes},
+        "leaf_raw_bytes": raw_leaf,
+        "entries_per_level": {l: entries[l] for l in range(h + 1, D)},
+        "tests_per_level": {l: su["pairs"][l] for l in range(h + 1, D)},
+        "leaf_pairs": su["leaf_pairs"], "leaf_candidates": su["candidates"],
+        "rechecked": su["rechecked"], "results": su["results"],
+        "unique_rows_per_level": {l: uniq[l] for l in range(h + 1, D + 1)},
+    }
+    return roofline, su, first_sparse
+
+
+def cpu_info():
+    """CPU model (from /proc/cpuinfo) and the cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return model, nproc
 
 
 def main():
@@ -103,6 +212,11 @@ def main():
                     help="also time the walk with each subtraction setting")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of each loaded serving run (0: no serving leg)")
+    ap.add_argument("--nq-variant", type=int, default=4096,
+                    help="batch size of the bfloat16 / float8 precision variant (0: skip it)")
+    ap.add_argument("--leg", default="all", choices=["all", "exh"],
+                    help="exh: only the exhaustive GEMM path on the headline batch, for "
+                         "counter profiles of its kernel")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU (the library has no multi-GPU path); use --gpus 1",
@@ -119,10 +233,13 @@ def main():
     dev = torch.device("cuda:0")
 
     t0 = time.time()
-    w = synth.workload1(nq=args.nq, rho=args.rho, n=args.n, d=args.d)
-    log(f"generated N={w.n} d={w.d} nq={args.nq} in {time.time() - t0:.1f}s")
+    # one database for the 1024- and the 4096-query batches (neighbours are
+    # planted for 4096 queries either way); the headline takes the first nq
+    w = synth.workload1(nq=max(args.nq, args.nq_variant), rho=args.rho, n=args.n, d=args.d)
+    log(f"generated N={w.n} d={w.d} nq={len(w.queries)} in {time.time() - t0:.1f}s")
     feats = torch.from_numpy(w.feats).to(dev)
-    q = torch.from_numpy(w.queries).to(dev)
+    q_all = torch.from_numpy(w.queries).to(dev)
+    q = q_all[:args.nq]
     torch.cuda.synchronize()
 
     t0 = time.time()
@@ -138,9 +255,11 @@ def main():
         idx.set_option("dense_last", args.dense_last)
     idx.set_option("walk_subtract", args.walk_subtract)
 
-    def run(pool, steps, warmup):
-        fn = (lambda: idx.exhaustive(q, args.rho)) if pool == "exh" else \
-            (lambda: idx.query(q, args.rho, pool=pool))
+    def run(pool, steps, warmup, qq=None, rho=None):
+        qq = q if qq is None else qq
+        rho = args.rho if rho is None else rho
+        fn = (lambda: idx.exhaustive(qq, rho)) if pool == "exh" else \
+            (lambda: idx.query(qq, rho, pool=pool))
         res = None
         for _ in range(warmup):
             res = fn()
@@ -156,20 +275,23 @@ def main():
         wall = time.perf_counter() - t_start
         return res, wall, lat
 
-    def run_pipelined(pool, steps, warmup, streams=1):
+    def run_pipelined(pool, steps, warmup, streams=1, qq=None, rho=None):
         # W = max(2, streams) workspaces: batch k is enqueued before the host
         # waits for batch k - W + 1, so the host's per-call work overlaps the
         # device's.  On one stream the device runs the batches back to back,
         # in order; with a stream per workspace a batch's first kernels may
         # also run while the previous batches' last ones finish.
+        qq = q if qq is None else qq
+        rho = args.rho if rho is None else rho
         W = max(2, streams)
-        ws = [gt.Workspace(idx, args.nq, stream=torch.cuda.current_stream() if streams == 1 else None)
+        ws = [gt.Workspace(idx, qq.shape[0],
+                           stream=torch.cuda.current_stream() if streams == 1 else None)
               for _ in range(W)]
 
         def go(n):
             r = None
             for k in range(n):
-                ws[k % W].submit(q, args.rho, pool=pool)
+                ws[k % W].submit(qq, rho, pool=pool)
                 if k >= W - 1:
                     r = ws[(k - W + 1) % W].finish()
             for k in range(max(0, n - W + 1), n):
@@ -186,6 +308,21 @@ def main():
             w_.close()
         return r, wall
 
+    if args.leg == "exh":
+        # the exhaustive path alone (counter profiles of k_gemm_threshold)
+        for _ in range(args.warmup):
+            idx.exhaustive(q, args.rho)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            r = idx.exhaustive(q, args.rho)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) / args.steps * 1e3
+        print(json.dumps({"leg": "exh", "ms_per_call": round(ms, 3), "results": r.total,
+                          "queries_per_s": round(args.nq / ms * 1e3, 1)}), flush=True)
+        idx.close()
+        return
+
     # ---- headline: the walk on the chosen pool format, batches back to back
     res_p, wall = run_pipelined(args.pool, args.steps, args.warmup, args.streams)
     ms_step = wall / args.steps * 1e3
@@ -201,88 +338,10 @@ def main():
     if not same_p:
         log("WARNING: pipelined and one-at-a-time results differ")
 
-    # ---- kernel timing with HIP events on the call's stream (profiling on)
-    idx.set_option("profile", 1)
-    prof = []
-    for _ in range(max(3, args.side_steps)):
-        idx.query(q, args.rho, pool=args.pool)
-        prof.append(idx.stats())
-    idx.set_option("profile", 0)
-    med = lambda k: float(np.median([p[k] for p in prof]))
-    ms_dense, ms_sparse, ms_leaf = med("ms_dense"), med("ms_frontier"), med("ms_leaf")
-    n_dense, n_sparse = prof[-1]["dense_launches"], prof[-1]["frontier_launches"]
-
-    # ---- algorithmic bytes: each distinct row a kernel must read, once
-    idx.set_option("count_unique", 1)
-    idx.query(q, args.rho, pool=args.pool)
-    su = idx.stats()
-    idx.set_option("count_unique", 0)
-    esz = {"bf16": 2, "fp8": 1, "f32": 4}[args.pool]
-    dp = su["d_pad"]
-    h, D = su["head_level"], su["depth"]
-    first_sparse = h + n_dense          # dense steps test levels h+1 .. h+n_dense
-    uniq = su["unique_rows"]
-    dense_bytes = sum(uniq[l] for l in range(h + 1, first_sparse + 1)) * dp * esz
-    sparse_bytes = sum(uniq[l] for l in range(first_sparse + 1, D)) * dp * esz
-    leaf_bytes = uniq[D] * dp * 4
-    entries = list(su["entries"])
-    # subtraction step (bf16 after a dense step): sparse levels first_sparse ..
-    # sub_to read one child row per entry plus the entry's 128-byte score
-    # record, and write records for outputs that a subtraction step reads next
-    ws = 1 if args.walk_subtract == -1 else args.walk_subtract
-    sub_to = -1
-    if args.pool == "bf16" and n_dense > 0 and ws > 0 and first_sparse <= D - 2:
-        sub_to = D - 2 if ws == 1 else D - 3
-    sub_levels = [l for l in range(first_sparse, D - 1) if l <= sub_to]
-    rec_bytes = 128 * (sum(entries[l] for l in sub_levels)
-                       + sum(entries[l + 1] for l in sub_levels if l + 1 <= sub_to))
-    dense_rec_bytes = 128 * entries[first_sparse] if sub_levels else 0
-    dense_bytes += dense_rec_bytes
-    sparse_bytes += rec_bytes
-    raw_sparse = sum(entries[l] * (1 if l in sub_levels else 2)
-                     for l in range(first_sparse, D - 1)) * dp * esz
-    if n_dense == 0:
-        raw_sparse += ((1 << h) * su["last_tiles"] - entries[h]) * 2 * dp * esz
-    raw_leaf = entries[D - 1] * 2 * dp * 4
-    n_sub = len(sub_levels)
-    walk_name = (f"k_walk_level<{args.pool}>" if n_sub == 0 else
-                 "k_walk_sub<bf16>" if n_sub == n_sparse else "k_walk_sub+k_walk_level<bf16>")
-    groups = {
-        f"k_dense_level<{args.pool}>": (dense_bytes, ms_dense, n_dense),
-        walk_name: (sparse_bytes, ms_sparse, n_sparse),
-        "k_leaf": (leaf_bytes, ms_leaf, 1),
-    }
-    gbps = lambda b, ms: round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None
-    dom = max(groups, key=lambda k: groups[k][1])
-    b, ms, nl = groups[dom]
-    achieved = gbps(b, ms)
-    roofline = {
-        "kernel": dom,
-        "bound": "hbm",
-        "achieved": achieved,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": stored_traffic().get(dom),
-        "algorithmic_bytes_per_launch": b / max(1, nl),
-        "launches_per_batch": nl,
-        "avg_launch_ms": ms / max(1, nl),
-        "kernels": {k: {"bytes": v[0], "ms": round(v[1], 4), "launches": v[2], "GBps": gbps(v[0], v[1])}
-                    for k, v in groups.items()},
-        # per-stage device time of one call (HIP events, median over the profiled calls)
-        "stage_ms": {k[3:]: round(med(k), 4) for k in ("ms_prep", "ms_dense", "ms_frontier", "ms_leaf",
-                                                      "ms_recheck", "ms_compact", "ms_total")},
-        "walk_all_levels": {"bytes": dense_bytes + sparse_bytes, "ms": round(ms_dense + ms_sparse, 4),
-                            "GBps": gbps(dense_bytes + sparse_bytes, ms_dense + ms_sparse)},
-        "sparse_raw_bytes": raw_sparse,
-        "score_record_bytes": {"dense_writes": dense_rec_bytes, "walk_reads_writes": rec_bytes},
-        "leaf_raw_bytes": raw_leaf,
-        "entries_per_level": {l: entries[l] for l in range(h + 1, D)},
-        "tests_per_level": {l: su["pairs"][l] for l in range(h + 1, D)},
-        "leaf_pairs": su["leaf_pairs"], "leaf_candidates": su["candidates"],
-        "rechecked": su["rechecked"], "results": su["results"],
-        "unique_rows_per_level": {l: uniq[l] for l in range(h + 1, D + 1)},
-    }
+    # ---- kernel timing (HIP events) and algorithmic bytes (distinct rows)
+    roofline, su, first_sparse = measure_roofline(idx, q, args.rho, args.pool, args.nq,
+                                                  args.walk_subtract, w.d, args.side_steps)
+    D = su["depth"]
 
     # ---- the TNE cost model (paper Sec. 5, Eq. 3) against the walk: lambda
     # fitted to a sample of this workload's similarities, predicted pools per
@@ -312,6 +371,45 @@ def main():
         "per query predicted/predicted/measured " +
         ", ".join(f"L{l} {v['moment']}/{v['loghist']}/{v['measured']}"
                   for l, v in cost_model["survivors_per_query"].items()))
+
+    # ---- the same batch at the other thresholds: walk vs exhaustive GEMM
+    rho_sweep = {}
+    if not args.no_side:
+        for r in (0.8, 0.95):
+            rr, wr = run_pipelined(args.pool, args.steps, 2, args.streams, rho=r)
+            ex, we, _ = run("exh", 2, 1, rho=r)
+            same = rr.total == ex.total and all(
+                np.array_equal(a[0], b[0]) for a, b in zip(rr.to_lists(), ex.to_lists()))
+            rho_sweep[r] = {"queries_per_s": round(args.nq * args.steps / wr, 1),
+                            "ms_per_batch": round(wr / args.steps * 1e3, 4),
+                            "results": rr.total, "exhaustive_queries_per_s": round(args.nq * 2 / we, 1),
+                            "ids_identical_to_exhaustive": bool(same)}
+            log(f"rho={r}: {rho_sweep[r]}")
+
+    # ---- precision variant: batches of nq_variant queries, bfloat16 and
+    # float8 pools (same database), each with the roofline of its dominant kernel
+    variant = None
+    if args.nq_variant > 0 and not args.no_side:
+        nqv = args.nq_variant
+        qv = q_all[:nqv]
+        variant = {"workload": f"softmax(z/0.2) unit features N={w.n} d={w.d} float32, "
+                               f"{nqv} queries per batch with planted neighbours, rho={args.rho}",
+                   "global_batch": nqv}
+        ref_lists = None
+        for pool in ("bf16", "fp8"):
+            steps_v = max(5, args.steps // 2)
+            rv, wv = run_pipelined(pool, steps_v, 2, args.streams, qq=qv)
+            rl, _, _ = measure_roofline(idx, qv, args.rho, pool, nqv, args.walk_subtract, w.d, 3)
+            lists = rv.to_lists()
+            same = ref_lists is None or all(np.array_equal(a[0], b[0]) for a, b in zip(lists, ref_lists))
+            ref_lists = ref_lists or lists
+            variant[pool] = {"queries_per_s": round(nqv * steps_v / wv, 1),
+                             "ms_per_batch": round(wv / steps_v * 1e3, 4), "results": rv.total,
+                             "ids_identical_to_bf16": bool(same), "roofline": rl}
+            log(f"{nqv}-query batches, {pool} pools: {variant[pool]['ms_per_batch']} ms/batch, "
+                f"{variant[pool]['queries_per_s']:.0f} queries/s, roofline {rl['kernel']} "
+                f"{rl['frac']}")
+        del ref_lists
 
     sweep = None
     if args.sweep_dense:
@@ -375,8 +473,12 @@ def main():
         se = idx.stats()
         idx.set_option("profile", 0)
         comparators["exhaustive_gemm_ms"] = se["ms_gemm"]
-        flops = 2.0 * args.nq * w.n * dp
+        # algorithmic flops 2 B N d; the GEMM itself runs over d_pad columns
+        flops = 2.0 * args.nq * w.n * w.d
         comparators["exhaustive_gemm_tflops"] = round(flops / (se["ms_gemm"] * 1e-3) / 1e12, 1) \
+            if se["ms_gemm"] > 0 else None
+        comparators["exhaustive_gemm_tflops_over_d_pad"] = round(
+            2.0 * args.nq * w.n * su["d_pad"] / (se["ms_gemm"] * 1e-3) / 1e12, 1) \
             if se["ms_gemm"] > 0 else None
     walk_lists = res.to_lists()
     recall = None
@@ -425,6 +527,10 @@ def main():
         "cpu_baseline": cpu,
     }
     out["cost_model"] = cost_model
+    if rho_sweep:
+        out["rho_sweep"] = rho_sweep
+    if variant is not None:
+        out["precision_variant"] = variant
     if sweep is not None:
         out["dense_last_sweep_ms"] = sweep
     if sub_sweep is not None:
@@ -453,13 +559,14 @@ def cpu_baseline(w, ns, nq, rho, walk_lists):
     import oracle.brute as ob
 
     threads = ob.default_threads()
+    model, nproc = cpu_info()
     t1 = time.perf_counter()
     ora = ob.range_search(w.feats, w.queries[:ns], rho, nthreads=threads)
     cpu_s = time.perf_counter() - t1
     match = all(np.array_equal(walk_lists[b][0], ora[b][0]) for b in range(ns))
     log(f"oracle: {ns} queries in {cpu_s:.1f}s on {threads} threads, match={match}")
     return {"value": round(ns / cpu_s, 3), "unit": "queries/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "nproc": nproc,
             "sample": f"first {ns} of the {nq} queries against the full database "
                       f"(N={w.n}, d={w.d}); canonical float64 scan, {cpu_s:.1f} s",
             "ids_match_gpu": bool(match)}
