@@ -73,9 +73,9 @@ typedef enum { GT_F32 = 0, GT_F16 = 1, GT_BF16 = 2 } gt_dtype; /* feature storag
  * smallest power of two >= the largest |value| at build (1 for an all-zero
  * build), the additions rounded up.  A query q is walked as [max(q,0) |
  * max(-q,0)] against the threshold tau + B |q|_1: the same test as the
- * max/min score against tau, with every operand non-negative.  Limits: d <=
- * 512; every rho > 0 (also for gt_exhaustive on such an index); inserted
- * values must lie in [-B, B]. */
+ * max/min score against tau, with every operand non-negative.  Limits: every
+ * rho > 0 (also for gt_exhaustive on such an index); inserted values must lie
+ * in [-B, B]. */
 typedef enum {
   GT_POOL_F32 = 1,
   GT_POOL_BF16 = 2,
@@ -131,7 +131,7 @@ typedef struct {
  * Copies the features; the index owns all its device memory until
  * gt_destroy.  Synchronises `stream` (validation result).  Errors:
  * INVALID_ARG (d < 1 or d > 4096, n < 0, n > capacity, capacity not a power of
- * two, dtype; with GT_POOL_SIGNED: d > 512 or a sum format asked for),
+ * two, dtype; with GT_POOL_SIGNED: a sum format asked for),
  * INVALID_INPUT, OUT_OF_MEMORY, DEVICE. */
 gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dtype,
                         int64_t capacity, uint32_t pool_formats, void* stream,
@@ -166,8 +166,10 @@ gt_status gt_insert(gt_index* index, const void* feats_dev, int64_t n_new, void*
  * matches.  Synchronises `stream` once (result count).  On
  * GT_ERR_RESULT_OVERFLOW, *total_out holds the required max_results and
  * offsets_dev is valid; ids/sims are not written.  Other errors:
- * INVALID_ARG (format not built, d too large for the format), INVALID_INPUT
- * (a NaN/Inf/negative query value), OUT_OF_MEMORY, DEVICE. */
+ * INVALID_ARG (format not built), INVALID_INPUT (a NaN/Inf/negative query
+ * value), OUT_OF_MEMORY, DEVICE.  Every d <= 4096 and every pool format is
+ * served; rows of more than 1152 padded columns (2304 for float8) stream the
+ * queries through on-chip memory in windows and take no subtraction step. */
 gt_status gt_query_batch(gt_index* index, const float* q_dev, int32_t nq, const double* rho_host,
                          gt_pool fmt, int64_t max_results, int64_t* offsets_dev, int64_t* ids_dev,
                          float* sims_dev, int64_t* total_out, void* stream);

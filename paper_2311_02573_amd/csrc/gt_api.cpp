@@ -137,10 +137,6 @@ int bucket_bits_of(int sparse_from, int nt) {
 
 int tq_of(int fmt) { return fmt == GT_POOL_F32 ? gt::kQueriesPerTileF32 : gt::kQueriesPerTile16; }
 
-int maxdp_of(int fmt) {
-  return fmt == GT_POOL_F32 ? gt::kMaxDpF32 : fmt == GT_POOL_BF16 ? gt::kMaxDpBf16 : gt::kMaxDpFp8;
-}
-
 gt_status zero_dev(void* p, size_t bytes, hipStream_t s) {
   HIPCHK(gt::launch_zero_u32(static_cast<uint32_t*>(p), (int64_t)(bytes / 4), s));
   return GT_OK;
@@ -407,7 +403,9 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
   // sparse levels sub_from .. sub_to read only the right children.
   const int ws = ix->walk_subtract < 0 ? 1 : ix->walk_subtract;
   // (sum pools only: a max pool is not its halves' combination)
-  bool sub = f == GT_POOL_BF16 && !b->maxpool && dl >= 0 && ws > 0 && dl <= D - 2;
+  // (and rows whose whole query tile fits in LDS)
+  bool sub = f == GT_POOL_BF16 && !b->maxpool && dl >= 0 && ws > 0 && dl <= D - 2 &&
+             (int)dp <= gt::kMaxDpBf16;
   int sub_to = !sub ? -1 : (ws == 2 ? D - 3 : D - 2);
   // A workspace with a query limit takes its score records and dense masks
   // for its largest call at once: growing them call by call would free and
@@ -724,7 +722,8 @@ gt_status carve_fixed(Index* ix, Batch* b, void* base, size_t bytes, int nq, int
                     std::to_string(bytes >> 20) + " MiB of fixed scratch for its frontier; " +
                     "use fewer queries per call");
   const size_t rec = (size_t)nt * (size_t)fr_cap * 64 * sizeof(uint16_t);
-  const bool want_rec = wf == GT_POOL_BF16 && !maxp && dl >= 0 && ix->walk_subtract != 0;
+  const bool want_rec = wf == GT_POOL_BF16 && !maxp && dl >= 0 && ix->walk_subtract != 0 &&
+                        ix->dp <= gt::kMaxDpBf16;
   const size_t left0 = bytes - b->arena_used;
   if (want_rec && left0 > 2 * rec + 2 * 256 + kMinPairs * kPerPair + 8 * 256) {
     take(b->fr_rec[0], rec / 2);
@@ -762,9 +761,9 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
       return fail(GT_ERR_INVALID_ARG, "unknown pool format");
     if (!(ix->formats & (uint32_t)user_fmt))
       return fail(GT_ERR_INVALID_ARG, "pool format was not built");
-    if ((maxp ? ix->pw : ix->dp) > maxdp_of(fmt))
-      return fail(GT_ERR_INVALID_ARG, "d too large for this pool format (padded d <= " +
-                                          std::to_string(maxdp_of(fmt)) + ")");
+    if ((maxp ? ix->pw : ix->dp) > gt::kMaxWalkWidth)
+      return fail(GT_ERR_INVALID_ARG, "pool rows wider than " +
+                                          std::to_string(gt::kMaxWalkWidth) + " columns");
   }
   TRY(check_query_args(ix, q, nq, rho, tq));
   if (ix->signed_mode)
@@ -965,7 +964,6 @@ gt_status gt_build_tree(const void* feats_dev, int64_t n, int32_t d, gt_dtype dt
   const bool sgn = (pool_formats & GT_POOL_SIGNED) != 0;
   if (sgn && (pool_formats & (GT_POOL_F32 | GT_POOL_BF16 | GT_POOL_FP8E4M3)))
     return fail(GT_ERR_INVALID_ARG, "an index of signed vectors keeps max/min pools only");
-  if (sgn && d > 512) return fail(GT_ERR_INVALID_ARG, "d must be <= 512 for signed vectors");
   if (capacity == 0) {
     capacity = 2;
     while (capacity < n) capacity <<= 1;

@@ -29,8 +29,14 @@ constexpr int kMaxSlots = 8192;       // nt << nb
 constexpr int kMaxSlotsPerXcd = kMaxSlots / kXcds;
 constexpr int kMaxBucketsPerXcd = (1 << kMaxBucketBits) / kXcds;
 
-// Largest padded dimension each walk format supports (query tile in LDS).
+// Largest row length (padded columns) whose whole query tile each walk
+// format keeps in LDS; wider rows (up to kMaxWalkWidth: d <= 4096, or the
+// 2 d_pad rows of a signed index) pass the tile through LDS in windows.
 constexpr int kMaxDpBf16 = 1152, kMaxDpFp8 = 2304, kMaxDpF32 = 1152;
+constexpr int kMaxWalkWidth = 8192;
+__host__ __device__ constexpr int maxdp_walk(int fmt) {
+  return fmt == GT_POOL_F32 ? kMaxDpF32 : fmt == GT_POOL_BF16 ? kMaxDpBf16 : kMaxDpFp8;
+}
 
 // Device scratch of the allocation-free query entry point (one array per
 // device, in gt_noalloc.hip).

@@ -477,6 +477,239 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
   }
 }
 
+// Level step for rows wider than the LDS query tile (padded width above
+// WalkFmt::MAXDP: the whole tile no longer fits in LDS).  Same buckets, XCD
+// split, groups and decisions as k_walk_level, but the tile's query rows pass
+// through LDS in windows of kWideWindow bytes: the workgroup's waves work in
+// rounds of one group each, and within a round every wave multiplies its
+// group's 32 child rows window by window, all waves stepping through the
+// windows together (one barrier pair per window).  Each window's 64-byte
+// steps are loaded eight at a time.  Scores are the same sums over the same
+// dimensions (in another order), so the decisions keep their slack.
+constexpr int kWideWindow = 2048;  // bytes of every query row per LDS window
+
+template <int FMT>
+__global__ __launch_bounds__(kWalkThreads, 1) void k_walk_wide(WalkLevelArgs a) {
+  using F = WalkFmt<FMT>;
+  constexpr int TQ = F::TQ;
+  constexpr int NQB = TQ / 16;
+  constexpr int RS = kWideWindow + 16;  // LDS row stride (bank spread)
+  __shared__ __attribute__((aligned(16))) unsigned char qlds[TQ * RS];
+  __shared__ uint32_t gpre[kMaxBucketsPerXcd + 1];
+  __shared__ uint32_t glo[kMaxBucketsPerXcd], ghi[kMaxBucketsPerXcd];
+  __shared__ float thr_lds[TQ];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int rowbytes = a.dp * F::ESZ;
+  const int nwin = (rowbytes + kWideWindow - 1) / kWideWindow;
+  const int c16 = lane & 15, g4 = lane >> 4;
+
+  const int nbk = 1 << a.nb;
+  const int xs = nbk < kXcds ? nbk : kXcds;
+  const int R = nbk / xs;
+  const int x = blockIdx.x % kXcds;
+  const int W = gridDim.x / kXcds, j = blockIdx.x / kXcds;
+  if (x >= xs) return;
+  int t0, tstep, m, c;
+  if (a.nt <= W) {
+    t0 = j % a.nt;
+    tstep = a.nt;
+    m = j / a.nt;
+    c = (W - 1 - t0) / a.nt + 1;
+  } else {
+    t0 = j;
+    tstep = W;
+    m = 0;
+    c = 1;
+  }
+  const int bshift = a.level - a.nb;
+  unsigned long long pairs = 0;
+
+  for (int t = t0; t < a.nt; t += tstep) {
+    const uint64_t tmask = a.tile_mask[t];
+    __syncthreads();
+    if (wave == 0) {
+      uint32_t ng = 0, lo = 0, hi = 0;
+      if (lane < R && tmask) {
+        const uint32_t n = a.dense ? (1u << bshift) : a.in_count[(size_t)(x * R + lane) * a.nt + t];
+        lo = (uint32_t)(((uint64_t)n * m) / c);
+        hi = (uint32_t)(((uint64_t)n * (m + 1)) / c);
+        ng = (hi - lo + kGroupEntries - 1) / kGroupEntries;
+      }
+      uint32_t incl = ng;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+      }
+      if (lane < R) {
+        gpre[lane] = incl - ng;
+        glo[lane] = lo;
+        ghi[lane] = hi;
+      }
+      if (lane == 63) gpre[R] = incl;
+    }
+    if (tid < TQ) {
+      const int qi = t * TQ + tid;
+      float th = a.thr[qi];
+      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+      thr_lds[tid] = th;
+    }
+    __syncthreads();
+    const uint32_t gtot = gpre[R];
+    if (gtot == 0) continue;
+    const unsigned char* qsrc = reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)t * TQ * rowbytes;
+
+    for (uint32_t base = 0; base < gtot; base += (uint32_t)nwaves) {
+      const uint32_t gg = base + (uint32_t)wave;
+      const bool valid = gg < gtot;  // uniform per wave
+      // group gg's entries held by this lane (rows c16 and 16 + c16 of the
+      // group's 32 child rows), as in k_walk_level; a wave without a group
+      // this round takes the last group with empty masks
+      const uint32_t ge = valid ? gg : gtot - 1;
+      const int r = find_slot(gpre, R, ge);
+      const uint32_t e0 = glo[r] + (ge - gpre[r]) * kGroupEntries + (c16 >> 1);
+      const uint32_t e1 = e0 + 8;
+      const uint32_t ehi = ghi[r];
+      const uint32_t bk = (uint32_t)(x * R + r);
+      const uint32_t slot = bk * (uint32_t)a.nt + (uint32_t)t;
+      const size_t ebase = (size_t)slot * a.bcap;
+      const uint32_t ef = e0 - (c16 >> 1);
+      const uint32_t i0 = e0 < ehi ? e0 : ef, i1 = e1 < ehi ? e1 : ef;
+      const uint32_t first = bk << bshift;
+      const uint32_t p0 = a.dense ? first + i0 : a.in_node[ebase + i0];
+      const uint32_t p1 = a.dense ? first + i1 : a.in_node[ebase + i1];
+      const uint64_t pm0 = (valid && e0 < ehi) ? (a.dense ? tmask : a.in_mask[ebase + i0]) : 0ull;
+      const uint64_t pm1 = (valid && e1 < ehi) ? (a.dense ? tmask : a.in_mask[ebase + i1]) : 0ull;
+      // rows this lane loads: lanes 4R'..4R'+3 take 64 contiguous bytes of
+      // row R' (entry R' / 2, child R' % 2) of each block
+      const int src = 2 * (lane >> 3);
+      const uint32_t q0 = (uint32_t)__shfl((int)p0, src, 64);
+      const uint32_t q1 = (uint32_t)__shfl((int)p1, src, 64);
+      const uint32_t ch = (uint32_t)((lane >> 2) & 1);
+      const unsigned char* rbase = reinterpret_cast<const unsigned char*>(a.child_rows) + 16 * (lane & 3);
+      const unsigned char* arow0 = rbase + (size_t)(2u * q0 + ch) * rowbytes;
+      const unsigned char* arow1 = rbase + (size_t)(2u * q1 + ch) * rowbytes;
+      const int bp_addr = 4 * (4 * c16 + g4);
+      auto to_mfma = [&](const uint4& v) {
+        uint4 o;
+        o.x = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.x);
+        o.y = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.y);
+        o.z = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.z);
+        o.w = (uint32_t)__builtin_amdgcn_ds_bpermute(bp_addr, (int)v.w);
+        return o;
+      };
+      f32x4 acc[2][NQB];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int qb = 0; qb < NQB; ++qb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[rb][qb][i] = 0.0f;
+
+      for (int wi = 0; wi < nwin; ++wi) {
+        const int wofs = wi * kWideWindow;
+        const int wbytes = rowbytes - wofs < kWideWindow ? rowbytes - wofs : kWideWindow;
+        __syncthreads();  // every wave is done with the previous window
+        {
+          const int vpr = wbytes / 16;  // 16-byte vectors per row in this window
+          const int nvec = TQ * vpr;
+          for (int v0 = 0; v0 < nvec; v0 += 8 * kWalkThreads) {
+            uint4 buf[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int v = v0 + k * kWalkThreads + tid;
+              const int vv = v < nvec ? v : nvec - 1;
+              const int row = vv / vpr, col = vv - row * vpr;
+              buf[k] = *reinterpret_cast<const uint4*>(qsrc + (size_t)row * rowbytes + wofs + col * 16);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              const int v = v0 + k * kWalkThreads + tid;
+              if (v < nvec) {
+                const int row = v / vpr, col = v - row * vpr;
+                *reinterpret_cast<uint4*>(qlds + row * RS + col * 16) = buf[k];
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (valid) {
+          const int wsteps = wbytes / 64;
+          const unsigned char* brow = qlds + c16 * RS + 16 * g4;
+          for (int s0 = 0; s0 < wsteps; s0 += 8) {
+            uint4 l0[8], l1[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int st = s0 + u < wsteps ? s0 + u : wsteps - 1;
+              l0[u] = ld_global16(arow0 + wofs + 64 * st);
+              l1[u] = ld_global16(arow1 + wofs + 64 * st);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              if (s0 + u < wsteps) {
+                const uint4 x0 = to_mfma(l0[u]), x1 = to_mfma(l1[u]);
+#pragma unroll
+                for (int qb = 0; qb < NQB; ++qb) {
+                  const uint4 bq = ld_lds16(brow + qb * 16 * RS + 64 * (s0 + u));
+                  mma16x16<FMT>(x0, bq, acc[0][qb]);
+                  mma16x16<FMT>(x1, bq, acc[1][qb]);
+                }
+              }
+            }
+          }
+        }
+      }
+      if (!valid) continue;
+      if (a.bitmap && lane < 16) {
+        const uint32_t child0 = 2u * p0 + (uint32_t)(lane & 1), child1 = 2u * p1 + (uint32_t)(lane & 1);
+        if (pm0) {
+          const uint64_t row = (uint64_t)a.bit_base + child0;
+          atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
+        }
+        if (pm1) {
+          const uint64_t row = (uint64_t)a.bit_base + child1;
+          atomicOr(&a.bitmap[row >> 5], 1u << (row & 31));
+        }
+      }
+      // survival bits as in k_walk_level: lane r < 32 ends with child row r's mask
+      const int gsel = 16 * ((lane & 15) >> 2);
+      uint64_t mine = 0ull;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          uint64_t part = 0ull;
+#pragma unroll
+          for (int qb = 0; qb < NQB; ++qb) {
+            const uint64_t bal = __ballot(acc[rb][qb][i] >= thr_lds[16 * qb + c16]);
+            part |= ((bal >> gsel) & 0xffffull) << (16 * qb);
+          }
+          if ((lane >> 4) == rb && (lane & 3) == i) mine = part;
+        }
+      const uint64_t pm_own = lane < 16 ? pm0 : pm1;
+      mine = lane < 32 ? (mine & pm_own) : 0ull;
+      if (lane < 32) pairs += (unsigned long long)__popcll(pm_own);
+      const uint64_t bal = __ballot(mine != 0ull);
+      if (bal == 0ull) continue;
+      uint32_t obase = 0;
+      if (lane == 0) obase = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(bal));
+      obase = __shfl(obase, 0, 64);
+      if (mine) {
+        const uint32_t pos = obase + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+        const size_t o = (size_t)slot * a.bcap + pos;
+        a.out_node[o] = 2u * (lane < 16 ? p0 : p1) + (uint32_t)(lane & 1);
+        a.out_mask[o] = mine;
+      }
+    }
+  }
+  if (a.stat_pairs) {
+    for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
+    if (lane == 0 && pairs) atomicAdd(a.stat_pairs, pairs);
+  }
+}
+
 // Level step with subtraction (bfloat16 pools; paper Sec. 2 and Alg. 1 derive
 // the score of one half of a pool from the pool's score and the other half's).
 // Every entry carries a score record: upper bounds of its pool's real score
@@ -1610,8 +1843,26 @@ hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStrea
   // whole workgroups per XCD; bucket and slot limits of the kernels
   grid = kXcds * ((grid + kXcds - 1) / kXcds);
   if (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
-      a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles)
+      a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles || a.dp < 128 || a.dp % 128 != 0 ||
+      a.dp > kMaxWalkWidth)
     return hipErrorInvalidValue;
+  // rows wider than the LDS query tile: windows of the tile through LDS
+  if (a.dp > maxdp_walk(fmt)) {
+    switch (fmt) {
+      case GT_POOL_BF16:
+        hipLaunchKernelGGL(k_walk_wide<GT_POOL_BF16>, dim3(grid), dim3(kWalkThreads), 0, s, a);
+        break;
+      case GT_POOL_FP8E4M3:
+        hipLaunchKernelGGL(k_walk_wide<GT_POOL_FP8E4M3>, dim3(grid), dim3(kWalkThreads), 0, s, a);
+        break;
+      case GT_POOL_F32:
+        hipLaunchKernelGGL(k_walk_wide<GT_POOL_F32>, dim3(grid), dim3(kWalkThreads), 0, s, a);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   // fast paths: padded width 1024
   switch (fmt) {
     case GT_POOL_BF16: return launch_walk_fmt<GT_POOL_BF16, 32>(a, grid, s);
@@ -1623,7 +1874,8 @@ hipError_t launch_walk_level(int fmt, const WalkLevelArgs& a, int grid, hipStrea
 
 hipError_t launch_walk_sub(const WalkLevelArgs& a, int grid, hipStream_t s) {
   grid = kXcds * ((grid + kXcds - 1) / kXcds);
-  if (a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
+  if (a.dp > kMaxDpBf16 || a.dp < 128 || a.dp % 128 != 0 ||
+      a.nb < 0 || a.nb > kMaxBucketBits || ((int64_t)a.nt << a.nb) > kMaxSlots ||
       a.level < a.nb || a.nt < 1 || a.nt > kMaxTiles || a.dense || !a.in_rec || !a.sabs ||
       a.level + 1 >= a.depth || a.depth > 32)
     return hipErrorInvalidValue;

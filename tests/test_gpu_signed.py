@@ -203,7 +203,7 @@ def test_signed_inserts_equal_rebuild(gtmod):
 
 
 def test_signed_errors(gtmod):
-    """Sum formats, d > 512, rho <= 0 and non-finite values are refused; a
+    """Sum formats, d > 4096, rho <= 0 and non-finite values are refused; a
     negative value without the signed flag is refused as before."""
     w = synth.workload_signed(600, 16, 3, seed_offset=5)
     F = _dev(w.feats)
@@ -212,7 +212,7 @@ def test_signed_errors(gtmod):
             gtmod.GTIndex(F, pools=p)
         assert e.value.status == gtmod.GT_ERR_INVALID_ARG, p
     with pytest.raises(gtmod.GTError) as e:
-        gtmod.GTIndex(_dev(np.zeros((4, 513), np.float32)), pools=SIGNED)
+        gtmod.GTIndex(_dev(np.zeros((4, 4097), np.float32)), pools=SIGNED)
     assert e.value.status == gtmod.GT_ERR_INVALID_ARG
     with pytest.raises(gtmod.GTError) as e:
         gtmod.GTIndex(F, pools=("f32", "max_f32"))
