@@ -238,6 +238,50 @@ gt_status gt_batch_finish(gt_batch* batch, int64_t max_results, int64_t* offsets
                           int64_t* ids_dev, float* sims_dev, int64_t* total_out);
 void gt_batch_destroy(gt_batch* batch);
 
+/* Admission by memory (continuous batching, paper Sec. 4 streaming setting):
+ * workspaces whose device memory the caller hands to each call, so that a
+ * server can hold one device arena and admit a call only while its memory
+ * fits.  Such a call's frontier gets what its memory leaves after its other
+ * buffers -- a budget, not the worst case -- and its kernels check every
+ * frontier write against it.  When a level outgrows the budget (or the
+ * candidates outgrow `pairs`), gt_batch_finish runs the call again one query
+ * tile (64 queries; 32 for float32 pools) at a time, each tile with the whole
+ * memory, which always holds one tile's worst case (the submit checks it):
+ * the results are the same, only later.
+ *
+ * gt_call_bytes  device bytes for a call of nq queries in format fmt with room
+ *                for frontier_entries entries per frontier level (all tiles
+ *                together; 0 = the least) and `pairs` leaf candidates and
+ *                results (at least 1024).  *min_bytes_out (may be NULL): the
+ *                least memory any such call accepts.  bf16 sum-pool calls
+ *                with a dense step keep 280 bytes per frontier entry
+ *                (subtraction-step score records), others 24.
+ * gt_batch_create_external  a workspace without device memory of its own
+ *                (an event and pinned counters only); calls up to max_queries.
+ * gt_batch_submit_external  as gt_batch_submit, with the call's device
+ *                memory [mem_dev, mem_dev + mem_bytes) (256-byte aligned,
+ *                owned by the caller, not touched by anything else until
+ *                gt_batch_finish returns) and its candidate room `pairs`.  The
+ *                queries q_dev must stay valid until gt_batch_finish returns
+ *                (a continuation reads them again).  Errors: CAPACITY
+ *                (mem_bytes below the call's least, nq above max_queries),
+ *                INVALID_ARG, DEVICE.
+ *   gt_batch_poll / gt_batch_finish / gt_batch_destroy as for any workspace;
+ *   after a result overflow of a continued call, the next finish runs its
+ *   tiles again.  A tile whose candidates outgrow `pairs` fails with CAPACITY.
+ * gt_batch_info  of the workspace's last finished call: the largest number
+ *                of frontier entries at any level, the results, and how many
+ *                tiles ran one by one (0: the call fitted its memory).  Any
+ *                output may be NULL. */
+gt_status gt_call_bytes(const gt_index* index, int32_t nq, gt_pool fmt, int64_t frontier_entries,
+                        int64_t pairs, int64_t* bytes_out, int64_t* min_bytes_out);
+gt_status gt_batch_create_external(gt_index* index, int32_t max_queries, gt_batch** out);
+gt_status gt_batch_submit_external(gt_batch* batch, const float* q_dev, int32_t nq,
+                                   const double* rho_host, gt_pool fmt, void* mem_dev,
+                                   int64_t mem_bytes, int64_t pairs, void* stream);
+gt_status gt_batch_info(const gt_batch* batch, int64_t* max_level_entries, int64_t* results,
+                        int32_t* continued_tiles);
+
 /* Counters of the index and of its last query call.  Synchronises the device
  * stream of the last call.  Errors: INVALID_ARG. */
 gt_status gt_get_stats(const gt_index* index, gt_stats* out);

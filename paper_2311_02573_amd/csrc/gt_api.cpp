@@ -204,6 +204,14 @@ void free_frontier(Batch* b) {
 void free_batch(Batch* b) {
   if (!b) return;
   Index* ix = b->ix;
+  if (b->external) {
+    // device buffers were the caller's: only the host-side resources
+    if (b->h_ctr) (void)hipHostFree(b->h_ctr);
+    b->h_ctr = nullptr;
+    if (b->done) (void)hipEventDestroy(b->done);
+    b->done = nullptr;
+    return;
+  }
   free_query_arrays(b);
   free_frontier(b);
   dfree(ix, &b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots);
@@ -269,8 +277,7 @@ gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
   Index* ix = b->ix;
   const size_t dp = (size_t)ix->dp;
   if (b->fixed) {
-    if (nq_pad > b->nq_alloc || nt > b->nt_alloc ||
-        b->fr_cap != (int64_t(1) << std::max(0, ix->depth - 1)))
+    if (nq_pad > b->nq_alloc || nt > b->nt_alloc || b->fr_cap < 1)
       return fail(GT_ERR_CAPACITY, "the call does not fit the buffers carved for it");
     return GT_OK;
   }
@@ -473,6 +480,7 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
       a.bitmap = bitmap;
       a.bit_base = level_row(L);
       a.out_rec = (use_rec && L == dl) ? b->fr_rec[L & 1] : nullptr;
+      a.over = &b->ctr->fr_over;
       ev_launch_begin(b);
       HIPCHK(gt::launch_dense_level(f, a, s));
       ev_launch_end(b, true);
@@ -503,6 +511,7 @@ gt_status enqueue_walk(Index* ix, Batch* b) {
     a.stat_pairs = &b->ctr->pairs[l + 1];
     a.bitmap = bitmap;
     a.bit_base = level_row(l + 1);
+    a.over = &b->ctr->fr_over;
     ev_launch_begin(b);
     if (use_rec && l <= sub_to) {
       a.in_rec = b->fr_rec[l & 1];
@@ -655,6 +664,102 @@ void* arena_take(Batch* b, size_t bytes) {
   return b->arena + off;
 }
 
+constexpr size_t kPerPair = sizeof(gt::Hit) + 4 + 4 * 4;  // hit, band index, 4 staging words
+constexpr size_t kPerEntry = 2 * (4 + 8);                   // node and mask, two levels
+constexpr size_t kPerRecord = 2 * 64 * 2;                   // 64 bf16 bounds, two levels
+
+// Call shape of a walk in user pool format fmt: the walked format, tiles.
+struct CallShape {
+  bool maxp;
+  int wf, tq, nt, nq_pad, h, dl;
+  bool want_rec;
+};
+CallShape call_shape(const Index* ix, int nq, int fmt) {
+  CallShape c{};
+  c.maxp = fmt == GT_POOL_MAX_F32 || fmt == GT_POOL_MAX_BF16;
+  c.wf = c.maxp ? (fmt == GT_POOL_MAX_F32 ? GT_POOL_F32 : GT_POOL_BF16) : fmt;
+  c.tq = tq_of(c.wf);
+  c.nt = std::max(1, (nq + c.tq - 1) / c.tq);
+  c.nq_pad = std::max(128, (nq + 127) / 128 * 128);
+  c.h = head_of(ix);
+  c.dl = dense_last_of(ix, c.wf, c.h);
+  c.want_rec = c.wf == GT_POOL_BF16 && !c.maxp && c.dl >= 0 && ix->walk_subtract != 0 &&
+               c.dl <= ix->depth - 2 && ix->dp <= gt::kMaxDpBf16;
+  return c;
+}
+
+template <class T>
+void take(Batch* b, T*& p, size_t count, bool& ok) {
+  p = static_cast<T*>(arena_take(b, std::max<size_t>(count, 1) * sizeof(T)));
+  ok = ok && p != nullptr;
+}
+
+// The buffers of a walk call other than its frontier, records and candidates:
+// counters, query copies, and the dense masks of chained dense steps.
+void carve_common(Index* ix, Batch* b, void* base, size_t bytes, int nq, const CallShape& c,
+                  bool& ok) {
+  b->ix = ix;
+  b->fixed = true;
+  b->arena = static_cast<unsigned char*>(base);
+  b->arena_size = bytes;
+  b->arena_used = 0;
+  b->max_queries = std::max(nq, 1);
+  b->rec_len = 0;
+  b->dmask_len = 0;
+  b->fr_rec[0] = b->fr_rec[1] = nullptr;
+  b->dmask[0] = b->dmask[1] = nullptr;
+  const size_t dp = (size_t)ix->dp, pw = (size_t)ix->pw, nqa = (size_t)c.nq_pad;
+  take(b, b->ctr, 1, ok);
+  take(b, b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots, ok);
+  take(b, b->tile_mask, gt::kMaxTiles, ok);
+  take(b, b->qf, nqa * dp, ok);
+  if (ix->signed_mode) take(b, b->qw, nqa * pw, ok);
+  take(b, b->qbf, nqa * pw, ok);
+  take(b, b->q8, nqa * dp, ok);
+  take(b, b->qexp, nqa, ok);
+  take(b, b->invn_q, nqa, ok);
+  take(b, b->qq, nqa, ok);
+  take(b, b->rho, nqa, ok);
+  take(b, b->thr, nqa, ok);
+  take(b, b->thr_gemm, nqa, ok);
+  take(b, b->sabs, nqa, ok);
+  take(b, b->qcount, nqa, ok);
+  take(b, b->offs, nqa + 1, ok);
+  b->nq_alloc = c.nq_pad;
+  b->nt_alloc = c.nt;
+  if (c.dl >= 0 && ix->head_level >= 0 && c.h + 1 < c.dl) {
+    const size_t need = ((size_t)1 << std::max(0, c.dl - 1)) * (size_t)c.nt;
+    take(b, b->dmask[0], need, ok);
+    take(b, b->dmask[1], need, ok);
+    b->dmask_len = (int64_t)need;
+  }
+}
+
+void carve_pairs(Batch* b, size_t pairs, bool& ok) {
+  take(b, b->hits, pairs, ok);
+  take(b, b->band_idx, pairs, ok);
+  take(b, b->out_id, pairs, ok);
+  take(b, b->out_sim, pairs, ok);
+  take(b, b->tmp_id, pairs, ok);
+  take(b, b->tmp_sim, pairs, ok);
+  b->hit_cap = (int64_t)pairs;
+  b->out_cap = (int64_t)pairs;
+}
+
+// Frontier of fr_cap entries per tile (two levels), with score records if asked.
+void carve_frontier(Batch* b, int nt, int64_t fr_cap, bool rec, bool& ok) {
+  for (int k = 0; k < 2; ++k) {
+    take(b, b->fr_node[k], (size_t)nt * fr_cap, ok);
+    take(b, b->fr_mask[k], (size_t)nt * fr_cap, ok);
+  }
+  if (rec) {
+    take(b, b->fr_rec[0], (size_t)nt * fr_cap * 64, ok);
+    take(b, b->fr_rec[1], (size_t)nt * fr_cap * 64, ok);
+    b->rec_len = (int64_t)nt * fr_cap;
+  }
+  b->fr_cap = fr_cap;
+}
+
 // Carves every buffer of one walk call of nq queries in pool format fmt out of
 // [base, base + bytes): counters, query copies, the frontier at its worst case
 // (every pool of the deepest level for every tile, so no level can overflow),
@@ -663,87 +768,62 @@ void* arena_take(Batch* b, size_t bytes) {
 // split between candidates and result staging.  GT_ERR_CAPACITY if the
 // frontier alone does not fit.
 gt_status carve_fixed(Index* ix, Batch* b, void* base, size_t bytes, int nq, int fmt) {
-  constexpr size_t kPerPair = sizeof(gt::Hit) + 4 + 4 * 4;  // hit, band index, 4 staging words
   constexpr size_t kMinPairs = size_t(1) << 20;
-  b->ix = ix;
-  b->fixed = true;
-  b->arena = static_cast<unsigned char*>(base);
-  b->arena_size = bytes;
-  b->arena_used = 0;
-  b->max_queries = std::max(nq, 1);
-  const bool maxp = fmt == GT_POOL_MAX_F32 || fmt == GT_POOL_MAX_BF16;
-  const int wf = maxp ? (fmt == GT_POOL_MAX_F32 ? GT_POOL_F32 : GT_POOL_BF16) : fmt;
-  const int tq = tq_of(wf);
-  const int nt = std::max(1, (nq + tq - 1) / tq);
-  const int nq_pad = std::max(128, (nq + 127) / 128 * 128);
-  const size_t dp = (size_t)ix->dp, pw = (size_t)ix->pw, nqa = (size_t)nq_pad;
+  const CallShape c = call_shape(ix, nq, fmt);
   const int64_t fr_cap = int64_t(1) << std::max(0, ix->depth - 1);
   bool ok = true;
-  auto take = [&](auto*& p, size_t count) {
-    using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
-    p = static_cast<T*>(arena_take(b, std::max<size_t>(count, 1) * sizeof(T)));
-    ok = ok && p != nullptr;
-  };
-  take(b->ctr, 1);
-  take(b->lvl_count, (size_t)GT_MAX_LEVELS * gt::kMaxSlots);
-  take(b->tile_mask, gt::kMaxTiles);
-  take(b->qf, nqa * dp);
-  if (ix->signed_mode) take(b->qw, nqa * pw);
-  take(b->qbf, nqa * pw);
-  take(b->q8, nqa * dp);
-  take(b->qexp, nqa);
-  take(b->invn_q, nqa);
-  take(b->qq, nqa);
-  take(b->rho, nqa);
-  take(b->thr, nqa);
-  take(b->thr_gemm, nqa);
-  take(b->sabs, nqa);
-  take(b->qcount, nqa);
-  take(b->offs, nqa + 1);
-  b->nq_alloc = nq_pad;
-  for (int k = 0; k < 2; ++k) {
-    take(b->fr_node[k], (size_t)nt * fr_cap);
-    take(b->fr_mask[k], (size_t)nt * fr_cap);
-  }
-  b->nt_alloc = nt;
-  b->fr_cap = fr_cap;
-  const int h = head_of(ix);
-  const int dl = dense_last_of(ix, wf, h);
-  if (dl >= 0 && ix->head_level >= 0 && h + 1 < dl) {
-    const size_t need = ((size_t)1 << std::max(0, dl - 1)) * (size_t)nt;
-    take(b->dmask[0], need);
-    take(b->dmask[1], need);
-    b->dmask_len = (int64_t)need;
-  }
+  carve_common(ix, b, base, bytes, nq, c, ok);
+  carve_frontier(b, c.nt, fr_cap, false, ok);
   if (!ok)
     return fail(GT_ERR_CAPACITY,
                 "a call of " + std::to_string(nq) + " queries on an index of depth " +
                     std::to_string(ix->depth) + " needs more than the " +
                     std::to_string(bytes >> 20) + " MiB of fixed scratch for its frontier; " +
                     "use fewer queries per call");
-  const size_t rec = (size_t)nt * (size_t)fr_cap * 64 * sizeof(uint16_t);
-  const bool want_rec = wf == GT_POOL_BF16 && !maxp && dl >= 0 && ix->walk_subtract != 0 &&
-                        ix->dp <= gt::kMaxDpBf16;
+  const size_t rec = (size_t)c.nt * (size_t)fr_cap * 64 * sizeof(uint16_t);
   const size_t left0 = bytes - b->arena_used;
-  if (want_rec && left0 > 2 * rec + 2 * 256 + kMinPairs * kPerPair + 8 * 256) {
-    take(b->fr_rec[0], rec / 2);
-    take(b->fr_rec[1], rec / 2);
-    b->rec_len = (int64_t)nt * fr_cap;
+  if (c.want_rec && left0 > 2 * rec + 2 * 256 + kMinPairs * kPerPair + 8 * 256) {
+    take(b, b->fr_rec[0], rec / 2, ok);
+    take(b, b->fr_rec[1], rec / 2, ok);
+    b->rec_len = (int64_t)c.nt * fr_cap;
   }
   const size_t left = bytes - b->arena_used;
   const size_t pairs = left > 8 * 256 ? (left - 8 * 256) / kPerPair : 0;
   if (pairs < 1024)
     return fail(GT_ERR_CAPACITY, "no room for candidates in the fixed scratch beside a call of " +
                                      std::to_string(nq) + " queries; use fewer queries per call");
-  take(b->hits, pairs);
-  take(b->band_idx, pairs);
-  take(b->out_id, pairs);
-  take(b->out_sim, pairs);
-  take(b->tmp_id, pairs);
-  take(b->tmp_sim, pairs);
+  carve_pairs(b, pairs, ok);
   if (!ok) return fail(GT_ERR_CAPACITY, "fixed scratch carve failed");
-  b->hit_cap = (int64_t)pairs;
-  b->out_cap = (int64_t)pairs;
+  return GT_OK;
+}
+
+// Bytes of the common buffers of a call (with their alignment).
+size_t common_bytes(Index* ix, int nq, const CallShape& c) {
+  Batch dry;
+  bool ok = true;
+  carve_common(ix, &dry, reinterpret_cast<void*>(uintptr_t(256)), SIZE_MAX / 4, nq, c, ok);
+  return dry.arena_used + 256;
+}
+
+// Carve of an external workspace's call: the common buffers, `pairs`
+// candidates and results, and a frontier of whatever the memory leaves (at
+// most the worst case), with score records only if allowed and wanted.
+gt_status carve_budget(Index* ix, Batch* b, void* base, size_t bytes, int nq, int fmt,
+                       int64_t pairs, bool allow_rec) {
+  const CallShape c = call_shape(ix, nq, fmt);
+  bool ok = true;
+  carve_common(ix, b, base, bytes, nq, c, ok);
+  carve_pairs(b, (size_t)std::max<int64_t>(pairs, 1024), ok);
+  if (!ok) return fail(GT_ERR_CAPACITY, "the call's memory does not hold its query and candidate buffers");
+  const bool rec = allow_rec && c.want_rec;
+  const size_t per = kPerEntry + (rec ? kPerRecord : 0);
+  const size_t left = bytes - b->arena_used;
+  const size_t usable = left > 8 * 256 ? left - 8 * 256 : 0;
+  const int64_t worst = int64_t(1) << std::max(0, ix->depth - 1);
+  const int64_t fr_cap = std::min<int64_t>(worst, (int64_t)(usable / per / (size_t)c.nt));
+  if (fr_cap < 64) return fail(GT_ERR_CAPACITY, "the call's memory leaves no room for its frontier");
+  carve_frontier(b, c.nt, fr_cap, rec, ok);
+  if (!ok) return fail(GT_ERR_CAPACITY, "frontier carve failed");
   return GT_OK;
 }
 
@@ -785,7 +865,8 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
   b->nq_pad = nq_pad;
   b->nt = nt;
   b->tq = tq;
-  b->n_epoch = ix->n;
+  // a continuation tile sees the rows its call saw, whatever was inserted since
+  b->n_epoch = b->cont ? b->ext_epoch : ix->n;
   b->head = head_of(ix);
   b->dense_last = kind == 1 ? dense_last_of(ix, fmt, b->head) : -1;
   if (kind == 1) b->dense_last = adapt_dense_last(ix, b, fmt, maxp, b->dense_last, b->head);
@@ -836,7 +917,7 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
                                  ix->signed_mode ? ix->sbound : 0.0f, &b->ctr->err, nq_pad, s));
   }
   ev_mark(b, 1);
-  if (nq > 0 && ix->n > 0) {
+  if (nq > 0 && b->n_epoch > 0) {
     if (kind == 1) {
       TRY(enqueue_walk(ix, b));
       ev_mark(b, 2);
@@ -864,10 +945,18 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
 // Waits for the counters, handles buffer overflow, writes offsets, ids and sims.
 // keep_on_overflow: after GT_ERR_RESULT_OVERFLOW the call stays in flight, so
 // finish can be called again with larger buffers without recomputing it.
+gt_status continue_by_tiles(Index* ix, Batch* b, int64_t max_results, int64_t* offsets,
+                            int64_t* ids, float* sims, int64_t* total_out, bool keep_on_overflow);
+
 gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int64_t* ids,
                  float* sims, int64_t* total_out, bool keep_on_overflow) {
   if (!b->pending) return fail(GT_ERR_INVALID_ARG, "no call in flight on this workspace");
   b->pending = false;
+  if (b->cont_again) {
+    if (!total_out || !offsets || max_results < 0 || (max_results > 0 && (!ids || !sims)))
+      return fail(GT_ERR_INVALID_ARG, "bad output arguments");
+    return continue_by_tiles(ix, b, max_results, offsets, ids, sims, total_out, keep_on_overflow);
+  }
   if (!total_out) return fail(GT_ERR_INVALID_ARG, "total_out is NULL");
   if (max_results < 0) return fail(GT_ERR_INVALID_ARG, "max_results < 0");
   if (!offsets) return fail(GT_ERR_INVALID_ARG, "offsets is NULL");
@@ -888,6 +977,10 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
       return fail(GT_ERR_CAPACITY, "a query has more than 2^30 results");
     const bool cand_over = b->kind == 2 && (int64_t)c.ncand > b->cand_cap;
     const bool hit_over = (int64_t)c.nhits > b->hit_cap;
+    if (b->external && !b->cont && (c.fr_over || hit_over))
+      return continue_by_tiles(ix, b, max_results, offsets, ids, sims, total_out, keep_on_overflow);
+    if (c.fr_over)
+      return fail(GT_ERR_CAPACITY, "a frontier level outgrew the memory given to one query tile");
     if (!cand_over && !hit_over) break;
     if (attempt > 3) return fail(GT_ERR_DEVICE, "candidate buffers did not converge");
     if (cand_over) {
@@ -909,6 +1002,10 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
     b->last_walk_nt = b->nt;
     b->last_n_epoch = b->n_epoch;
     memcpy(b->last_entries, b->h_ctr->entries, sizeof(b->last_entries));
+    int64_t mx = 0;
+    for (int l = 0; l < GT_MAX_LEVELS; ++l) mx = std::max(mx, (int64_t)b->h_ctr->entries[l]);
+    b->last_max_entries = mx;
+    b->last_results = (int64_t)b->h_ctr->total;
   }
   const int64_t total = (int64_t)b->h_ctr->total;
   *total_out = total;
@@ -938,6 +1035,79 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
     b->ms[5] = b->kind == 2 ? ev_walk(b, true) : 0.0;        // exhaustive GEMM
     b->ms[6] = ev_between(b, 0, 6);
     b->ms[7] = b->kind == 1 ? ev_walk(b, true) : 0.0;        // dense levels
+  }
+  return GT_OK;
+}
+
+// An external workspace's call whose frontier (or candidates) outgrew its
+// memory: the same call again, one query tile at a time, each tile with the
+// whole memory (enough for one tile's worst case, checked at submit) and
+// without score records.  A query's result does not depend on the other
+// queries of its call, so the results are those of the call; each tile's
+// results go straight to the caller's buffers after the previous tiles', and
+// its offsets are shifted by the results before it.
+gt_status continue_by_tiles(Index* ix, Batch* b, int64_t max_results, int64_t* offsets,
+                            int64_t* ids, float* sims, int64_t* total_out, bool keep_on_overflow) {
+  const int tq = tq_of(call_shape(ix, 1, b->user_fmt).wf);
+  const int nq = (int)b->rho_in.size();
+  const int nt = std::max(1, (nq + tq - 1) / tq);
+  const hipStream_t s = b->stream;
+  const std::vector<double> rho = b->rho_in;
+  std::vector<int64_t> hoff((size_t)tq + 1);
+  int64_t total = 0, max_entries = 0;
+  bool over = false;
+  b->cont = true;
+  b->cont_again = false;
+  b->continued_tiles = nt;
+  gt_status st = GT_OK;
+  for (int t = 0; t < nt && st == GT_OK; ++t) {
+    const int nq_t = std::min(tq, nq - t * tq);
+    const int64_t room = max_results > total ? max_results - total : 0;
+    int64_t* ids_t = room > 0 ? ids + total : nullptr;
+    float* sims_t = room > 0 ? sims + total : nullptr;
+    int64_t tot_t = 0;
+    st = carve_budget(ix, b, b->ext_mem, b->ext_bytes, nq_t, b->user_fmt, b->ext_pairs, false);
+    if (st == GT_OK) {
+      set_targets(b, room, ids_t, sims_t);
+      st = submit(ix, b, 1, b->q_in + (size_t)t * tq * ix->d, nq_t, rho.data() + (size_t)t * tq,
+                  b->user_fmt, s);
+    }
+    if (st == GT_OK) st = finish(ix, b, room, offsets + (size_t)t * tq, ids_t, sims_t, &tot_t, false);
+    if (st == GT_ERR_RESULT_OVERFLOW) {
+      over = true;
+      st = GT_OK;
+    }
+    if (st != GT_OK) break;
+    max_entries = std::max(max_entries, b->last_max_entries);
+    // the tile's offsets start at 0: shift them past the earlier tiles' results
+    const hipError_t e1 = hipMemcpyAsync(hoff.data(), offsets + (size_t)t * tq,
+                                         (size_t)(nq_t + 1) * 8, hipMemcpyDeviceToHost, s);
+    const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(s) : e1;
+    if (e2 != hipSuccess) {
+      st = fail(GT_ERR_DEVICE, std::string("continuation offsets: ") + hipGetErrorString(e2));
+      break;
+    }
+    for (int k = 0; k <= nq_t; ++k) hoff[k] += total;
+    const hipError_t e3 = hipMemcpyAsync(offsets + (size_t)t * tq, hoff.data(),
+                                         (size_t)(nq_t + 1) * 8, hipMemcpyHostToDevice, s);
+    const hipError_t e4 = e3 == hipSuccess ? hipStreamSynchronize(s) : e3;
+    if (e4 != hipSuccess) {
+      st = fail(GT_ERR_DEVICE, std::string("continuation offsets: ") + hipGetErrorString(e4));
+      break;
+    }
+    total += tot_t;
+  }
+  b->cont = false;
+  b->rho_in = rho;
+  if (st != GT_OK) return st;
+  b->last_max_entries = max_entries;
+  b->last_results = total;
+  *total_out = total;
+  if (over) {
+    // the next finish, with larger buffers, runs the tiles again
+    b->pending = keep_on_overflow;
+    b->cont_again = keep_on_overflow;
+    return fail(GT_ERR_RESULT_OVERFLOW, "need max_results >= " + std::to_string(total));
   }
   return GT_OK;
 }
@@ -1294,10 +1464,101 @@ gt_status gt_batch_create(gt_index* ix, int32_t max_queries, gt_batch** out) {
   return GT_OK;
 }
 
+gt_status gt_call_bytes(const gt_index* cix, int32_t nq, gt_pool fmt, int64_t frontier_entries,
+                        int64_t pairs, int64_t* bytes_out, int64_t* min_bytes_out) {
+  g_err.clear();
+  if (!cix || !bytes_out) return fail(GT_ERR_INVALID_ARG, "NULL argument");
+  if (nq < 1 || nq > gt::kMaxTiles * gt::kQueriesPerTileF32) return fail(GT_ERR_INVALID_ARG, "nq out of range");
+  if (frontier_entries < 0 || pairs < 0) return fail(GT_ERR_INVALID_ARG, "negative capacity");
+  Index* ix = const_cast<gt_index*>(cix);
+  const CallShape c = call_shape(ix, nq, (int)fmt);
+  const CallShape c1 = call_shape(ix, std::min(nq, c.tq), (int)fmt);
+  const int64_t worst = int64_t(1) << std::max(0, ix->depth - 1);
+  const size_t per = kPerEntry + (c.want_rec ? kPerRecord : 0);
+  const size_t slack = 24 * 256;
+  const size_t pr = (size_t)std::max<int64_t>(pairs, 1024) * kPerPair;
+  const int64_t fr_cap = std::max<int64_t>(64, std::min<int64_t>(worst, (frontier_entries + c.nt - 1) / c.nt));
+  const size_t want = common_bytes(ix, nq, c) + pr + (size_t)c.nt * (size_t)fr_cap * per + slack;
+  const size_t min_first = common_bytes(ix, nq, c) + pr + (size_t)c.nt * 64 * per + slack;
+  const size_t min_cont = common_bytes(ix, std::min(nq, c.tq), c1) + pr + (size_t)worst * kPerEntry + slack;
+  const size_t mn = std::max(min_first, min_cont);
+  *bytes_out = (int64_t)std::max(want, mn);
+  if (min_bytes_out) *min_bytes_out = (int64_t)mn;
+  return GT_OK;
+}
+
+gt_status gt_batch_create_external(gt_index* ix, int32_t max_queries, gt_batch** out) {
+  g_err.clear();
+  if (!ix || !out) return fail(GT_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  if (max_queries < 1 || max_queries > gt::kMaxTiles * gt::kQueriesPerTileF32)
+    return fail(GT_ERR_INVALID_ARG, "max_queries out of range");
+  gt_batch* b = new gt_batch();
+  b->ix = ix;
+  b->external = true;
+  b->max_queries = max_queries;
+  b->ext_max_queries = max_queries;
+  hipError_t e = hipHostMalloc((void**)&b->h_ctr, sizeof(gt::DevCounters), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    free_batch(b);
+    delete b;
+    return fail(GT_ERR_DEVICE, std::string("workspace set-up: ") + hipGetErrorString(e));
+  }
+  *out = b;
+  return GT_OK;
+}
+
+gt_status gt_batch_submit_external(gt_batch* b, const float* q_dev, int32_t nq,
+                                   const double* rho_host, gt_pool fmt, void* mem_dev,
+                                   int64_t mem_bytes, int64_t pairs, void* stream) {
+  g_err.clear();
+  if (!b) return fail(GT_ERR_INVALID_ARG, "batch is NULL");
+  if (!b->external) return fail(GT_ERR_INVALID_ARG, "not an external workspace");
+  if (b->pending) return fail(GT_ERR_INVALID_ARG, "the workspace has a call in flight");
+  Index* ix = b->ix;
+  if (nq < 1) return fail(GT_ERR_INVALID_ARG, "nq < 1");
+  if (nq > b->ext_max_queries)
+    return fail(GT_ERR_CAPACITY, "batch of " + std::to_string(nq) + " queries exceeds the workspace's " +
+                                     std::to_string(b->ext_max_queries));
+  if (!q_dev || !rho_host || !mem_dev) return fail(GT_ERR_INVALID_ARG, "NULL argument");
+  if (reinterpret_cast<uintptr_t>(mem_dev) % 256) return fail(GT_ERR_INVALID_ARG, "memory not 256-byte aligned");
+  if (pairs < 0 || mem_bytes < 0) return fail(GT_ERR_INVALID_ARG, "negative size");
+  int64_t need = 0, mn = 0;
+  TRY(gt_call_bytes(static_cast<gt_index*>(ix), nq, fmt, 0, pairs, &need, &mn));
+  if (mem_bytes < mn)
+    return fail(GT_ERR_CAPACITY, "a call of " + std::to_string(nq) + " queries needs at least " +
+                                     std::to_string(mn) + " bytes of workspace memory (given " +
+                                     std::to_string(mem_bytes) + ")");
+  b->q_in = q_dev;
+  b->rho_in.assign(rho_host, rho_host + nq);
+  b->user_fmt = (int)fmt;
+  b->ext_mem = static_cast<unsigned char*>(mem_dev);
+  b->ext_bytes = (size_t)mem_bytes;
+  b->ext_pairs = std::max<int64_t>(pairs, 1024);
+  b->cont_again = false;
+  b->continued_tiles = 0;
+  b->ext_epoch = ix->n;
+  TRY(carve_budget(ix, b, mem_dev, (size_t)mem_bytes, nq, (int)fmt, b->ext_pairs, true));
+  set_targets(b, 0, nullptr, nullptr);
+  return submit(ix, b, 1, q_dev, nq, b->rho_in.data(), (int)fmt, (hipStream_t)stream);
+}
+
+gt_status gt_batch_info(const gt_batch* b, int64_t* max_level_entries, int64_t* results,
+                        int32_t* continued_tiles) {
+  g_err.clear();
+  if (!b) return fail(GT_ERR_INVALID_ARG, "batch is NULL");
+  if (max_level_entries) *max_level_entries = b->last_max_entries;
+  if (results) *results = b->last_results;
+  if (continued_tiles) *continued_tiles = b->continued_tiles;
+  return GT_OK;
+}
+
 gt_status gt_batch_submit(gt_batch* b, const float* q_dev, int32_t nq, const double* rho_host,
                           gt_pool fmt, void* stream) {
   g_err.clear();
   if (!b) return fail(GT_ERR_INVALID_ARG, "batch is NULL");
+  if (b->external) return fail(GT_ERR_INVALID_ARG, "an external workspace takes gt_batch_submit_external");
   if (!b->pending) set_targets(b, 0, nullptr, nullptr);
   return submit(b->ix, b, 1, q_dev, nq, rho_host, (int)fmt, (hipStream_t)stream);
 }

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "gt.h"
 
@@ -67,6 +68,8 @@ struct DevCounters {
   unsigned long long nband;         // candidates within the recheck band
   unsigned int err;                 // invalid query input seen
   unsigned int slot_over;           // a query reached kMaxResultsPerQuery results
+  unsigned int fr_over;             // a frontier slot outgrew its capacity (entries dropped)
+  unsigned int pad_;
   unsigned long long pairs[GT_MAX_LEVELS];
   unsigned long long entries[GT_MAX_LEVELS];  // frontier (pool, tile) entries per level
 };
@@ -99,6 +102,7 @@ struct WalkLevelArgs {
   const float* sabs;        // [nt * TQ] absolute term of the lower bound
   int64_t n_epoch;          // rows visible to the call
   int depth;                // leaves are at this level
+  unsigned int* over;       // set when an output slot is full (its entry is dropped)
 };
 
 // Arguments of a dense level step (children at `level`, all 2^level pools).
@@ -122,6 +126,7 @@ struct DenseLevelArgs {
   uint32_t* bitmap;
   int64_t bit_base;
   uint16_t* out_rec;        // score records of the sparse output, or NULL
+  unsigned int* over;       // set when an output slot is full (its entry is dropped)
 };
 
 struct LeafArgs {
@@ -163,6 +168,26 @@ struct Batch {
   bool fixed = false;
   unsigned char* arena = nullptr;  // the fixed buffer and how much of it is used
   size_t arena_size = 0, arena_used = 0;
+  // External workspace (gt_batch_create_external): the caller hands each call
+  // its device memory.  The frontier gets what the memory leaves after the
+  // other buffers (a budget, not the worst case); when a level outgrows it,
+  // or the candidates outgrow theirs, finish runs the call again one query
+  // tile at a time, each tile with the whole memory.  The call's inputs are
+  // kept for that.
+  bool external = false;
+  bool cont = false;                 // a continuation tile is running
+  const float* q_in = nullptr;       // the call's queries (borrowed until finish)
+  std::vector<double> rho_in;        // the call's thresholds
+  int user_fmt = 0;
+  unsigned char* ext_mem = nullptr;
+  size_t ext_bytes = 0;
+  int64_t ext_pairs = 0;
+  int ext_max_queries = 0;           // the external workspace's call limit
+  int64_t ext_epoch = 0;             // rows the call sees (kept by its continuation)
+  int continued_tiles = 0;           // tiles the last call ran one by one
+  bool cont_again = false;           // a continued call ended in a result overflow
+  int64_t last_max_entries = 0;      // largest frontier level of the last call
+  int64_t last_results = 0;
   int nt_alloc = 0;
   int nq_alloc = 0;
   uint32_t* fr_node[2] = {nullptr, nullptr};

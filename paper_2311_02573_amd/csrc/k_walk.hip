@@ -74,7 +74,7 @@ __device__ __forceinline__ void mma16<GT_POOL_F32>(const uint4& a, const uint4& 
 // pool of the bucket (1 << shift of them) for the tile's queries.
 __device__ __forceinline__ void slot_prefix(uint32_t* pre, int n, int slot0, int nt, int dense,
                                             int shift, const uint64_t* tile_mask,
-                                            const uint32_t* counts) {
+                                            const uint32_t* counts, uint32_t cap) {
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     const int per_lane = (n + 63) / 64;
@@ -87,7 +87,7 @@ __device__ __forceinline__ void slot_prefix(uint32_t* pre, int n, int slot0, int
       uint32_t c = 0;
       if (i < per_lane && sl < n) {
         const int gs = slot0 + sl;
-        c = dense ? (tile_mask[gs % nt] ? (1u << shift) : 0u) : counts[gs];
+        c = dense ? (tile_mask[gs % nt] ? (1u << shift) : 0u) : min(counts[gs], cap);
       }
       loc[i] = sum;
       sum += c;
@@ -215,7 +215,8 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
     if (wave == 0) {  // groups of this workgroup's share of each bucket (R <= 16)
       uint32_t ng = 0, lo = 0, hi = 0;
       if (lane < R && tmask) {
-        const uint32_t n = a.dense ? (1u << bshift) : a.in_count[(size_t)(x * R + lane) * a.nt + t];
+        const uint32_t n = a.dense ? (1u << bshift)
+                                   : min(a.in_count[(size_t)(x * R + lane) * a.nt + t], (uint32_t)a.bcap);
         lo = (uint32_t)(((uint64_t)n * m) / c);
         hi = (uint32_t)(((uint64_t)n * (m + 1)) / c);
         ng = (hi - lo + kGroupEntries - 1) / kGroupEntries;
@@ -411,9 +412,13 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
             pend_base = __shfl(pend_base, 0, 64);
             if (lane < 32 && pend_mask) {
               const uint32_t pos = pend_base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
-              const size_t o = (size_t)pend_slot * a.bcap + pos;
-              a.out_node[o] = pend_child;
-              a.out_mask[o] = pend_mask;
+              if (pos < a.bcap) {
+                const size_t o = (size_t)pend_slot * a.bcap + pos;
+                a.out_node[o] = pend_child;
+                a.out_mask[o] = pend_mask;
+              } else {
+                atomicOr(a.over, 1u);
+              }
             }
             pend = false;
           }
@@ -465,9 +470,13 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
       base = __shfl(base, 0, 64);
       if (lane < 32 && pend_mask) {
         const uint32_t pos = base + (uint32_t)__popcll(pend_bal & ((1ull << lane) - 1ull));
-        const size_t o = (size_t)pend_slot * a.bcap + pos;
-        a.out_node[o] = pend_child;
-        a.out_mask[o] = pend_mask;
+        if (pos < a.bcap) {
+          const size_t o = (size_t)pend_slot * a.bcap + pos;
+          a.out_node[o] = pend_child;
+          a.out_mask[o] = pend_mask;
+        } else {
+          atomicOr(a.over, 1u);
+        }
       }
     }
   }
@@ -532,7 +541,8 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_wide(WalkLevelArgs a) 
     if (wave == 0) {
       uint32_t ng = 0, lo = 0, hi = 0;
       if (lane < R && tmask) {
-        const uint32_t n = a.dense ? (1u << bshift) : a.in_count[(size_t)(x * R + lane) * a.nt + t];
+        const uint32_t n = a.dense ? (1u << bshift)
+                                   : min(a.in_count[(size_t)(x * R + lane) * a.nt + t], (uint32_t)a.bcap);
         lo = (uint32_t)(((uint64_t)n * m) / c);
         hi = (uint32_t)(((uint64_t)n * (m + 1)) / c);
         ng = (hi - lo + kGroupEntries - 1) / kGroupEntries;
@@ -698,9 +708,13 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_wide(WalkLevelArgs a) 
       obase = __shfl(obase, 0, 64);
       if (mine) {
         const uint32_t pos = obase + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-        const size_t o = (size_t)slot * a.bcap + pos;
-        a.out_node[o] = 2u * (lane < 16 ? p0 : p1) + (uint32_t)(lane & 1);
-        a.out_mask[o] = mine;
+        if (pos < a.bcap) {
+          const size_t o = (size_t)slot * a.bcap + pos;
+          a.out_node[o] = 2u * (lane < 16 ? p0 : p1) + (uint32_t)(lane & 1);
+          a.out_mask[o] = mine;
+        } else {
+          atomicOr(a.over, 1u);
+        }
       }
     }
   }
@@ -792,7 +806,7 @@ __global__ __launch_bounds__(kSubThreads, 1) void k_walk_sub(WalkLevelArgs a) {
     if (wave == 0) {
       uint32_t ng = 0, lo = 0, hi = 0;
       if (lane < R && tmask) {
-        const uint32_t n = a.in_count[(size_t)(x * R + lane) * a.nt + t];
+        const uint32_t n = min(a.in_count[(size_t)(x * R + lane) * a.nt + t], (uint32_t)a.bcap);
         lo = (uint32_t)(((uint64_t)n * m) / c);
         hi = (uint32_t)(((uint64_t)n * (m + 1)) / c);
         ng = (hi - lo + kSubGroup - 1) / kSubGroup;
@@ -1010,9 +1024,13 @@ __global__ __launch_bounds__(kSubThreads, 1) void k_walk_sub(WalkLevelArgs a) {
       base = __shfl(base, 0, 64);
       const uint32_t opos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
       if (out_m) {
-        const size_t o = (size_t)slot * a.bcap + opos;
-        a.out_node[o] = 2u * p + (lane < 32 ? 1u : 0u);
-        a.out_mask[o] = out_m;
+        if (opos < a.bcap) {
+          const size_t o = (size_t)slot * a.bcap + opos;
+          a.out_node[o] = 2u * p + (lane < 32 ? 1u : 0u);
+          a.out_mask[o] = out_m;
+        } else {
+          atomicOr(a.over, 1u);
+        }
       }
       if (!a.out_rec) continue;
 #pragma unroll
@@ -1033,10 +1051,10 @@ __global__ __launch_bounds__(kSubThreads, 1) void k_walk_sub(WalkLevelArgs a) {
             vr[qb] = bf16_ceil_hi(score_upper(sr, aup));
             vl[qb] = bf16_ceil_hi(left_ub(rec_of(rb, i, qb), sr, sabs_lds[q], sub));
           }
-          if (keep_r)
+          if (keep_r && or_ < a.bcap)
             *reinterpret_cast<uint2*>(a.out_rec + ((size_t)slot * a.bcap + or_) * TQ + 4 * c16) =
                 make_uint2((vr[0] >> 16) | vr[1], (vr[2] >> 16) | vr[3]);
-          if (keep_l)
+          if (keep_l && ol_ < a.bcap)
             *reinterpret_cast<uint2*>(a.out_rec + ((size_t)slot * a.bcap + ol_) * TQ + 4 * c16) =
                 make_uint2((vl[0] >> 16) | vl[1], (vl[2] >> 16) | vl[3]);
         }
@@ -1199,18 +1217,26 @@ __device__ __forceinline__ void dense_block_out(const DenseLevelArgs& a, const f
     base = __shfl(base, 0, 64);
     if (rv && mine) {
       const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
-      const size_t o = (size_t)slot * a.bcap + pos;
-      a.out_node[o] = (uint32_t)row;
-      a.out_mask[o] = mine;
-      oe = (int64_t)o;
+      if (pos < a.bcap) {
+        const size_t o = (size_t)slot * a.bcap + pos;
+        a.out_node[o] = (uint32_t)row;
+        a.out_mask[o] = mine;
+        oe = (int64_t)o;
+      } else {
+        atomicOr(a.over, 1u);
+      }
     }
   } else if (eb && rv && mine) {
     const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
     const uint32_t pos = atomicAdd(&a.out_count[slot], 1u);
-    const size_t o = (size_t)slot * a.bcap + pos;
-    a.out_node[o] = (uint32_t)row;
-    a.out_mask[o] = mine;
-    oe = (int64_t)o;
+    if (pos < a.bcap) {
+      const size_t o = (size_t)slot * a.bcap + pos;
+      a.out_node[o] = (uint32_t)row;
+      a.out_mask[o] = mine;
+      oe = (int64_t)o;
+    } else {
+      atomicOr(a.over, 1u);
+    }
   }
   if (FMT == GT_POOL_BF16 && a.out_rec && eb) {
     // score record of every kept pool: upper bounds of its real score for
@@ -1427,7 +1453,8 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
   if (x >= xs) return;
   const int nsl = (nbk / xs) * a.nt;
   const int slot0 = x * nsl;
-  slot_prefix(epre, nsl, slot0, a.nt, a.dense, a.level - a.nb, a.tile_mask, a.in_count);
+  slot_prefix(epre, nsl, slot0, a.nt, a.dense, a.level - a.nb, a.tile_mask, a.in_count,
+              (uint32_t)a.bcap);
   const uint32_t etot = epre[nsl];
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t wgs = gridDim.x / kXcds;

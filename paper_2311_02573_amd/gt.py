@@ -28,7 +28,8 @@ POOLS = {"f32": POOL_F32, "bf16": POOL_BF16, "fp8": POOL_FP8,
 GT_MAX_LEVELS = 40
 
 EXPORTS = ["gt_build_tree", "gt_insert", "gt_query_batch", "gt_query_batch_noalloc",
-           "gt_exhaustive", "gt_batch_create",
+           "gt_exhaustive", "gt_call_bytes", "gt_batch_create_external",
+           "gt_batch_submit_external", "gt_batch_info", "gt_batch_create",
            "gt_batch_submit", "gt_batch_poll", "gt_batch_finish", "gt_batch_destroy",
            "gt_get_stats", "gt_read_pools", "gt_set_option", "gt_destroy", "gt_last_error"]
 
@@ -81,6 +82,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                            ctypes.POINTER(i64), vp]
     lib.gt_exhaustive.restype = st
     lib.gt_exhaustive.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, ctypes.POINTER(i64), vp]
+    lib.gt_call_bytes.restype = st
+    lib.gt_call_bytes.argtypes = [vp, i32, ctypes.c_int, i64, i64, ctypes.POINTER(i64),
+                                  ctypes.POINTER(i64)]
+    lib.gt_batch_create_external.restype = st
+    lib.gt_batch_create_external.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.gt_batch_submit_external.restype = st
+    lib.gt_batch_submit_external.argtypes = [vp, vp, i32, vp, ctypes.c_int, vp, i64, i64, vp]
+    lib.gt_batch_info.restype = st
+    lib.gt_batch_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                  ctypes.POINTER(i32)]
     lib.gt_batch_create.restype = st
     lib.gt_batch_create.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.gt_batch_submit.restype = st
@@ -328,3 +339,55 @@ class Workspace:
         res = Results(offsets, ids, sims, total.value)
         self._q = None
         return res
+
+
+def call_bytes(index: "GTIndex", nq: int, pool: str = "bf16", frontier_entries: int = 0,
+               pairs: int = 0):
+    """(bytes, least bytes) of device memory for a call of nq queries given to
+    ExternalWorkspace.submit with room for frontier_entries entries per level
+    and `pairs` candidates (gt_call_bytes)."""
+    b, m = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().gt_call_bytes(index.handle, nq, POOLS[pool], int(frontier_entries), int(pairs),
+                               ctypes.byref(b), ctypes.byref(m)))
+    return b.value, m.value
+
+
+class ExternalWorkspace(Workspace):
+    """A workspace whose device memory each call brings (gt_batch_create_external):
+    submit(q, rho, pool, mem_ptr, mem_bytes, pairs) carves the call's buffers
+    out of [mem_ptr, mem_ptr + mem_bytes), which the caller keeps reserved
+    until finish() returns."""
+
+    def __init__(self, index: "GTIndex", max_queries: int, stream=None):
+        self.index = index
+        self.max_queries = max_queries
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = ctypes.c_void_p()
+        _check(lib().gt_batch_create_external(index.handle, max_queries, ctypes.byref(h)))
+        self._h = h
+        self._q = None
+        self._rho = None
+        self._max_results = 1 << 16
+
+    def submit(self, q: torch.Tensor, rho, pool: str = "bf16", mem_ptr: int = 0, mem_bytes: int = 0,
+               pairs: int = 0):
+        q = q.contiguous()
+        if q.dtype != torch.float32 or not q.is_cuda:
+            raise ValueError("queries must be a float32 device tensor")
+        nq = q.shape[0]
+        self._rho = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, dtype=np.float64), (nq,)))
+        self._q = q  # read again by a continuation: kept until finish
+        self._pool = pool
+        self.stream.wait_stream(torch.cuda.current_stream())
+        _check(lib().gt_batch_submit_external(self._h, ctypes.c_void_p(q.data_ptr()), nq,
+                                              ctypes.c_void_p(self._rho.ctypes.data), POOLS[pool],
+                                              ctypes.c_void_p(mem_ptr), int(mem_bytes), int(pairs),
+                                              ctypes.c_void_p(self.stream.cuda_stream)))
+        self._nq = nq
+
+    def info(self) -> dict:
+        """Of the last finished call: largest frontier level, results, tiles
+        that ran one by one."""
+        e, r, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+        _check(lib().gt_batch_info(self._h, ctypes.byref(e), ctypes.byref(r), ctypes.byref(c)))
+        return {"max_level_entries": e.value, "results": r.value, "continued_tiles": c.value}

@@ -1,5 +1,6 @@
-"""Continuous-batching scheduler, driven on the CPU by a stand-in backend whose
-workspaces answer with the float64 oracle after a few polls."""
+"""Continuous-batching scheduler with admission by memory, driven on the CPU by
+a stand-in backend whose workspaces answer with the float64 oracle after a
+few polls and whose calls cost a known number of bytes."""
 import numpy as np
 import pytest
 
@@ -19,41 +20,68 @@ class FakeWorkspace:
     def __init__(self, backend, max_queries):
         self.b, self.max_queries = backend, max_queries
         self.pending = None
+        self.last = None
 
-    def submit(self, q, rho, pool):
+    def submit(self, q, rho, pool, offset, nbytes, pairs):
         assert self.pending is None, "workspace reused while busy"
         assert len(q) <= self.max_queries
+        assert nbytes >= self.b.call_bytes(len(q), 0, pairs)[1]
         self.b.in_flight += 1
         self.b.peak = max(self.b.peak, self.b.in_flight)
+        self.b.bytes_in_flight += nbytes
+        self.b.peak_bytes = max(self.b.peak_bytes, self.b.bytes_in_flight)
         self.b.calls.append(len(q))
         n = self.b.n
-        self.pending = (np.asarray(q), np.asarray(rho), n, self.b.polls_needed)
+        self.pending = (np.asarray(q), np.asarray(rho), n, self.b.polls_needed, nbytes)
 
     def poll(self):
-        q, rho, n, left = self.pending
+        q, rho, n, left, nb = self.pending
         if left > 0:
-            self.pending = (q, rho, n, left - 1)
+            self.pending = (q, rho, n, left - 1, nb)
             return False
         return True
 
     def finish(self):
-        q, rho, n, _ = self.pending
+        q, rho, n, _, nb = self.pending
         self.pending = None
         self.b.in_flight -= 1
+        self.b.bytes_in_flight -= nb
         res = ob.range_search(self.b.feats[:n], q, rho)
+        self.last = {"max_level_entries": 40 * len(q), "results": sum(len(i) for i, _ in res),
+                     "continued_tiles": 0}
         return _Res([(i, s.astype(np.float32)) for i, s in res])
+
+    def info(self):
+        return self.last
 
 
 class FakeBackend:
+    """Calls cost 4096 + 64 per query + 24 per frontier entry + 36 per pair
+    bytes; the least a call accepts is 4096 + 64 per query + 36 per pair +
+    2048 (one tile's frontier)."""
+
     def __init__(self, feats, polls_needed=2):
         self.feats = feats
         self.n = len(feats)
         self.polls_needed = polls_needed
         self.in_flight = self.peak = 0
+        self.bytes_in_flight = self.peak_bytes = 0
         self.calls = []
+        self.reserved = None
 
-    def workspace(self, max_queries):
+    def reserve(self, nbytes):
+        self.reserved = nbytes
+
+    def slot(self, max_queries):
         return FakeWorkspace(self, max_queries)
+
+    def call_bytes(self, nq, entries, pairs):
+        base = 4096 + 64 * nq + 36 * pairs
+        return base + 24 * max(entries, 0) + 2048, base + 2048
+
+    def submit(self, ws, q, rho, pool, offset, nbytes, pairs):
+        assert 0 <= offset and offset + nbytes <= self.reserved
+        ws.submit(q, rho, pool, offset, nbytes, pairs)
 
     def concat(self, parts):
         return np.concatenate(parts, 0)
@@ -71,7 +99,7 @@ def _workload():
 def test_every_request_gets_its_own_results_in_order():
     F, Q = _workload()
     be = FakeBackend(F)
-    srv = serve.Server(be, n_workspaces=3, max_queries=40)
+    srv = serve.Server(be, 1 << 30, streams=3, max_queries=40)
     sizes = [1, 7, 13, 40, 2, 25, 9, 31, 5, 17, 3, 38]
     off, reqs = 0, []
     for i, k in enumerate(sizes):
@@ -98,7 +126,7 @@ def test_every_request_gets_its_own_results_in_order():
 def test_requests_admitted_while_others_run():
     F, Q = _workload()
     be = FakeBackend(F, polls_needed=5)
-    srv = serve.Server(be, n_workspaces=2, max_queries=16)
+    srv = serve.Server(be, 1 << 30, streams=2, max_queries=16)
     r0 = serve.Request(0, Q[:16], np.full(16, 0.9), arrival=srv.now())
     srv.submit(r0)
     srv.step()
@@ -113,7 +141,7 @@ def test_requests_admitted_while_others_run():
 
 def test_oversized_request_is_rejected():
     F, Q = _workload()
-    srv = serve.Server(FakeBackend(F), n_workspaces=1, max_queries=8)
+    srv = serve.Server(FakeBackend(F), 1 << 30, streams=1, max_queries=8)
     with pytest.raises(ValueError):
         srv.submit(serve.Request(0, Q[:9], np.full(9, 0.9), arrival=0.0))
 
@@ -121,7 +149,7 @@ def test_oversized_request_is_rejected():
 def test_inserts_are_visible_to_requests_admitted_after_them():
     F, Q = _workload()
     be = FakeBackend(F[:2000])
-    srv = serve.Server(be, n_workspaces=2, max_queries=64)
+    srv = serve.Server(be, 1 << 30, streams=2, max_queries=64)
     r0 = serve.Request(0, Q[:10], np.full(10, 0.85), arrival=srv.now())
     srv.submit(r0)
     srv.step()
@@ -139,7 +167,7 @@ def test_inserts_are_visible_to_requests_admitted_after_them():
 def test_poisson_driver_and_latency_summary():
     F, Q = _workload()
     be = FakeBackend(F, polls_needed=1)
-    srv = serve.Server(be, n_workspaces=4, max_queries=64)
+    srv = serve.Server(be, 1 << 30, streams=4, max_queries=64)
     sched = synth.poisson_arrivals(0, rate_per_s=400.0, duration_s=0.2, max_batch=16)
     assert len(sched) > 20
     reqs, wall, ins = serve.run_poisson(
@@ -147,3 +175,86 @@ def test_poisson_driver_and_latency_summary():
         lambda i, k: np.full(k, 0.9), duration_s=0.2)
     s = serve.latency_summary(reqs)
     assert s["requests"] == len(sched) and s["p99_ms"] >= s["p50_ms"] >= 0
+
+
+def test_arena_allocates_disjoint_aligned_ranges_and_merges():
+    rng = np.random.default_rng(5)
+    size = 1 << 20
+    a = serve.Arena(size)
+    live = {}
+    for step in range(2000):
+        if live and (rng.random() < 0.45 or len(live) > 40):
+            off = list(live)[rng.integers(len(live))]
+            a.release(off, live.pop(off))
+        else:
+            n = int(rng.integers(1, 60000))
+            off = a.alloc(n)
+            if off is None:
+                continue
+            assert off % 256 == 0 and off + n <= size
+            for o, m in live.items():      # no overlap with a live range
+                assert off + n <= o or o + m <= off
+            live[off] = n
+        assert a.used == sum(serve.Arena._round(m) for m in live.values())
+    for off in list(live):
+        a.release(off, live.pop(off))
+    assert a.free == [(0, size)] and a.used == 0
+
+
+def test_memory_budget_forces_queueing():
+    """A budget that holds one call of 16 queries at a time: with three streams
+    free, the second and third calls still wait until the first returns its
+    memory; every request gets the oracle's result."""
+    F, Q = _workload()
+    be = FakeBackend(F, polls_needed=3)
+    est = serve.Estimator(entries_per_query=100, pairs_per_query=10, margin=1.0)
+    one = be.call_bytes(16, est.frontier(16), est.pairs(16))[0]
+    srv = serve.Server(be, int(one * 1.5), streams=3, max_queries=16, estimator=est)
+    reqs = []
+    for i in range(6):
+        r = serve.Request(i, Q[16 * i:16 * i + 16], np.full(16, 0.9), arrival=srv.now())
+        srv.submit(r)
+        reqs.append(r)
+    srv.step()
+    assert be.in_flight == 1 and len(srv.waiting) == 5
+    srv.drain(timeout_s=30)
+    assert be.peak == 1 and srv.memory_waits > 0
+    assert be.peak_bytes <= int(one * 1.5) and srv.arena.used == 0
+    for r in reqs:
+        want = ob.range_search(F, r.queries, r.rho)
+        for (gi, _), (wi, _) in zip(r.results, want):
+            np.testing.assert_array_equal(gi, wi)
+
+
+def test_group_is_cut_back_to_what_fits():
+    """Waiting requests of 4 queries each: a full pack of 64 queries would not
+    fit the budget, so the call takes as many requests as fit."""
+    F, Q = _workload()
+    be = FakeBackend(F, polls_needed=2)
+    est = serve.Estimator(entries_per_query=100, pairs_per_query=10, margin=1.0)
+    fit = be.call_bytes(24, est.frontier(24), est.pairs(24))[0]
+    srv = serve.Server(be, fit + 100, streams=2, max_queries=64, estimator=est)
+    for i in range(16):
+        srv.submit(serve.Request(i, Q[4 * i:4 * i + 4], np.full(4, 0.9), arrival=srv.now()))
+    srv.step()
+    assert be.calls == [24]
+    srv.drain(timeout_s=30)
+    assert sum(be.calls) == 64 and max(be.calls) <= 24
+
+
+def test_request_that_never_fits_is_refused():
+    F, Q = _workload()
+    be = FakeBackend(F)
+    srv = serve.Server(be, 5000, streams=1, max_queries=64)
+    srv.submit(serve.Request(0, Q[:40], np.full(40, 0.9), arrival=0.0))
+    with pytest.raises(MemoryError):
+        srv.step()
+
+
+def test_estimator_follows_measured_calls():
+    est = serve.Estimator(entries_per_query=10, pairs_per_query=10, margin=2.0)
+    est.observe(100, 5000, 300)          # larger: taken at once
+    assert est.entries == 50 and est.pairs_q == 10 * 0.9 + 3 * 0.1
+    est.observe(100, 1000, 3000)         # smaller entries decay slowly
+    assert est.entries == 0.9 * 50 + 0.1 * 10 and est.pairs_q == 30
+    assert est.frontier(10) == int(np.ceil(10 * est.entries * 2.0))
