@@ -210,13 +210,13 @@ def main():
                          "one stream each")
     ap.add_argument("--sweep-subtract", action="store_true",
                     help="also time the walk with each subtraction setting")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of each loaded serving run (0: no serving leg)")
     ap.add_argument("--nq-variant", type=int, default=4096,
                     help="batch size of the bfloat16 / float8 precision variant (0: skip it)")
-    ap.add_argument("--leg", default="all", choices=["all", "exh"],
+    ap.add_argument("--leg", default="all", choices=["all", "exh", "serve"],
                     help="exh: only the exhaustive GEMM path on the headline batch, for "
-                         "counter profiles of its kernel")
+                         "counter profiles of its kernel; serve: only the serving legs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU (the library has no multi-GPU path); use --gpus 1",
@@ -231,6 +231,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.leg == "serve":
+        out = {"serving": serving_leg(args.serve_seconds, torch, gt, synth, dev),
+               "serving_stress": stress_serving_leg(args.serve_seconds, torch, gt, synth, dev)}
+        print(json.dumps(out), flush=True)
+        return
 
     t0 = time.time()
     # one database for the 1024- and the 4096-query batches (neighbours are
@@ -543,6 +548,7 @@ def main():
         torch.cuda.empty_cache()
     if args.serve_seconds > 0:
         out["serving"] = serving_leg(args.serve_seconds, torch, gt, synth, dev)
+        out["serving_stress"] = stress_serving_leg(args.serve_seconds, torch, gt, synth, dev)
     print(json.dumps(out), flush=True)
     if args.copy_calib:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -642,12 +648,59 @@ def signed_leg(args, torch, gt, synth, dev):
     return out
 
 
+def _serve_runs(srv_factory, make_q, rho_of, max_batch, seconds, loads, seed_workload,
+                insert_rows=None, saturated_requests=400):
+    """Saturated rate (a backlog of requests present at t = 0), then a Poisson
+    run of `seconds` at each offered load (a fraction of the saturated rate),
+    with inserts every 10 ms if insert_rows is given."""
+    from paper_2311_02573_amd import serve, synth
+
+    sched = [(0.0, k) for _, k in synth.poisson_arrivals(seed_workload, float(saturated_requests),
+                                                         1.0, max_batch, seed_offset=1)]
+    srv = srv_factory()
+    reqs, wall, _ = serve.run_poisson(srv, sched, make_q, rho_of, 0.0)
+    sat = sum(r.nq for r in reqs) / wall
+    out = {"saturated_qps": round(sat, 1), "saturated_memory": srv.summary()}
+    log(f"serving: saturated {sat:.0f} queries/s ({len(reqs)} requests in {wall:.2f}s), "
+        f"{srv.summary()}")
+    mean_batch = (max_batch + 1) / 2.0
+    for load in loads:
+        rate = load * sat / mean_batch
+        sched = synth.poisson_arrivals(seed_workload, rate, seconds, max_batch,
+                                       seed_offset=int(load * 10))
+        srv = srv_factory()
+        n_ins = [0]
+
+        def ins(k):
+            rows = insert_rows(k)
+            n_ins[0] += len(rows)
+            return rows
+
+        reqs, wall, _ = serve.run_poisson(
+            srv, sched, make_q, rho_of, seconds,
+            insert_every_s=0.01 if insert_rows is not None else None,
+            insert_rows=ins if insert_rows is not None else None,
+            progress=lambda t: log(f"  load {load:.0%}: {t:.0f} s"))
+        lat = serve.latency_summary(reqs)
+        nq_tot = sum(r.nq for r in reqs)
+        out[f"load_{int(load * 100)}"] = dict(
+            seconds=round(wall, 1), offered_qps=round(load * sat, 1),
+            achieved_qps=round(nq_tot / wall, 1), inserted_rows=n_ins[0],
+            inserts_per_s=round(n_ins[0] / wall, 1), memory=srv.summary(), **lat)
+        log(f"serving at {load:.0%}: {lat}, {n_ins[0]} rows inserted, {srv.summary()}")
+    return out, srv
+
+
 def serving_leg(seconds, torch, gt, synth, dev):
-    """Continuous batching under load: N0 = 2^22 float16 rows, d = 512, requests
-    of U{1..512} queries at rho = 0.9 arriving as a Poisson process, 10,000
-    inserted rows per second in groups of 100 every 10 ms.  The saturated rate
-    is measured first (every request waiting at t = 0); loaded runs offer 50%
-    and 80% of it.  Latency = completion - arrival, host clock."""
+    """Continuous batching with admission by memory under load.
+
+    Serving workload: N0 = 2^22 float16 rows, d = 512, capacity 2^23,
+    requests of U{1..512} queries at rho = 0.9 arriving as a Poisson process,
+    10,000 inserted rows per second in groups of 100 every 10 ms; an 8 GiB
+    arena for the calls' memory, four streams, calls of up to 1024 queries.
+    The saturated rate is measured first (every request waiting at t = 0);
+    loaded runs offer 50% and 80% of it.  Latency = completion - arrival, host
+    clock."""
     from paper_2311_02573_amd import serve
 
     t0 = time.time()
@@ -699,41 +752,77 @@ def serving_leg(seconds, torch, gt, synth, dev):
     nqp = qpool.shape[0]
     make_q = lambda i, k: qpool[(i * 613) % (nqp - 512):(i * 613) % (nqp - 512) + k]
     rho_of = lambda i, k: np.full(k, w.rho[0])
-    n_ins = [0]
+    ins_rows = lambda k: torch.from_numpy(synth.insert_rows(3, 100, w.d, w.temp, offset=k)).to(
+        dev, torch.float16)
+    budget = 8 << 30
+    est = serve.Estimator()
 
-    def ins_rows(k):
-        rows = synth.insert_rows(3, 100, w.d, w.temp, offset=k)
-        n_ins[0] += 100
-        return torch.from_numpy(rows).to(dev, torch.float16)
+    def factory():
+        return serve.Server(backend, budget, streams=4, max_queries=1024, pool="bf16", estimator=est)
 
-    def server():
-        return serve.Server(backend, n_workspaces=4, max_queries=1024, pool="bf16")
-
-    # saturated: a backlog of requests, all present at t = 0
-    sched = [(0.0, k) for _, k in synth.poisson_arrivals(3, 400.0, 1.0, 512, seed_offset=1)]
-    srv = server()
-    reqs, wall, _ = serve.run_poisson(srv, sched, make_q, rho_of, 0.0)
-    sat_qps = sum(r.nq for r in reqs) / wall
-    log(f"serving: saturated {sat_qps:.0f} queries/s ({len(reqs)} requests in {wall:.2f}s)")
+    runs, srv = _serve_runs(factory, make_q, rho_of, 512, seconds, (0.5, 0.8), 3, ins_rows)
     out = {"workload": f"N0={w.n} d={w.d} float16, capacity {w.capacity}, bf16 pools, "
                        "requests U{1..512} queries at rho=0.9, Poisson arrivals, "
                        "inserts 10000/s in groups of 100",
-           "saturated_qps": round(sat_qps, 1), "workspaces": 4, "max_queries_per_call": 1024,
-           "call_1024_queries": call, "inserts": inserts}
-    for load in (0.5, 0.8):
-        rate = load * sat_qps / 256.5          # requests/s (mean request 256.5 queries)
-        sched = synth.poisson_arrivals(3, rate, seconds, 512, seed_offset=int(load * 10))
-        n_ins[0] = 0
-        srv = server()
-        reqs, wall, k_ins = serve.run_poisson(srv, sched, make_q, rho_of, seconds,
-                                              insert_every_s=0.01, insert_rows=ins_rows)
-        lat = serve.latency_summary(reqs)
-        nq_tot = sum(r.nq for r in reqs)
-        out[f"load_{int(load * 100)}"] = dict(
-            offered_qps=round(load * sat_qps, 1), achieved_qps=round(nq_tot / wall, 1),
-            inserted_rows=n_ins[0], inserts_per_s=round(n_ins[0] / wall, 1), **lat)
-        log(f"serving at {load:.0%}: {lat}, {n_ins[0]} rows inserted")
+           "admission": f"by memory: {budget >> 30} GiB arena, 4 streams, calls of up to 1024 queries",
+           "call_1024_queries": call, "inserts": inserts, **runs}
+    del srv, backend
     idx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def stress_serving_leg(seconds, torch, gt, synth, dev):
+    """Continuous batching on the stress workload: N = 2^24 rows softmax(z/0.3)
+    stored as bfloat16, d = 256; 64 centres with 10^4 near-duplicates each
+    (logit noise sigma 0.02) written over uniformly chosen rows; a pool of
+    8192 queries of which 10% are a centre plus the same noise (about 10^4
+    neighbours each); requests of U{1..2048} queries, each request with its
+    own rho uniform in [0.75, 0.95]; admission by memory from a 48 GiB arena,
+    four streams, calls of up to 2048 queries.  Saturated rate, then a
+    Poisson run at 80% of it; a sample of requests is compared with the
+    same queries run alone."""
+    from paper_2311_02573_amd import serve
+
+    t0 = time.time()
+    w = synth.workload4(n=1 << 24, d=256, nq=8192, clusters=64, per_cluster=10000)
+    feats = w.feats.to(dev)
+    qpool = torch.from_numpy(w.queries).to(dev)
+    idx = gt.GTIndex(feats, pools=("f32", "bf16"))
+    torch.cuda.synchronize()
+    del feats
+    log(f"stress index: N={w.n} d={w.d} bf16, built in {time.time() - t0:.1f}s (incl. generation)")
+    g = np.random.default_rng(synth.stream_seed(4, synth.STREAM_ARRIVAL) + 7)
+    backend = serve.GpuBackend(idx)
+    nqp = qpool.shape[0]
+    # queries in pool order, so every request mixes cluster and plain queries
+    # as the pool does (cluster queries are its first 10%, spread by a stride)
+    perm = torch.from_numpy(g.permutation(nqp)).to(dev)
+    qperm = qpool[perm]
+    make_q = lambda i, k: qperm[(i * 1031) % (nqp - 2048):(i * 1031) % (nqp - 2048) + k]
+    rho_req = g.uniform(0.75, 0.95, size=1 << 16)
+    rho_of = lambda i, k: np.full(k, rho_req[i % len(rho_req)])
+    budget = 48 << 30
+    est = serve.Estimator()
+
+    def factory():
+        return serve.Server(backend, budget, streams=4, max_queries=2048, pool="bf16", estimator=est)
+
+    runs, srv = _serve_runs(factory, make_q, rho_of, 2048, seconds, (0.8,), 4,
+                            saturated_requests=60)
+    # a sample of the last run's requests against the same queries alone
+    same = True
+    for r in srv.finished[:: max(1, len(srv.finished) // 6)][:6]:
+        alone = idx.query(r.queries, r.rho, pool="bf16").to_lists()
+        same = same and all(np.array_equal(a[0], b[0]) for a, b in zip(r.results, alone))
+    out = {"workload": f"softmax(z/0.3) N={w.n} d={w.d} bfloat16, 64 centres x 10^4 "
+                       "near-duplicates (sigma 0.02), 10% cluster queries, requests U{1..2048} "
+                       "queries, per-request rho U[0.75, 0.95]",
+           "admission": f"by memory: {budget >> 30} GiB arena, 4 streams, calls of up to 2048 queries",
+           "mix_equals_alone_sample": bool(same), **runs}
+    del srv, backend
+    idx.close()
+    torch.cuda.empty_cache()
     return out
 
 

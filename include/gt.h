@@ -251,8 +251,9 @@ void gt_batch_destroy(gt_batch* batch);
  *
  * gt_call_bytes  device bytes for a call of nq queries in format fmt with room
  *                for frontier_entries entries per frontier level (all tiles
- *                together; 0 = the least) and `pairs` leaf candidates and
- *                results (at least 1024).  *min_bytes_out (may be NULL): the
+ *                together, spread over the subtrees that hold rows; 0 = the
+ *                least) and `pairs` leaf candidates and results (at least
+ *                1024).  *min_bytes_out (may be NULL): the
  *                least memory any such call accepts.  bf16 sum-pool calls
  *                with a dense step keep 280 bytes per frontier entry
  *                (subtraction-step score records), others 24.

@@ -315,10 +315,12 @@ gt_status batch_reserve(Batch* b, int nq_pad, int nt) {
 
 gt_status grow_hits(Batch* b, int64_t need) {
   Index* ix = b->ix;
-  if (b->fixed)
+  if (b->fixed) {
+    b->hits_overflowed = true;
     return fail(GT_ERR_CAPACITY, "the call's " + std::to_string(need) +
                                      " leaf candidates exceed the fixed scratch (room for " +
                                      std::to_string(b->hit_cap) + "); use fewer queries per call");
+  }
   dfree(ix, &b->hits, (size_t)b->hit_cap);
   dfree(ix, &b->band_idx, (size_t)b->hit_cap);
   b->hit_cap = 0;
@@ -813,6 +815,19 @@ gt_status carve_budget(Index* ix, Batch* b, void* base, size_t bytes, int nq, in
   const CallShape c = call_shape(ix, nq, fmt);
   bool ok = true;
   carve_common(ix, b, base, bytes, nq, c, ok);
+  if (pairs < 0) {
+    // continuation: the worst-case frontier of the call's tiles, without
+    // records, and every remaining byte for candidates and results
+    const int64_t worst = int64_t(1) << std::max(0, ix->depth - 1);
+    carve_frontier(b, c.nt, worst, false, ok);
+    const size_t left = ok ? bytes - b->arena_used : 0;
+    const size_t np = left > 8 * 256 ? (left - 8 * 256) / kPerPair : 0;
+    if (!ok || np < 1024)
+      return fail(GT_ERR_CAPACITY, "the call's memory does not hold one tile's worst case");
+    carve_pairs(b, np, ok);
+    if (!ok) return fail(GT_ERR_CAPACITY, "continuation carve failed");
+    return GT_OK;
+  }
   carve_pairs(b, (size_t)std::max<int64_t>(pairs, 1024), ok);
   if (!ok) return fail(GT_ERR_CAPACITY, "the call's memory does not hold its query and candidate buffers");
   const bool rec = allow_rec && c.want_rec;
@@ -922,8 +937,10 @@ gt_status submit(Index* ix, Batch* b, int kind, const float* q, int nq, const do
       TRY(enqueue_walk(ix, b));
       ev_mark(b, 2);
       TRY(enqueue_leaf(ix, b));
-      if (ix->dense_last == -2 && b->dense_last >= 0)
-        HIPCHK(gt::launch_level_entries(b->lvl_count, b->dense_last, ix->depth, b->ctr, s));
+      // entries of every walked level (the automatic dense level and the
+      // memory estimates of a server read them)
+      HIPCHK(gt::launch_level_entries(b->lvl_count, b->dense_last >= 0 ? b->dense_last : b->head,
+                                      ix->depth, b->ctr, s));
     } else {
       TRY(enqueue_exhaustive(ix, b));
       ev_mark(b, 2);
@@ -1041,55 +1058,66 @@ gt_status finish(Index* ix, Batch* b, int64_t max_results, int64_t* offsets, int
 
 // An external workspace's call whose frontier (or candidates) outgrew its
 // memory: the same call again, one query tile at a time, each tile with the
-// whole memory (enough for one tile's worst case, checked at submit) and
-// without score records.  A query's result does not depend on the other
-// queries of its call, so the results are those of the call; each tile's
-// results go straight to the caller's buffers after the previous tiles', and
-// its offsets are shifted by the results before it.
+// worst-case frontier of one tile (the submit checked that it fits) and every
+// other byte for candidates; a tile whose candidates still do not fit runs
+// query by query.  A query's result does not depend on the other queries of
+// its call, so the results are those of the call; each part's results go
+// straight to the caller's buffers after the earlier parts', and its offsets
+// are shifted by the results before it.
 gt_status continue_by_tiles(Index* ix, Batch* b, int64_t max_results, int64_t* offsets,
                             int64_t* ids, float* sims, int64_t* total_out, bool keep_on_overflow) {
-  const int tq = tq_of(call_shape(ix, 1, b->user_fmt).wf);
+  const int tq = call_shape(ix, 1, b->user_fmt).tq;
   const int nq = (int)b->rho_in.size();
-  const int nt = std::max(1, (nq + tq - 1) / tq);
   const hipStream_t s = b->stream;
   const std::vector<double> rho = b->rho_in;
+  std::vector<std::pair<int, int>> work;  // query ranges [first, first + count), in order
+  for (int a = 0; a < nq; a += tq) work.emplace_back(a, std::min(tq, nq - a));
   std::vector<int64_t> hoff((size_t)tq + 1);
-  int64_t total = 0, max_entries = 0;
+  int64_t total = 0;
+  unsigned long long level_sum[GT_MAX_LEVELS] = {};
   bool over = false;
   b->cont = true;
   b->cont_again = false;
-  b->continued_tiles = nt;
+  b->continued_tiles = (int)work.size();
   gt_status st = GT_OK;
-  for (int t = 0; t < nt && st == GT_OK; ++t) {
-    const int nq_t = std::min(tq, nq - t * tq);
+  for (size_t w = 0; w < work.size() && st == GT_OK; ++w) {
+    const int a = work[w].first, n = work[w].second;
     const int64_t room = max_results > total ? max_results - total : 0;
     int64_t* ids_t = room > 0 ? ids + total : nullptr;
     float* sims_t = room > 0 ? sims + total : nullptr;
     int64_t tot_t = 0;
-    st = carve_budget(ix, b, b->ext_mem, b->ext_bytes, nq_t, b->user_fmt, b->ext_pairs, false);
+    b->hits_overflowed = false;
+    st = carve_budget(ix, b, b->ext_mem, b->ext_bytes, n, b->user_fmt, -1, false);
     if (st == GT_OK) {
       set_targets(b, room, ids_t, sims_t);
-      st = submit(ix, b, 1, b->q_in + (size_t)t * tq * ix->d, nq_t, rho.data() + (size_t)t * tq,
-                  b->user_fmt, s);
+      st = submit(ix, b, 1, b->q_in + (size_t)a * ix->d, n, rho.data() + a, b->user_fmt, s);
     }
-    if (st == GT_OK) st = finish(ix, b, room, offsets + (size_t)t * tq, ids_t, sims_t, &tot_t, false);
+    if (st == GT_OK) st = finish(ix, b, room, offsets + a, ids_t, sims_t, &tot_t, false);
+    if (st == GT_ERR_CAPACITY && b->hits_overflowed && n > 1) {
+      // too many candidates for one tile: its queries one by one
+      std::vector<std::pair<int, int>> singles;
+      for (int k = 0; k < n; ++k) singles.emplace_back(a + k, 1);
+      work.insert(work.begin() + (long)w + 1, singles.begin(), singles.end());
+      st = GT_OK;
+      continue;
+    }
     if (st == GT_ERR_RESULT_OVERFLOW) {
       over = true;
       st = GT_OK;
     }
     if (st != GT_OK) break;
-    max_entries = std::max(max_entries, b->last_max_entries);
-    // the tile's offsets start at 0: shift them past the earlier tiles' results
-    const hipError_t e1 = hipMemcpyAsync(hoff.data(), offsets + (size_t)t * tq,
-                                         (size_t)(nq_t + 1) * 8, hipMemcpyDeviceToHost, s);
+    for (int l = 0; l < GT_MAX_LEVELS; ++l) level_sum[l] += b->h_ctr->entries[l];
+    // the part's offsets start at 0: shift them past the earlier parts' results
+    const hipError_t e1 = hipMemcpyAsync(hoff.data(), offsets + a, (size_t)(n + 1) * 8,
+                                         hipMemcpyDeviceToHost, s);
     const hipError_t e2 = e1 == hipSuccess ? hipStreamSynchronize(s) : e1;
     if (e2 != hipSuccess) {
       st = fail(GT_ERR_DEVICE, std::string("continuation offsets: ") + hipGetErrorString(e2));
       break;
     }
-    for (int k = 0; k <= nq_t; ++k) hoff[k] += total;
-    const hipError_t e3 = hipMemcpyAsync(offsets + (size_t)t * tq, hoff.data(),
-                                         (size_t)(nq_t + 1) * 8, hipMemcpyHostToDevice, s);
+    for (int k = 0; k <= n; ++k) hoff[k] += total;
+    const hipError_t e3 = hipMemcpyAsync(offsets + a, hoff.data(), (size_t)(n + 1) * 8,
+                                         hipMemcpyHostToDevice, s);
     const hipError_t e4 = e3 == hipSuccess ? hipStreamSynchronize(s) : e3;
     if (e4 != hipSuccess) {
       st = fail(GT_ERR_DEVICE, std::string("continuation offsets: ") + hipGetErrorString(e4));
@@ -1099,12 +1127,15 @@ gt_status continue_by_tiles(Index* ix, Batch* b, int64_t max_results, int64_t* o
   }
   b->cont = false;
   b->rho_in = rho;
+  b->nq = nq;
   if (st != GT_OK) return st;
-  b->last_max_entries = max_entries;
+  int64_t mx = 0;
+  for (int l = 0; l < GT_MAX_LEVELS; ++l) mx = std::max(mx, (int64_t)level_sum[l]);
+  b->last_max_entries = mx;
   b->last_results = total;
   *total_out = total;
   if (over) {
-    // the next finish, with larger buffers, runs the tiles again
+    // the next finish, with larger buffers, runs the parts again
     b->pending = keep_on_overflow;
     b->cont_again = keep_on_overflow;
     return fail(GT_ERR_RESULT_OVERFLOW, "need max_results >= " + std::to_string(total));
@@ -1477,7 +1508,17 @@ gt_status gt_call_bytes(const gt_index* cix, int32_t nq, gt_pool fmt, int64_t fr
   const size_t per = kPerEntry + (c.want_rec ? kPerRecord : 0);
   const size_t slack = 24 * 256;
   const size_t pr = (size_t)std::max<int64_t>(pairs, 1024) * kPerPair;
-  const int64_t fr_cap = std::max<int64_t>(64, std::min<int64_t>(worst, (frontier_entries + c.nt - 1) / c.nt));
+  // Entries fall only into subtrees that hold rows (rows fill the tree from
+  // the left), while every subtree's slot gets the same room: scale by the
+  // populated share of the 2^7 subtrees.  At least 64 entries per slot
+  // (small calls spread their entries unevenly).
+  const int64_t nbk = int64_t(1) << gt::kMaxBucketBits;
+  const int64_t span = std::max<int64_t>(1, ix->cap / nbk);
+  const int64_t populated = std::max<int64_t>(1, std::min<int64_t>(nbk, (ix->n + span - 1) / span));
+  const int64_t per_tile = (frontier_entries + c.nt - 1) / c.nt;
+  const int64_t floor_cap = std::min<int64_t>(worst, int64_t(64) << gt::kMaxBucketBits);
+  const int64_t fr_cap = std::max<int64_t>(
+      floor_cap, std::min<int64_t>(worst, (per_tile * nbk + populated - 1) / populated));
   const size_t want = common_bytes(ix, nq, c) + pr + (size_t)c.nt * (size_t)fr_cap * per + slack;
   const size_t min_first = common_bytes(ix, nq, c) + pr + (size_t)c.nt * 64 * per + slack;
   const size_t min_cont = common_bytes(ix, std::min(nq, c.tq), c1) + pr + (size_t)worst * kPerEntry + slack;

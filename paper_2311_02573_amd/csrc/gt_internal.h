@@ -184,6 +184,7 @@ struct Batch {
   int64_t ext_pairs = 0;
   int ext_max_queries = 0;           // the external workspace's call limit
   int64_t ext_epoch = 0;             // rows the call sees (kept by its continuation)
+  bool hits_overflowed = false;      // the last fixed call's candidates outgrew their room
   int continued_tiles = 0;           // tiles the last call ran one by one
   bool cont_again = false;           // a continued call ended in a result overflow
   int64_t last_max_entries = 0;      // largest frontier level of the last call

@@ -101,28 +101,34 @@ class Arena:
 
 
 class Estimator:
-    """Per-query memory figures of a call: frontier entries at its largest
-    level and candidate pairs (results; the leaf test's candidates are about
-    as many), scaled by a margin.  Starts from a prior and follows what
-    finished calls report: a larger figure is taken at once, a smaller one
-    slowly."""
+    """Memory figures of a call: frontier entries at its largest level per
+    query tile (an entry is a (pool, tile) pair, so a tile of a few queries
+    holds nearly as many as a full one) and candidate pairs per query (about
+    the results), each scaled by a margin.  Starts from a prior and follows
+    what finished calls report: a larger figure is taken at once, a smaller
+    one slowly."""
 
-    def __init__(self, entries_per_query: float = 512.0, pairs_per_query: float = 512.0,
-                 margin: float = 1.5):
-        self.entries = float(entries_per_query)
+    def __init__(self, entries_per_tile: float = 8192.0, pairs_per_query: float = 512.0,
+                 margin: float = 2.0, pairs_margin: float = 1.5, tile_queries: int = 64):
+        self.entries = float(entries_per_tile)
         self.pairs_q = float(pairs_per_query)
-        self.margin = margin
+        self.margin = margin            # entries spread unevenly over the frontier's slots
+        self.pairs_margin = pairs_margin
+        self.tile = tile_queries
+
+    def tiles(self, nq: int) -> int:
+        return (nq + self.tile - 1) // self.tile
 
     def frontier(self, nq: int) -> int:
-        return int(math.ceil(nq * self.entries * self.margin))
+        return int(math.ceil(self.tiles(nq) * self.entries * self.margin))
 
     def pairs(self, nq: int) -> int:
-        return int(math.ceil(nq * self.pairs_q * self.margin)) + 1024
+        return int(math.ceil(nq * self.pairs_q * self.pairs_margin)) + 1024
 
     def observe(self, nq: int, max_level_entries: int, results: int):
         if nq <= 0:
             return
-        for name, v in (("entries", max_level_entries / nq), ("pairs_q", results / nq)):
+        for name, v in (("entries", max_level_entries / self.tiles(nq)), ("pairs_q", results / nq)):
             old = getattr(self, name)
             setattr(self, name, v if v > old else 0.9 * old + 0.1 * v)
 
@@ -262,7 +268,7 @@ class Server:
         return {"memory_budget_bytes": self.arena.size, "memory_peak_bytes": self.arena.peak,
                 "calls": self.calls, "memory_waits": self.memory_waits,
                 "continued_calls": self.continued_calls,
-                "estimate_entries_per_query": round(self.est.entries, 1),
+                "estimate_entries_per_tile": round(self.est.entries, 1),
                 "estimate_pairs_per_query": round(self.est.pairs_q, 1)}
 
 

@@ -208,7 +208,7 @@ def test_memory_admission_queues_clustered_requests(gt):
     idx = gt.GTIndex(w.feats.cuda(), pools=("f32", "bf16"))
     Q = torch.from_numpy(w.queries).cuda()
     be = serve.GpuBackend(idx)
-    est = serve.Estimator(entries_per_query=2000, pairs_per_query=500)
+    est = serve.Estimator(entries_per_tile=20000, pairs_per_query=500)
     one, _ = be.call_bytes(256, est.frontier(256), est.pairs(256))
     srv = serve.Server(be, int(one * 1.3), streams=3, max_queries=256, estimator=est)
     rng = np.random.default_rng(4)

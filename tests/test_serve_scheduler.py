@@ -207,7 +207,7 @@ def test_memory_budget_forces_queueing():
     memory; every request gets the oracle's result."""
     F, Q = _workload()
     be = FakeBackend(F, polls_needed=3)
-    est = serve.Estimator(entries_per_query=100, pairs_per_query=10, margin=1.0)
+    est = serve.Estimator(entries_per_tile=100, pairs_per_query=10, margin=1.0, pairs_margin=1.0)
     one = be.call_bytes(16, est.frontier(16), est.pairs(16))[0]
     srv = serve.Server(be, int(one * 1.5), streams=3, max_queries=16, estimator=est)
     reqs = []
@@ -231,9 +231,9 @@ def test_group_is_cut_back_to_what_fits():
     fit the budget, so the call takes as many requests as fit."""
     F, Q = _workload()
     be = FakeBackend(F, polls_needed=2)
-    est = serve.Estimator(entries_per_query=100, pairs_per_query=10, margin=1.0)
+    est = serve.Estimator(entries_per_tile=100, pairs_per_query=10, margin=1.0, pairs_margin=1.0)
     fit = be.call_bytes(24, est.frontier(24), est.pairs(24))[0]
-    srv = serve.Server(be, fit + 100, streams=2, max_queries=64, estimator=est)
+    srv = serve.Server(be, serve.Arena._round(fit) + 100, streams=2, max_queries=64, estimator=est)
     for i in range(16):
         srv.submit(serve.Request(i, Q[4 * i:4 * i + 4], np.full(4, 0.9), arrival=srv.now()))
     srv.step()
@@ -252,9 +252,10 @@ def test_request_that_never_fits_is_refused():
 
 
 def test_estimator_follows_measured_calls():
-    est = serve.Estimator(entries_per_query=10, pairs_per_query=10, margin=2.0)
-    est.observe(100, 5000, 300)          # larger: taken at once
-    assert est.entries == 50 and est.pairs_q == 10 * 0.9 + 3 * 0.1
+    est = serve.Estimator(entries_per_tile=10, pairs_per_query=10, margin=2.0, pairs_margin=1.5)
+    est.observe(100, 5000, 300)          # 2 tiles of 64 queries; larger: taken at once
+    assert est.entries == 2500 and est.pairs_q == 10 * 0.9 + 3 * 0.1
     est.observe(100, 1000, 3000)         # smaller entries decay slowly
-    assert est.entries == 0.9 * 50 + 0.1 * 10 and est.pairs_q == 30
-    assert est.frontier(10) == int(np.ceil(10 * est.entries * 2.0))
+    assert est.entries == 0.9 * 2500 + 0.1 * 500 and est.pairs_q == 30
+    assert est.frontier(10) == int(np.ceil(1 * est.entries * 2.0))
+    assert est.frontier(65) == int(np.ceil(2 * est.entries * 2.0))
