@@ -363,6 +363,13 @@ def main():
     meas = {l: su["pairs"][l + 1] / (2.0 * args.nq) for l in range(first_sparse, D - 1)}
     meas[D - 1] = su["leaf_pairs"] / (2.0 * args.nq)   # two vectors tested per pool
     meas[D] = su["results"] / args.nq
+    # the same recursion fed with the index's own pool scores: 64 queries of
+    # the batch against 16,384 sampled pools of each level
+    t1 = time.time()
+    plan = cm.plan(idx, w.queries[:64], args.rho, levels=list(range(first_sparse, D + 1)))
+    plan_s = time.time() - t1
+    ps = plan["survivors"]
+    ratio = {l: (ps[l] / meas[l] if meas[l] > 0 else None) for l in sorted(meas)}
     cost_model = {
         "sample": "16 queries x 65,536 random rows of this workload",
         "lambda_moment_fit": round(lam_m, 2),
@@ -370,12 +377,25 @@ def main():
         "E_rho_eq3": {"moment": round(cm.expected_tests(w.n, args.rho, lam_m), 1),
                       "loghist": round(cm.expected_tests(w.n, args.rho, lam_h), 1)},
         "survivors_per_query": {l: {"moment": round(pm[l], 1), "loghist": round(ph[l], 1),
+                                    "sampled_pools": round(ps[l], 1),
                                     "measured": round(meas[l], 1)} for l in sorted(meas)},
+        "sampled_model": {
+            "sample": "64 queries of the batch x 16,384 pools of each level (float32 sums)",
+            "seconds": round(plan_s, 2),
+            "predicted_over_measured": {l: (round(v, 3) if v is not None else None)
+                                        for l, v in ratio.items()},
+            "within_2x": all(v is not None and 0.5 <= v <= 2.0 for v in ratio.values()),
+            "dense_level": plan["dense_level"],
+            "dense_level_walked": first_sparse,
+            "entries_per_tile": round(plan["entries_per_tile"], 1),
+            "results_per_query": round(plan["results_per_query"], 1),
+        },
     }
     log(f"cost model: lambda {lam_m:.1f} (moments) / {lam_h:.1f} (log histogram); survivors "
-        "per query predicted/predicted/measured " +
-        ", ".join(f"L{l} {v['moment']}/{v['loghist']}/{v['measured']}"
-                  for l, v in cost_model["survivors_per_query"].items()))
+        "per query TNE moments / TNE log-histogram / sampled pools / measured " +
+        ", ".join(f"L{l} {v['moment']}/{v['loghist']}/{v['sampled_pools']}/{v['measured']}"
+                  for l, v in cost_model["survivors_per_query"].items()) +
+        f"; sampled model's dense level {plan['dense_level']} (walked {first_sparse})")
 
     # ---- the same batch at the other thresholds: walk vs exhaustive GEMM
     rho_sweep = {}
@@ -748,6 +768,14 @@ def serving_leg(seconds, torch, gt, synth, dev):
                "groups_of_100_rows_per_s": round(100 * 1e3 / float(np.mean(ins_lat)), 1),
                "bulk_100000_rows_per_s": round(1e5 / bulk_s, 1)}
     log(f"serving index, inserts: {inserts}")
+    from paper_2311_02573_amd import costmodel as cm
+
+    plan = cm.plan(idx, w.queries[:64], float(w.rho[0]))
+    if plan["dense_level"] is not None:
+        idx.set_option("dense_start", plan["dense_level"])
+    log(f"serving index, sampled cost model: dense level {plan['dense_level']}, "
+        f"entries per tile {plan['entries_per_tile']:.0f}, results per query "
+        f"{plan['results_per_query']:.0f}")
     backend = serve.GpuBackend(idx)
     nqp = qpool.shape[0]
     make_q = lambda i, k: qpool[(i * 613) % (nqp - 512):(i * 613) % (nqp - 512) + k]
@@ -755,7 +783,8 @@ def serving_leg(seconds, torch, gt, synth, dev):
     ins_rows = lambda k: torch.from_numpy(synth.insert_rows(3, 100, w.d, w.temp, offset=k)).to(
         dev, torch.float16)
     budget = 8 << 30
-    est = serve.Estimator()
+    est = serve.Estimator(entries_per_tile=plan["entries_per_tile"],
+                          pairs_per_query=max(1.0, plan["results_per_query"]))
 
     def factory():
         return serve.Server(backend, budget, streams=4, max_queries=1024, pool="bf16", estimator=est)
@@ -765,7 +794,11 @@ def serving_leg(seconds, torch, gt, synth, dev):
                        "requests U{1..512} queries at rho=0.9, Poisson arrivals, "
                        "inserts 10000/s in groups of 100",
            "admission": f"by memory: {budget >> 30} GiB arena, 4 streams, calls of up to 1024 queries",
-           "call_1024_queries": call, "inserts": inserts, **runs}
+           "call_1024_queries": call, "inserts": inserts,
+           "sampled_cost_model": {"dense_level": plan["dense_level"],
+                                  "entries_per_tile": round(plan["entries_per_tile"], 1),
+                                  "results_per_query": round(plan["results_per_query"], 1)},
+           **runs}
     del srv, backend
     idx.close()
     torch.cuda.empty_cache()
@@ -802,8 +835,14 @@ def stress_serving_leg(seconds, torch, gt, synth, dev):
     make_q = lambda i, k: qperm[(i * 1031) % (nqp - 2048):(i * 1031) % (nqp - 2048) + k]
     rho_req = g.uniform(0.75, 0.95, size=1 << 16)
     rho_of = lambda i, k: np.full(k, rho_req[i % len(rho_req)])
+    from paper_2311_02573_amd import costmodel as cm
+
+    plan = cm.plan(idx, w.queries[::128][:64], 0.85)
+    log(f"stress index, sampled cost model at rho 0.85: entries per tile "
+        f"{plan['entries_per_tile']:.0f}, results per query {plan['results_per_query']:.0f}")
     budget = 48 << 30
-    est = serve.Estimator()
+    est = serve.Estimator(entries_per_tile=plan["entries_per_tile"],
+                          pairs_per_query=max(1.0, plan["results_per_query"]))
 
     def factory():
         return serve.Server(backend, budget, streams=4, max_queries=2048, pool="bf16", estimator=est)

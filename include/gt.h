@@ -317,6 +317,10 @@ gt_status gt_read_pools(const gt_index* index, int32_t level, int64_t first, int
  *                 call of the same format met (deeper while the entries of a
  *                 level fill more than 4.6e-4 x row length of its populated
  *                 (pool, query tile) pairs)
+ *   "dense_start" the automatic dense level's level for a workspace's first
+ *                 call, before it has measured a frontier (-1 = the fixed
+ *                 rule above); a cost model's prediction (paper Sec. 5, Eq. 3)
+ *                 goes here
  *   "walk_subtract" subtraction step of the bf16 walk after a dense step (paper
  *                 Sec. 2, Alg. 1: one dot product per split, the other half
  *                 bounded by the pool's score minus it): 0 off, 1 every sparse

@@ -1,8 +1,11 @@
 """Expected number of pool tests per query under the TNE similarity model
 (paper Sec. 5: Eq. 2, the CLT and truncated-Erlang pool-score laws, the Q_k
-recursion and Eq. 3).  Host-side arithmetic only: it predicts how many pools
-per query survive each level of the walk, which the benchmark sets beside the
-walk's own counts.  The walk itself never uses it.
+recursion and Eq. 3), and the same recursion fed with pool-score laws
+sampled from an index.  Host-side arithmetic only: it predicts how many pools
+per query survive each level of the walk; the sampled model's predictions
+choose the first dense level of a call (gt option "dense_start") and the
+serving loop's first memory estimates (frontier entries per query tile,
+results per query).  Results never depend on it.
 
 Model (Sec. 5).  Each similarity x = q.f_i of a query with a database vector
 is an independent draw from the truncated normalised exponential on [0, 1]
@@ -27,7 +30,9 @@ from __future__ import annotations
 import math
 
 __all__ = ["tne_mean", "tne_var", "prune_prob", "pools_per_round", "expected_tests",
-           "fit_lambda", "fit_lambda_loghist", "level_survivors"]
+           "fit_lambda", "fit_lambda_loghist", "level_survivors", "empirical_prune_probs",
+           "survivors_from_probs", "dense_level_from_model", "entries_per_tile_from_model",
+           "sample_index", "plan"]
 
 
 def tne_mean(lam: float) -> float:
@@ -145,3 +150,125 @@ def fit_lambda_loghist(samples, bins: int = 50) -> float:
     slope = np.linalg.lstsq(A, np.log(dens), rcond=None)[0][1]
     return float(max(1e-6, -slope))
 
+
+
+# --------------------------------------------------------------------------
+# The same recursion fed with the index's own pool scores.
+#
+# The TNE law need not describe a database (a spike of near-zero similarities
+# beside a flat tail holds for softmax features of few classes).  Eq. 3 only
+# needs, per round, the probability that a pool of that round scores below
+# the threshold; here it is read off the index: for a sample of queries and a
+# sample of each level's stored pool sums, the fraction of (query, pool) pairs
+# scoring below tau = rho |q| m_min is the level's prune probability p_l.  A
+# pool never scores above its parent (non-negative members), so a pool of
+# level l survives its test iff its score reaches tau, and the conditional
+# probability that a child of a surviving pool is pruned is
+#   1 - (1 - p_l) / (1 - p_{l-1}),
+# which, put into Q_{l+1} = 2 (1 - p_{l+1 | l}) Q_l, gives 2^l (1 - p_l)
+# surviving pools at level l.
+
+def empirical_prune_probs(level_rows: dict, queries, rho, m_min: float):
+    """p_l per level from sampled pool sums.  level_rows: {level: [m, d]
+    float64 pool sums (a sample of the level's pools)}; queries: [s, d];
+    rho: scalar or [s].  Returns {level: p_l} (the fraction of sampled
+    (query, pool) pairs scoring below rho |q| m_min)."""
+    import numpy as np
+
+    q = np.asarray(queries, np.float64)
+    r = np.broadcast_to(np.asarray(rho, np.float64), (q.shape[0],))
+    tau = r * np.sqrt(np.einsum("ij,ij->i", q, q)) * m_min
+    out = {}
+    for l, rows in level_rows.items():
+        S = np.asarray(rows, np.float64)
+        scores = S[:, :q.shape[1]] @ q.T            # [m, s]
+        out[l] = float(np.mean(scores < tau[None, :]))
+    return out
+
+
+def survivors_from_probs(p: dict, depth: int):
+    """Expected surviving pools per query at each level in p (complete tree of
+    the given depth) through the Q_k recursion with conditional prune
+    probabilities: {level: 2^l (1 - p_l)}; levels absent from p are skipped."""
+    out = {}
+    prev_l, prev_p = None, None
+    for l in sorted(p):
+        if prev_l is None or l != prev_l + 1:
+            surv = (2.0 ** l) * (1.0 - p[l])        # a fresh start: unconditional
+        else:
+            cond = 1.0 - (1.0 - p[l]) / max(1e-300, 1.0 - prev_p) if prev_p < 1.0 else 1.0
+            q_tested = 2.0 * out[prev_l]           # Q of this round: children of survivors
+            surv = q_tested * (1.0 - cond)
+        out[l] = surv
+        prev_l, prev_p = l, p[l]
+    return out
+
+
+def dense_level_from_model(survivors: dict, depth: int, d_pad: int, tile_queries: int = 64,
+                           populated: float = 1.0, threshold_per_column: float = 4.6e-4):
+    """First level whose predicted frontier density is at most the dense /
+    sparse crossover: a dense step over level L costs in proportion to its
+    pools x tiles x d_pad, a sparse step to the entries of level L; the dense
+    step is cheaper while the entries fill more than threshold_per_column x
+    d_pad of the (pool, tile) pairs of populated pools.  The entries of a
+    tile at level L are taken as min(pools, tile_queries x survivors per
+    query) (no two queries of a tile sharing a pool: an upper bound).
+    Returns the level, or None."""
+    thr = threshold_per_column * d_pad
+    for L in sorted(survivors):
+        pools = populated * 2.0 ** L
+        entries = min(pools, tile_queries * survivors[L])
+        if entries / pools <= thr:
+            return L
+    return None
+
+
+def entries_per_tile_from_model(survivors: dict, tile_queries: int = 64, populated: float = 1.0):
+    """Largest predicted frontier entries of one full query tile over the
+    levels in survivors: min(pools, tile_queries x survivors per query)."""
+    return max(min(populated * 2.0 ** L, tile_queries * s) for L, s in survivors.items())
+
+
+def sample_index(index, queries, rho, levels, count: int = 16384, seed: int = 0):
+    """Reads a contiguous block of `count` populated pools of each level from
+    a GTIndex (float32 master sums, rounded up) and returns (p_l per level,
+    survivors per query per level).  queries: [s, d] float32 host array."""
+    import numpy as np
+
+    st = index.stats()
+    D, n = st["depth"], st["n"]
+    g = np.random.default_rng(seed)
+    rows = {}
+    for l in levels:
+        span = 1 << (D - l)
+        pop = max(1, (n + span - 1) // span)        # pools holding a row
+        c = min(count, pop)
+        first = int(g.integers(0, pop - c + 1))
+        rows[l] = index.read_pools(l, first, c, pool="f32").astype(np.float64)
+    p = empirical_prune_probs(rows, queries, rho, st["m_min"])
+    return p, survivors_from_probs(p, D)
+
+
+def plan(index, queries, rho, levels=None, count: int = 16384, tile_queries: int = 64,
+         seed: int = 0) -> dict:
+    """Model of a workload from a sample of its queries: prune probabilities
+    and surviving pools per query per level (sampled pool scores through the
+    Eq. 3 recursion), the dense level it calls for (rows of 512 columns or
+    more, where the dense / sparse crossover was measured; else None), the
+    frontier entries of a full query tile at its largest sparse level, and
+    the results per query (the leaves' survivors)."""
+    st = index.stats()
+    D, n, cap, dp = st["depth"], st["n"], st["capacity"], st["d_pad"]
+    if levels is None:
+        levels = list(range(max(1, D - 12), D + 1))
+    p, surv = sample_index(index, queries, rho, levels, count=count, seed=seed)
+    populated = min(1.0, n / cap)
+    dense = None
+    if dp >= 512:
+        dense = dense_level_from_model({l: s for l, s in surv.items() if l < D}, D, dp,
+                                       tile_queries, populated)
+    start = dense if dense is not None else max(0, D - 4)
+    sparse = {l: s for l, s in surv.items() if start <= l < D}
+    return {"prune_probs": p, "survivors": surv, "dense_level": dense,
+            "entries_per_tile": entries_per_tile_from_model(sparse or surv, tile_queries, populated),
+            "results_per_query": surv.get(D, 0.0)}

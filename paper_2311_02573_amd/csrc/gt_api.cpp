@@ -88,10 +88,11 @@ int head_of(const Index* ix) {
 // matrix cores are 16x slower than bfloat16 ones).
 int dense_last_of(const Index* ix, int fmt, int h) {
   if (fmt == GT_POOL_F32 || ix->dense_last == -1) return -1;
-  // automatic: the level whose pools hold about 16 of the populated rows
+  // automatic: a level given by the caller (a cost model's choice), else
+  // the level whose pools hold about 16 of the populated rows
   int lg = 0;
   while ((int64_t(1) << lg) < ix->n) ++lg;
-  int dl = ix->dense_last >= 0 ? ix->dense_last : lg - 4;
+  int dl = ix->dense_last >= 0 ? ix->dense_last : ix->dense_start >= 0 ? ix->dense_start : lg - 4;
   dl = std::min(dl, ix->depth - 1);
   return dl > h ? dl : -1;
 }
@@ -1734,6 +1735,9 @@ gt_status gt_set_option(gt_index* ix, const char* key, int64_t value) {
   } else if (!strcmp(key, "dense_last")) {
     if (value < -2 || value > ix->depth - 1) return fail(GT_ERR_INVALID_ARG, "dense_last out of range");
     ix->dense_last = (int)value;
+  } else if (!strcmp(key, "dense_start")) {
+    if (value < -1 || value > ix->depth - 1) return fail(GT_ERR_INVALID_ARG, "dense_start out of range");
+    ix->dense_start = (int)value;
   } else if (!strcmp(key, "walk_subtract")) {
     if (value < -1 || value > 2) return fail(GT_ERR_INVALID_ARG, "walk_subtract out of range");
     ix->walk_subtract = (int)value;

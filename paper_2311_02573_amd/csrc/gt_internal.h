@@ -277,6 +277,7 @@ struct Index {
   int head_level = -1;       // -1: automatic
   int grid = 0;              // 0: one workgroup per CU
   int dense_last = -2;       // last level walked densely (-2: automatic, -1: none)
+  int dense_start = -1;      // automatic: the first call's level (-1: the fixed rule)
   int walk_subtract = -1;    // subtraction step (bfloat16 after a dense step): 0 off,
                              // 1 every sparse level, 2 all but the last, -1 automatic
   bool profile = false;

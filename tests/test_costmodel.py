@@ -118,3 +118,57 @@ def test_loghist_fit_recovers_the_parameter():
         x = _tne_samples(rng, lam, 400_000)
         assert abs(cm.fit_lambda_loghist(x, bins=25) / lam - 1) < 0.1
 
+
+
+def test_sampled_model_reproduces_the_exact_walk():
+    """With every pool of every level as the 'sample' and one query, the
+    prune probabilities give exactly the surviving pools per level that the
+    level-wise walk in rational arithmetic finds (tests at level l + 1 are
+    twice the survivors of level l) at the threshold rho |q| m_min."""
+    from oracle import exact, pools
+
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        n, d = 64, 5
+        F = rng.exponential(size=(n, d)) ** 3
+        F /= np.linalg.norm(F, axis=1, keepdims=True)
+        F = F.astype(np.float32).astype(np.float64)
+        q = F[rng.integers(n)] + 0.05 * rng.random(d)
+        q = q.astype(np.float32).astype(np.float64)
+        rho = [0.5, 0.8, 0.9][trial % 3]
+        m_min = float(np.min(np.linalg.norm(F, axis=1)))
+        tau = rho * float(np.sqrt(q @ q)) * m_min
+        lv = pools.pool_tree(F)
+        D = len(lv) - 1
+        p = cm.empirical_prune_probs({l: lv[l] for l in range(D + 1)}, q[None, :], rho, m_min)
+        surv = cm.survivors_from_probs(p, D)
+        _, tests = exact.levelwise_walk(F, q, tau)
+        for l in range(D):
+            want = tests[l + 1] / 2 if l + 1 < len(tests) else 0
+            assert surv[l] == pytest.approx(want, abs=1e-9), (trial, l, surv[l], want)
+        # leaves: members scoring at least tau
+        assert surv[D] == pytest.approx(np.sum(F @ q >= tau), abs=1e-9)
+
+
+def test_sampled_model_survivors_follow_any_probabilities():
+    """The recursion with conditional prune probabilities returns 2^l (1 - p_l)
+    for consecutive levels, whatever the probabilities."""
+    p = {10: 0.2, 11: 0.6, 12: 0.95, 14: 0.99}
+    s = cm.survivors_from_probs(p, 14)
+    assert s[10] == pytest.approx(2 ** 10 * 0.8)
+    assert s[11] == pytest.approx(2 ** 11 * 0.4)
+    assert s[12] == pytest.approx(2 ** 12 * 0.05)
+    assert s[14] == pytest.approx(2 ** 14 * 0.01)
+
+
+def test_dense_level_from_model_picks_the_crossover():
+    """The first level whose predicted entry density (no sharing within a
+    tile) is at most 4.6e-4 x d_pad."""
+    surv = {14: 400.0, 15: 380.0, 16: 345.0, 17: 299.0}
+    # d_pad 1024: threshold 0.471; densities 1.0 (capped), 0.74, 0.337, 0.146
+    assert cm.dense_level_from_model(surv, 20, 1024) == 16
+    # half the tree populated: twice the density
+    assert cm.dense_level_from_model(surv, 20, 1024, populated=0.5) == 17
+    assert cm.dense_level_from_model(surv, 20, 128) is None
+    # the largest tile frontier: level 15, 64 x 380 entries (level 14 is capped at 2^14)
+    assert cm.entries_per_tile_from_model(surv) == pytest.approx(64 * 380)

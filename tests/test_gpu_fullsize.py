@@ -128,3 +128,34 @@ def test_fullsize_planted_neighbours_found(setup):
                 total += 1
                 found += int(pid in set(res[b][0].tolist()))
     assert total > 100 and found == total
+
+
+def test_fullsize_sampled_cost_model(setup):
+    """The Eq. 3 recursion fed with sampled pool scores of this index (64
+    queries x 16,384 pools per level) predicts the walk's surviving pools per
+    query within a factor of two at every level the walk tests; the dense
+    level it picks, given as the automatic level's start, changes no result."""
+    from paper_2311_02573_amd import costmodel as cm
+
+    gt, w, idx, q = setup
+    nq = 64
+    say("sampled cost model")
+    plan = cm.plan(idx, w.queries[:nq], 0.9, levels=list(range(12, 21)))
+    base = idx.query(q[:nq], 0.9, pool="bf16").to_lists()
+    st = idx.stats()
+    D, h = st["depth"], st["head_level"]
+    meas = {l: st["pairs"][l + 1] / (2.0 * nq) for l in range(h + 1, D - 1)}
+    meas[D - 1] = st["leaf_pairs"] / (2.0 * nq)
+    meas[D] = st["results"] / nq
+    for l, m in meas.items():
+        say(f"level {l}: predicted {plan['survivors'][l]:.1f}, measured {m:.1f}")
+        assert 0.5 <= plan["survivors"][l] / m <= 2.0, (l, plan["survivors"][l], m)
+    assert plan["dense_level"] is not None and h < plan["dense_level"] < D
+    try:
+        idx.set_option("dense_start", plan["dense_level"])
+        again = idx.query(q[:nq], 0.9, pool="bf16").to_lists()
+        for (a, sa), (b, sb) in zip(base, again):
+            np.testing.assert_array_equal(a, b)
+            np.testing.assert_array_equal(sa, sb)
+    finally:
+        idx.set_option("dense_start", -1)
