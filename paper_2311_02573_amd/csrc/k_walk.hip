@@ -146,6 +146,29 @@ __device__ __forceinline__ void mma16x16<GT_POOL_F32>(const uint4& a, const uint
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
 }
 
+// gfx950 f8f6f4 forms for float8 (e4m3: format 0 for both operands, no
+// block scales): 32 bytes per lane, the lane's two 16-byte slices a0, a1 and
+// the matching slices b0, b1 of the other operand, so A and B lanes again
+// carry the same dimensions.  Same numerics as the fp8 forms above (measured
+// equal), twice the products per instruction.
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+__device__ __forceinline__ i32x8 pack32(const uint4& x0, const uint4& x1) {
+  i32x8 v;
+  v[0] = (int)x0.x; v[1] = (int)x0.y; v[2] = (int)x0.z; v[3] = (int)x0.w;
+  v[4] = (int)x1.x; v[5] = (int)x1.y; v[6] = (int)x1.z; v[7] = (int)x1.w;
+  return v;
+}
+__device__ __forceinline__ void mma_f8_16x16x128(const uint4& a0, const uint4& a1, const uint4& b0,
+                                                 const uint4& b1, f32x4& acc) {
+  acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(pack32(a0, a1), pack32(b0, b1), acc, 0, 0,
+                                                        0, 0, 0, 0);
+}
+__device__ __forceinline__ void mma_f8_32x32x64(const uint4& a0, const uint4& a1, const uint4& b0,
+                                                const uint4& b1, f32x16& acc) {
+  acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(pack32(a0, a1), pack32(b0, b1), acc, 0, 0,
+                                                       0, 0, 0, 0);
+}
+
 // Index i with pre[i] <= g < pre[i + 1] (pre ascending, n + 1 values).
 __device__ __forceinline__ int find_slot(const uint32_t* pre, int n, uint32_t g) {
   int lo = 0, hi = n;
@@ -266,7 +289,7 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
     if (tid < TQ) {
       const int qi = t * TQ + tid;
       float th = a.thr[qi];
-      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th * kFp8ThrFactor, -(a.qexp[qi] + a.lexp));
       thr_lds[tid] = th;
     }
     __syncthreads();
@@ -389,6 +412,19 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
           mma16x16<FMT>(x1, bq, acc[1][qb]);
         }
       };
+      // float8: steps s and s + 1 in one 16x16x128 product
+      auto step2 = [&](const uint4& l0a, const uint4& l1a, const uint4& l0b, const uint4& l1b,
+                       int s) {
+        const uint4 x0a = to_mfma(l0a), x1a = to_mfma(l1a);
+        const uint4 x0b = to_mfma(l0b), x1b = to_mfma(l1b);
+#pragma unroll
+        for (int qb = 0; qb < NQB; ++qb) {
+          const uint4 bqa = ld_lds16(brow + qb * 16 * rs + 64 * s);
+          const uint4 bqb = ld_lds16(brow + qb * 16 * rs + 64 * (s + 1));
+          mma_f8_16x16x128(x0a, x0b, bqa, bqb, acc[0][qb]);
+          mma_f8_16x16x128(x1a, x1b, bqa, bqb, acc[1][qb]);
+        }
+      };
 #pragma unroll
       for (int s0 = 0; s0 < nsteps; s0 += 2 * kPipe) {
 #pragma unroll
@@ -398,9 +434,16 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
           bB1[u] = ld_global16(arow1 + 64 * st);
         }
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (FMT == GT_POOL_FP8E4M3) {
+          // (a float8 row has an even number of 64-byte steps)
 #pragma unroll
-        for (int u = 0; u < kPipe; ++u)
-          if (s0 + u < nsteps) step(bA0[u], bA1[u], s0 + u);
+          for (int u = 0; u < kPipe; u += 2)
+            if (s0 + u < nsteps) step2(bA0[u], bA1[u], bA0[u + 1], bA1[u + 1], s0 + u);
+        } else {
+#pragma unroll
+          for (int u = 0; u < kPipe; ++u)
+            if (s0 + u < nsteps) step(bA0[u], bA1[u], s0 + u);
+        }
         __builtin_amdgcn_sched_barrier(0);
         {
           // next stage of this group, or the first stage of the next group
@@ -433,9 +476,16 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_level(WalkLevelArgs a)
           }
         }
         __builtin_amdgcn_sched_barrier(0);
+        if constexpr (FMT == GT_POOL_FP8E4M3) {
 #pragma unroll
-        for (int u = 0; u < kPipe; ++u)
-          if (s0 + kPipe + u < nsteps) step(bB0[u], bB1[u], s0 + kPipe + u);
+          for (int u = 0; u < kPipe; u += 2)
+            if (s0 + kPipe + u < nsteps)
+              step2(bB0[u], bB1[u], bB0[u + 1], bB1[u + 1], s0 + kPipe + u);
+        } else {
+#pragma unroll
+          for (int u = 0; u < kPipe; ++u)
+            if (s0 + kPipe + u < nsteps) step(bB0[u], bB1[u], s0 + kPipe + u);
+        }
         __builtin_amdgcn_sched_barrier(0);
       }
 
@@ -563,7 +613,7 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_wide(WalkLevelArgs a) 
     if (tid < TQ) {
       const int qi = t * TQ + tid;
       float th = a.thr[qi];
-      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+      if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th * kFp8ThrFactor, -(a.qexp[qi] + a.lexp));
       thr_lds[tid] = th;
     }
     __syncthreads();
@@ -656,15 +706,33 @@ __global__ __launch_bounds__(kWalkThreads, 1) void k_walk_wide(WalkLevelArgs a) 
               l0[u] = ld_global16(arow0 + wofs + 64 * st);
               l1[u] = ld_global16(arow1 + wofs + 64 * st);
             }
+            if constexpr (FMT == GT_POOL_FP8E4M3) {
+              // steps s and s + 1 in one 16x16x128 product (an even count per window)
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-              if (s0 + u < wsteps) {
-                const uint4 x0 = to_mfma(l0[u]), x1 = to_mfma(l1[u]);
+              for (int u = 0; u < 8; u += 2) {
+                if (s0 + u < wsteps) {
+                  const uint4 x0a = to_mfma(l0[u]), x1a = to_mfma(l1[u]);
+                  const uint4 x0b = to_mfma(l0[u + 1]), x1b = to_mfma(l1[u + 1]);
 #pragma unroll
-                for (int qb = 0; qb < NQB; ++qb) {
-                  const uint4 bq = ld_lds16(brow + qb * 16 * RS + 64 * (s0 + u));
-                  mma16x16<FMT>(x0, bq, acc[0][qb]);
-                  mma16x16<FMT>(x1, bq, acc[1][qb]);
+                  for (int qb = 0; qb < NQB; ++qb) {
+                    const uint4 bqa = ld_lds16(brow + qb * 16 * RS + 64 * (s0 + u));
+                    const uint4 bqb = ld_lds16(brow + qb * 16 * RS + 64 * (s0 + u + 1));
+                    mma_f8_16x16x128(x0a, x0b, bqa, bqb, acc[0][qb]);
+                    mma_f8_16x16x128(x1a, x1b, bqa, bqb, acc[1][qb]);
+                  }
+                }
+              }
+            } else {
+#pragma unroll
+              for (int u = 0; u < 8; ++u) {
+                if (s0 + u < wsteps) {
+                  const uint4 x0 = to_mfma(l0[u]), x1 = to_mfma(l1[u]);
+#pragma unroll
+                  for (int qb = 0; qb < NQB; ++qb) {
+                    const uint4 bq = ld_lds16(brow + qb * 16 * RS + 64 * (s0 + u));
+                    mma16x16<FMT>(x0, bq, acc[0][qb]);
+                    mma16x16<FMT>(x1, bq, acc[1][qb]);
+                  }
                 }
               }
             }
@@ -1166,7 +1234,7 @@ __device__ __forceinline__ void dense_thresholds(const DenseLevelArgs& a, int t,
   for (int j = 0; j < 2; ++j) {
     const int qi = t * 64 + 32 * j + r;
     float th = a.thr[qi];
-    if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th, -(a.qexp[qi] + a.lexp));
+    if (FMT == GT_POOL_FP8E4M3) th = ldexpf(th * kFp8ThrFactor, -(a.qexp[qi] + a.lexp));
     thr[j] = th;
   }
 }
@@ -1318,6 +1386,32 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
 
   auto compute = [&](const unsigned char* As) {
     const unsigned char* Bs = As + kDStageA;
+    if constexpr (FMT == GT_POOL_FP8E4M3) {
+      // one 32x32x64 product per 64 bytes of K: lanes 0-31 take chunks 0-1
+      // of the 64-byte block, lanes 32-63 chunks 2-3, the same in A and B
+#pragma unroll
+      for (int sl = 0; sl < kDK / 64; ++sl) {
+        const int c0 = 4 * sl + 2 * half;
+        uint4 av[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int ar = wr * 64 + i * 32 + r;
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            av[i][h] = *reinterpret_cast<const uint4*>(As + ar * kDK + 16 * ((c0 + h) ^ dswz(ar)));
+        }
+        // (query fragments one block at a time: the accumulators leave little room)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int br = wq * 128 + j * 32 + r;
+          const uint4 b0 = *reinterpret_cast<const uint4*>(Bs + br * kDK + 16 * (c0 ^ dswz(br)));
+          const uint4 b1 = *reinterpret_cast<const uint4*>(Bs + br * kDK + 16 * ((c0 + 1) ^ dswz(br)));
+          mma_f8_32x32x64(av[0][0], av[0][1], b0, b1, acc[0][j]);
+          mma_f8_32x32x64(av[1][0], av[1][1], b0, b1, acc[1][j]);
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int sl = 0; sl < kDK / 32; ++sl) {
       const int c = 2 * sl + half;
