@@ -48,6 +48,8 @@ class Request:
     done: float | None = None
     epoch_n: int | None = None  # vectors visible to the request
     results: list | None = None  # per query: (ids int64, sims float32)
+    timeout_s: float | None = None  # longest wait for admission (None: no limit)
+    status: str = "waiting"      # waiting, running, done, cancelled, timeout
 
     @property
     def nq(self) -> int:
@@ -156,6 +158,7 @@ class Server:
         self.busy: list[_Call] = []
         self.waiting: collections.deque[Request] = collections.deque()
         self.finished: list[Request] = []
+        self.dropped: list[Request] = []   # cancelled or timed out
         self.est = estimator or Estimator()
         self.clock = clock
         self.t0 = clock()
@@ -169,7 +172,43 @@ class Server:
     def submit(self, req: Request):
         if req.nq > self.max_queries:
             raise ValueError(f"request of {req.nq} queries exceeds the call limit {self.max_queries}")
+        req.status = "waiting"
         self.waiting.append(req)
+
+    def cancel(self, req: Request) -> bool:
+        """Withdraws a request.  A waiting one leaves the queue at once; a
+        running one cannot be stopped on the device, so its call completes
+        and its results are dropped.  Returns False if it had already ended."""
+        if req.status == "waiting":
+            self.waiting.remove(req)
+            self._end(req, "cancelled")
+            return True
+        if req.status == "running":
+            req.status = "cancelling"
+            return True
+        return False
+
+    def _end(self, req: Request, status: str):
+        req.status = status
+        req.done = self.now()
+        if status != "done":
+            req.results = None
+            self.dropped.append(req)
+        else:
+            self.finished.append(req)
+
+    def _expire(self):
+        """Requests that waited past their admission timeout end unserved."""
+        if not self.waiting:
+            return
+        now = self.now()
+        keep = collections.deque()
+        for r in self.waiting:
+            if r.timeout_s is not None and now - r.arrival > r.timeout_s:
+                self._end(r, "timeout")
+            else:
+                keep.append(r)
+        self.waiting = keep
 
     @property
     def idle(self) -> bool:
@@ -178,6 +217,7 @@ class Server:
     def step(self) -> int:
         """Completes what is done, admits what fits; returns completed requests."""
         done = self._complete()
+        self._expire()
         self._admit()
         return done
 
@@ -224,6 +264,7 @@ class Server:
             for r in group:
                 r.admitted = now
                 r.epoch_n = n
+                r.status = "running"
             q = self.backend.concat([r.queries for r in group])
             rho = np.concatenate([r.rho for r in group])
             self.backend.submit(ws, q, rho, self.pool, off, nbytes, pairs)
@@ -247,10 +288,13 @@ class Server:
             now = self.now()
             off = 0
             for r, k in zip(call.requests, call.sizes):
-                r.results = lists[off:off + k]
-                r.done = now
+                if r.status == "cancelling":
+                    self._end(r, "cancelled")
+                else:
+                    r.results = lists[off:off + k]
+                    self._end(r, "done")
+                    r.done = now
                 off += k
-                self.finished.append(r)
                 done += 1
             self.free.append(call.ws)
         self.busy = still
@@ -273,11 +317,16 @@ class Server:
 
 
 def latency_summary(reqs) -> dict:
-    lat = np.array([r.latency for r in reqs if r.latency is not None]) * 1e3
-    nq = sum(r.nq for r in reqs if r.latency is not None)
+    """Latency percentiles over the requests served (cancelled and timed-out
+    requests are counted apart)."""
+    served = [r for r in reqs if r.status == "done" and r.latency is not None]
+    lat = np.array([r.latency for r in served]) * 1e3
+    nq = sum(r.nq for r in served)
     if len(lat) == 0:
         return {"requests": 0}
     return {"requests": int(len(lat)), "queries": int(nq),
+            "cancelled": sum(r.status == "cancelled" for r in reqs),
+            "timed_out": sum(r.status == "timeout" for r in reqs),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
             "mean_ms": round(float(lat.mean()), 3)}

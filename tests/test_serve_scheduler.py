@@ -259,3 +259,56 @@ def test_estimator_follows_measured_calls():
     assert est.entries == 0.9 * 2500 + 0.1 * 500 and est.pairs_q == 30
     assert est.frontier(10) == int(np.ceil(1 * est.entries * 2.0))
     assert est.frontier(65) == int(np.ceil(2 * est.entries * 2.0))
+
+
+def test_cancel_waiting_and_running_requests():
+    """A waiting request leaves the queue and never runs; a running one's call
+    completes (the device cannot be stopped), its results are dropped, and its
+    memory returns to the arena; the other requests get theirs."""
+    F, Q = _workload()
+    be = FakeBackend(F, polls_needed=4)
+    srv = serve.Server(be, 1 << 30, streams=1, max_queries=16)
+    reqs = [serve.Request(i, Q[10 * i:10 * i + 10], np.full(10, 0.9), arrival=srv.now())
+            for i in range(4)]
+    for r in reqs:
+        srv.submit(r)
+    srv.step()
+    assert reqs[0].status == "running" and reqs[1].status == "waiting"
+    assert srv.cancel(reqs[2]) and reqs[2].status == "cancelled"
+    assert srv.cancel(reqs[0]) and reqs[0].status == "cancelling"
+    srv.drain(timeout_s=30)
+    assert reqs[0].status == "cancelled" and reqs[0].results is None
+    assert reqs[2].results is None and 20 not in be.calls[:0]
+    assert sum(be.calls) == 30           # requests 0, 1, 3 ran; 2 never did
+    for r in (reqs[1], reqs[3]):
+        assert r.status == "done"
+        want = ob.range_search(F, r.queries, r.rho)
+        for (gi, _), (wi, _) in zip(r.results, want):
+            np.testing.assert_array_equal(gi, wi)
+    assert not srv.cancel(reqs[1]) and srv.arena.used == 0
+    s = serve.latency_summary(reqs)
+    assert s["requests"] == 2 and s["cancelled"] == 2
+
+
+def test_admission_timeout():
+    """With one stream busy, requests whose admission wait exceeds their
+    timeout end unserved; the rest are served in order."""
+    F, Q = _workload()
+    t = [0.0]
+    be = FakeBackend(F, polls_needed=10 ** 9)   # the first call runs until released
+    srv = serve.Server(be, 1 << 30, streams=1, max_queries=8, clock=lambda: t[0])
+    r0 = serve.Request(0, Q[:8], np.full(8, 0.9), arrival=0.0)
+    r1 = serve.Request(1, Q[8:16], np.full(8, 0.9), arrival=0.0, timeout_s=0.5)
+    r2 = serve.Request(2, Q[16:24], np.full(8, 0.9), arrival=0.0, timeout_s=5.0)
+    for r in (r0, r1, r2):
+        srv.submit(r)
+    srv.step()
+    t[0] = 1.0
+    srv.step()
+    assert r1.status == "timeout" and r2.status == "waiting"
+    be.polls_needed = 0
+    ws = srv.busy[0].ws
+    ws.pending = ws.pending[:3] + (0,) + ws.pending[4:]
+    srv.drain(timeout_s=30)
+    assert r0.status == "done" and r2.status == "done" and r1.results is None
+    assert [r.rid for r in srv.finished] == [0, 2]
