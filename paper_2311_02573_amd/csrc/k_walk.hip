@@ -1137,93 +1137,77 @@ __global__ __launch_bounds__(kSubThreads, 1) void k_walk_sub(WalkLevelArgs a) {
 // Dense level step: every pool of a level against every query, as a matrix
 // product with a masked epilogue.  Used where almost every (pool, query tile)
 // pair is live (the first tested level): each pool row is read once per
-// 256-query column block instead of once per tile.  A workgroup (8 waves)
-// computes 256 pools x 256 queries (4 tiles); wave w owns pools 64 (w / 2)
-// .. +63 and tiles 2 (w % 2), 2 (w % 2) + 1 (2 x 4 blocks of 32x32
-// matrix-core tiles).  K advances 128 bytes per row per stage: a stage's
-// global loads (each instruction moves 8 rows x 128 contiguous bytes) are
-// issued one stage ahead into registers, then written to one of two LDS
-// buffers.  Within a row the 16-byte chunks are stored XOR-swizzled
-// so that the matrix-core operand reads of any aligned 8 or 16 lanes hit
-// distinct LDS banks.  Child j of level L survives for query b iff its
-// parent's bit b is set and its score reaches tau'_b.  Output: per-(pool,
-// tile) masks for a following dense level, or the bucketed sparse frontier
-// for the walk that follows.
+// 256-query column block instead of once per tile.  A workgroup (4 waves, one
+// per SIMD) computes 256 pools x 256 queries (4 tiles); wave w owns pools
+// 128 (w / 2) .. +127 and tiles 2 (w % 2), 2 (w % 2) + 1: 4 x 4 blocks of
+// 32x32 matrix-core tiles whose accumulators fill the wave's accumulation
+// registers, so that every 16-byte operand read from LDS feeds four matrix
+// products.  K advances 128 bytes per row per stage.  A stage is loaded
+// straight from global memory into LDS (no staging registers) one stage
+// ahead, into the other of two buffers; within a stage the operands of the
+// next K step are read from LDS while the current step's matrix products
+// run, and the next stage's first step is read across the stage's barrier.
+// Child j of level L survives for query b iff its parent's bit b is set and
+// its score reaches tau'_b.  Output: per-(pool, tile) masks for a following
+// dense level, or the bucketed sparse frontier for the walk that follows.
+//
+// LDS layout of a stage: two regions (pool rows, query rows) of 256 rows x
+// 128 bytes, each in 32 blocks of 8 rows; row R of a region is row R / 32 of
+// block R % 32, and the blocks are 1040 bytes apart.  The 16-byte skew per
+// block puts the same chunk of 8 (or 16) consecutive rows on distinct banks,
+// so operand reads are conflict-free, and every read of a wave is one base
+// register plus an immediate offset.  One direct-to-LDS load instruction
+// fills one block (its 64 lanes write 1 KB contiguously).
 constexpr int kDM = 256, kDN = 256, kDK = 128;  // pools, queries, K bytes per stage
-constexpr int kDStageA = kDM * kDK, kDStage = (kDM + kDN) * kDK;  // 32 KB + 32 KB
-constexpr int kDThreads = 512;
+constexpr int kDBlk = 8 * kDK + 16;             // block pitch
+constexpr int kDRegion = 32 * kDBlk;
+constexpr int kDStage = 2 * kDRegion;           // 2 x 32.5 KB
+constexpr int kDThreads = 256;
 constexpr int kDTiles = kDN / 64;  // query tiles per workgroup
 
-// physical 16-byte chunk of logical chunk c in LDS row r: c ^ dswz(r)
-__device__ __forceinline__ int dswz(int r) { return (r + (r >> 3)) & 7; }
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
-// The eight load slots of a thread in a dense stage (see k_dense_level):
-// slots 0-3 are pool rows lr0 + 64 m, slots 4-7 query rows lr0 + 64 (m - 4).
-struct DenseSlots {
-  int lr0, lc, rowbytes;
-  int64_t row0, rows;
-  int q0, qrows;  // first query row of the workgroup; query rows that exist
-  const unsigned char* crow;
-  const unsigned char* qrow;
+// A thread's 16 direct-to-LDS loads of a stage: instructions j = w + 4 m of
+// wave w (j < 32: pool block j, else query block j - 32).  Lane l of an
+// instruction writes byte 16 l of its block, i.e. chunk l % 8 of block row
+// l / 8, which is region row 32 (l / 8) + block.  Sources are 32-bit offsets
+// from the workgroup's first pool row and first query row.  Rows past the
+// last pool re-read the last pool; query rows past the last tile re-read the
+// last query row (their columns are never tested).
+struct DenseLoads {
+  const unsigned char* pool;   // first pool row of the workgroup
+  const unsigned char* query;  // first query row of the workgroup
+  uint32_t off[16];
 };
-__device__ __forceinline__ void dense_slot(const DenseSlots& d, int m, const unsigned char*& g,
-                                           int& l) {
-  const int lr = d.lr0 + 64 * (m & 3);  // row within the pool or query block
-  const int off = 16 * (d.lc ^ dswz(lr));
-  if (m < 4) {
-    const int64_t gr = d.row0 + lr < d.rows ? d.row0 + lr : d.rows - 1;
-    g = d.crow + (size_t)gr * d.rowbytes + 16 * d.lc;
-    l = lr * kDK + off;
-  } else {
-    // query rows past the last tile re-read the last row; their columns are
-    // never tested
-    const int qr = d.q0 + lr < d.qrows ? d.q0 + lr : d.qrows - 1;
-    g = d.qrow + (size_t)qr * d.rowbytes + 16 * d.lc;
-    l = kDStageA + lr * kDK + off;
+__device__ __forceinline__ void dense_sources(DenseLoads& L, int rowbytes, int64_t row0,
+                                              int64_t rows, int q0, int qrows, int wave,
+                                              int lane) {
+  const int plim = (int)min(rows - row0, (int64_t)kDM), qlim = min(qrows - q0, kDN);
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int j = wave + 4 * m;                 // instruction of the stage
+    const int R = 32 * (lane >> 3) + (j & 31);  // region row
+    const int lim = j < 32 ? plim : qlim;
+    const int rr = R < lim ? R : lim - 1;
+    L.off[m] = (uint32_t)rr * (uint32_t)rowbytes + 16u * (uint32_t)(lane & 7);
   }
 }
-// One register set of a stage: eight 16-byte slots, kept as separate values
-// so that they live in registers.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-struct DenseRegs {
-  u32x4 v[8];
-};
-template <int M>
-__device__ __forceinline__ void dense_gload1(const DenseSlots& d, int ss, DenseRegs& R) {
-  const unsigned char* g;
-  int l;
-  dense_slot(d, M, g, l);
-  R.v[M] = *reinterpret_cast<const u32x4*>(g + ss * kDK);
-}
-template <int M>
-__device__ __forceinline__ void dense_lwrite1(const DenseSlots& d, const DenseRegs& R,
-                                              unsigned char* buf) {
-  const unsigned char* g;
-  int l;
-  dense_slot(d, M, g, l);
-  *reinterpret_cast<u32x4*>(buf + l) = R.v[M];
-}
-__device__ __forceinline__ void dense_gload(const DenseSlots& d, int s, int slast, DenseRegs& R) {
-  const int ss = s < slast ? s : slast;
-  dense_gload1<0>(d, ss, R);
-  dense_gload1<1>(d, ss, R);
-  dense_gload1<2>(d, ss, R);
-  dense_gload1<3>(d, ss, R);
-  dense_gload1<4>(d, ss, R);
-  dense_gload1<5>(d, ss, R);
-  dense_gload1<6>(d, ss, R);
-  dense_gload1<7>(d, ss, R);
-}
-__device__ __forceinline__ void dense_lwrite(const DenseSlots& d, const DenseRegs& R,
-                                             unsigned char* buf) {
-  dense_lwrite1<0>(d, R, buf);
-  dense_lwrite1<1>(d, R, buf);
-  dense_lwrite1<2>(d, R, buf);
-  dense_lwrite1<3>(d, R, buf);
-  dense_lwrite1<4>(d, R, buf);
-  dense_lwrite1<5>(d, R, buf);
-  dense_lwrite1<6>(d, R, buf);
-  dense_lwrite1<7>(d, R, buf);
+// (instruction m of wave w fills block w + 4 m of the pool region for m < 8,
+// block w + 4 m - 32 of the query region after; the destination is the
+// wave's offset plus a constant.  The empty asm keeps that offset from being
+// treated as loop-invariant: otherwise all 32 destinations are precomputed
+// and held in scalar registers through the loop.)
+__device__ __forceinline__ void dense_issue(const DenseLoads& L, unsigned char* buf, int s,
+                                            uint32_t wave_off) {
+  asm volatile("" : "+s"(wave_off));
+  const unsigned char* ps = L.pool + s * kDK;
+  const unsigned char* qs = L.query + s * kDK;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const uint32_t c = m < 8 ? 4 * m * kDBlk : kDRegion + (4 * m - 32) * kDBlk;
+    __builtin_amdgcn_global_load_lds((const void*)((m < 8 ? ps : qs) + L.off[m]),
+                                     (lds_void_ptr)(buf + wave_off + c), 16, 0, 0);
+  }
 }
 
 // Thresholds of tile t for the two 32-query halves a lane's accumulator
@@ -1239,109 +1223,122 @@ __device__ __forceinline__ void dense_thresholds(const DenseLevelArgs& a, int t,
   }
 }
 
-// Output of one 32-pool block (rows rb0 .. rb0 + 31) against tile t: c0 and
-// c1 are the 32x32 accumulators of the tile's query halves.  Lane l holds
-// query column l % 32 of rows 8 (x / 4) + 4 (l / 32) + x % 4 (register x).
-// Survival bits by ballots (lane r < 32 ends with row r's 64-query mask),
-// ANDed with the parent masks; then per-(pool, tile) masks for a following
-// dense level, or the bucketed sparse frontier (and, for the subtraction
-// step, the kept pools' score records).
-template <int FMT>
-__device__ __forceinline__ void dense_block_out(const DenseLevelArgs& a, const f32x16& c0,
-                                                const f32x16& c1, int64_t rb0, int t,
-                                                const float (&thr)[2], int lane,
-                                                unsigned long long& pairs) {
-  const int r = lane & 31, half = lane >> 5;
-  const int64_t rows = a.rows;
-  const int bshift = a.level - a.nb;  // node -> bucket of the sparse output
-  const int64_t row = rb0 + r;
-  const bool rv = lane < 32 && row < rows;
-  uint64_t pm = 0ull;
-  if (rv) pm = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
-  uint64_t mine = 0ull;
+// Survival mask of one 32-pool block against tile t: c0 and c1 are the
+// 32x32 accumulators of the tile's query halves.  Lane l holds query column
+// l % 32 of rows 8 (x / 4) + 4 (l / 32) + x % 4 (register x), so the ballot
+// of register x over a query half holds, in its low 32 bits, row
+// 8 (x / 4) + x % 4 and, in its high 32 bits, the row 4 below; each half is
+// selected into that row's lane.  Lane r < 32 ends with row r's
+// 64-query mask (other lanes: 0).
+__device__ __forceinline__ uint64_t dense_block_mask(const f32x16& c0, const f32x16& c1,
+                                                     const float (&thr)[2], int lane) {
+  uint32_t mlo = 0u, mhi = 0u;  // queries 0-31 and 32-63
 #pragma unroll
   for (int x = 0; x < 16; ++x) {
     const uint64_t b0 = __ballot(c0[x] >= thr[0]);
     const uint64_t b1 = __ballot(c1[x] >= thr[1]);
-    const uint64_t lo = (b0 & 0xffffffffull) | (b1 << 32);
-    const uint64_t hi = (b0 >> 32) | (b1 & 0xffffffff00000000ull);
     const int rr = 8 * (x >> 2) + (x & 3);
-    if (lane == rr) mine = lo;
-    if (lane == rr + 4) mine = hi;
-  }
-  mine &= pm;
-  if (rv) pairs += (unsigned long long)__popcll(pm);
-  if (a.bitmap && rv && pm) atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
-  const uint64_t eb = __ballot(rv && mine != 0ull);
-  int64_t oe = -1;  // output entry of this lane's row
-  if (a.out_dense) {
-    if (rv) a.out_dense[row * a.nt + t] = mine;
-    if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
-  } else if (eb && bshift >= 5) {
-    // the 32 rows (aligned) share one bucket: one reservation per wave
-    const uint32_t slot = (uint32_t)(rb0 >> bshift) * (uint32_t)a.nt + t;
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&a.out_count[slot], (uint32_t)__popcll(eb));
-    base = __shfl(base, 0, 64);
-    if (rv && mine) {
-      const uint32_t pos = base + (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
-      if (pos < a.bcap) {
-        const size_t o = (size_t)slot * a.bcap + pos;
-        a.out_node[o] = (uint32_t)row;
-        a.out_mask[o] = mine;
-        oe = (int64_t)o;
-      } else {
-        atomicOr(a.over, 1u);
-      }
+    if (lane == rr) {
+      mlo = (uint32_t)b0;
+      mhi = (uint32_t)b1;
     }
-  } else if (eb && rv && mine) {
-    const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
-    const uint32_t pos = atomicAdd(&a.out_count[slot], 1u);
-    if (pos < a.bcap) {
-      const size_t o = (size_t)slot * a.bcap + pos;
-      a.out_node[o] = (uint32_t)row;
-      a.out_mask[o] = mine;
-      oe = (int64_t)o;
-    } else {
-      atomicOr(a.over, 1u);
+    if (lane == rr + 4) {
+      mlo = (uint32_t)(b0 >> 32);
+      mhi = (uint32_t)(b1 >> 32);
     }
+    // (the empty asm makes each register's ballots be used at once: left to
+    // itself the compiler gathers all 32 wave-wide results first, and they
+    // overflow the scalar registers)
+    asm volatile("" : "+v"(mlo), "+v"(mhi));
   }
-  if (FMT == GT_POOL_BF16 && a.out_rec && eb) {
-    // score record of every kept pool: upper bounds of its real score for
-    // all 64 queries of the tile, query q at 4 (q % 16) + q / 16.  Lanes l
-    // and l ^ 16 together hold the four queries c, 16 + c, 32 + c, 48 + c
-    // (c = l % 16) of a row.  For a pair of registers x, x + 1 the lower lane
-    // of the two writes row x, the upper row x + 1.
-    const float aup = score_abs_up(a.dp);
-    const bool up = (r >> 4) & 1;
+  return ((uint64_t)mhi << 32) | mlo;
+}
+
+// Score records of the kept pools (subtraction step): upper bounds of each
+// pool's real score for all 64 queries of the tile, query q at
+// 4 (q % 16) + q / 16 of the pool's 128-byte record.  A block's bounds are
+// first written to LDS in record order (32 rows x 128 bytes), then the kept
+// rows are copied out with 16-byte accesses.  Lane l holds queries l % 32
+// (c0) and 32 + l % 32 (c1) of rows 8 (x / 4) + 4 (l / 32) + x % 4
+// (register x): two 16-bit writes per register at fixed offsets from the
+// lane's base.
+__device__ __forceinline__ void dense_stage_records(unsigned char* blk, float aup,
+                                                    const f32x16& c0, const f32x16& c1,
+                                                    int lane) {
+  const int q = lane & 15, hi16 = (lane >> 4) & 1;
+  unsigned char* base = blk + (lane >> 5) * 4 * 128 + 8 * q + 2 * hi16;
 #pragma unroll
-    for (int x = 0; x < 16; x += 2) {
-      // bounds as the high halves of 32-bit words
-      const uint32_t lo0 = bf16_ceil_hi(score_upper(c0[x], aup));
-      const uint32_t lo1 = bf16_ceil_hi(score_upper(c1[x], aup));
-      const uint32_t hi0 = bf16_ceil_hi(score_upper(c0[x + 1], aup));
-      const uint32_t hi1 = bf16_ceil_hi(score_upper(c1[x + 1], aup));
-      // keep the row this lane writes, send the other to lane l ^ 16
-      // (queries r and 32 + r of it, as the low and high half)
-      const uint32_t send = up ? ((lo0 >> 16) | lo1) : ((hi0 >> 16) | hi1);
-      const uint32_t got = (uint32_t)__shfl_xor((int)send, 16, 64);
-      const int xr = up ? x + 1 : x;
-      const int64_t o = __shfl(oe, 8 * (xr >> 2) + 4 * half + (xr & 3), 64);
-      // own values are queries r and 32 + r; slots qb = 0..3 of the record
-      // are queries c, 16 + c, 32 + c, 48 + c
-      const uint32_t m0 = up ? hi0 : lo0, m1 = up ? hi1 : lo1;
-      uint2 v;
-      v.x = up ? ((got & 0xFFFFu) | m0) : ((m0 >> 16) | (got << 16));
-      v.y = up ? ((got >> 16) | m1) : ((m1 >> 16) | (got & 0xFFFF0000u));
-      if (o >= 0) *reinterpret_cast<uint2*>(a.out_rec + (size_t)o * 64 + 4 * (r & 15)) = v;
-    }
+  for (int x = 0; x < 16; ++x) {
+    const int rr = 8 * (x >> 2) + (x & 3);
+    const uint32_t v0 = bf16_ceil_hi(score_upper(c0[x], aup));
+    const uint32_t v1 = bf16_ceil_hi(score_upper(c1[x], aup));
+    *reinterpret_cast<uint16_t*>(base + rr * 128) = (uint16_t)(v0 >> 16);
+    *reinterpret_cast<uint16_t*>(base + rr * 128 + 4) = (uint16_t)(v1 >> 16);
   }
+}
+// Copies the records of the kept rows of a staged block: oe, lane r < 32, is
+// the output entry of row r (-1: not kept).  Lane l moves chunk l % 8 of rows
+// l / 8 + 8 k.
+__device__ __forceinline__ void dense_copy_records(uint16_t* out_rec, const unsigned char* blk,
+                                                   int64_t oe, int lane) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int row = (lane >> 3) + 8 * k;
+    const int64_t o = __shfl(oe, row, 64);
+    const uint4 v = *reinterpret_cast<const uint4*>(blk + row * 128 + 16 * (lane & 7));
+    if (o >= 0) *reinterpret_cast<uint4*>(out_rec + (size_t)o * 64 + 8 * (lane & 7)) = v;
+  }
+}
+
+// Operands of one K step of a wave: bf16, 16 elements (one 32x32x16
+// product per block pair); float8, 64 elements (one 32x32x64 product).
+// Lanes 0-31 and 32-63 carry different K ranges, the same in A and B.
+template <int FMT>
+struct DenseOps {
+  static constexpr int NC = FMT == GT_POOL_FP8E4M3 ? 2 : 1;  // 16-byte chunks per lane
+  uint4 a[4][NC], b[4][NC];
+};
+// Lane (r, half) reads, for block i of its pool rows (region row
+// 128 wr + 32 i + r: block r, block row 4 wr + i) and K step st, chunks
+// NC (2 st + half) + h: base + 128 i + 16 (2 NC st + h), with
+// base = 1040 r + 512 wr + 16 NC half (queries alike with wq, in the second
+// region).
+template <int FMT>
+__device__ __forceinline__ void dense_read(const unsigned char* buf, int st, uint32_t abase,
+                                           uint32_t bbase, DenseOps<FMT>& o) {
+  constexpr int NC = DenseOps<FMT>::NC;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int h = 0; h < NC; ++h)
+      o.a[i][h] = *reinterpret_cast<const uint4*>(buf + abase + kDK * i + 16 * (2 * NC * st + h));
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int h = 0; h < NC; ++h)
+      o.b[j][h] = *reinterpret_cast<const uint4*>(buf + bbase + kDK * j + 16 * (2 * NC * st + h));
+}
+template <int FMT, int I0, int I1>
+__device__ __forceinline__ void dense_mma(const DenseOps<FMT>& o, f32x16 (&acc)[4][4]) {
+#pragma unroll
+  for (int i = I0; i < I1; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (FMT == GT_POOL_FP8E4M3)
+        mma_f8_32x32x64(o.a[i][0], o.a[i][1], o.b[j][0], o.b[j][1], acc[i][j]);
+      else
+        mma16<FMT>(o.a[i][0], o.b[j][0], acc[i][j]);
+    }
 }
 
 template <int FMT>
 __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) {
   using F = WalkFmt<FMT>;
   static_assert(F::TQ == 64, "dense steps use 64-query tiles");
+  // K steps per stage: bf16 steps of 32 bytes, float8 steps of 64 bytes
+  constexpr int NS = FMT == GT_POOL_FP8E4M3 ? 2 : 4;
+  // (two separate arrays: a read of one is then known not to depend on the
+  // loads in flight into the other)
   __shared__ __attribute__((aligned(1024))) unsigned char lds0[kDStage];
   __shared__ __attribute__((aligned(1024))) unsigned char lds1[kDStage];
   const int64_t rows = a.rows;  // pools holding a row below the call's epoch
@@ -1355,129 +1352,208 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
   if (wid >= total) return;
   const int qb = (int)(wid % QB);
   const int64_t row0 = (wid / QB) * kDM;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wq = wave & 1;
   const int r = lane & 31, half = lane >> 5;
   const int rowbytes = a.dp * F::ESZ;
   const int nst = rowbytes / kDK;
-  const int slast = nst - 1;
 
-  // A stage is 64 load instructions of 8 rows x 128 bytes (32 for the pool
-  // rows, 32 for the query rows); wave w issues instructions w + 8 m.  Lane l
-  // moves chunk l % 8 of row l / 8 of the instruction.
-  DenseSlots sl8;
-  sl8.lr0 = wave * 8 + (lane >> 3);
-  sl8.lc = lane & 7;
-  sl8.row0 = row0;
-  sl8.rows = rows;
-  sl8.q0 = qb * kDN;
-  sl8.qrows = a.nt * 64;
-  sl8.crow = reinterpret_cast<const unsigned char*>(a.child_rows);
-  sl8.qrow = reinterpret_cast<const unsigned char*>(a.qtile);
-  sl8.rowbytes = rowbytes;
+  const uint32_t wave_off = (uint32_t)(wave * kDBlk);
+  DenseLoads L;
+  L.pool = reinterpret_cast<const unsigned char*>(a.child_rows) + (size_t)row0 * rowbytes;
+  L.query = reinterpret_cast<const unsigned char*>(a.qtile) + (size_t)qb * kDN * rowbytes;
+  dense_sources(L, rowbytes, row0, rows, qb * kDN, a.nt * 64, wave, lane);
+  constexpr int NC = DenseOps<FMT>::NC;
+  const uint32_t abase = (uint32_t)(kDBlk * r + 4 * kDK * wr + 16 * NC * half);
+  const uint32_t bbase = (uint32_t)(kDRegion + kDBlk * r + 4 * kDK * wq + 16 * NC * half);
 
-  f32x16 acc[2][4];
+  f32x16 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int x = 0; x < 16; ++x) acc[i][j][x] = 0.0f;
 
-  auto compute = [&](const unsigned char* As) {
-    const unsigned char* Bs = As + kDStageA;
-    if constexpr (FMT == GT_POOL_FP8E4M3) {
-      // one 32x32x64 product per 64 bytes of K: lanes 0-31 take chunks 0-1
-      // of the 64-byte block, lanes 32-63 chunks 2-3, the same in A and B
-#pragma unroll
-      for (int sl = 0; sl < kDK / 64; ++sl) {
-        const int c0 = 4 * sl + 2 * half;
-        uint4 av[2][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int ar = wr * 64 + i * 32 + r;
-#pragma unroll
-          for (int h = 0; h < 2; ++h)
-            av[i][h] = *reinterpret_cast<const uint4*>(As + ar * kDK + 16 * ((c0 + h) ^ dswz(ar)));
-        }
-        // (query fragments one block at a time: the accumulators leave little room)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int br = wq * 128 + j * 32 + r;
-          const uint4 b0 = *reinterpret_cast<const uint4*>(Bs + br * kDK + 16 * (c0 ^ dswz(br)));
-          const uint4 b1 = *reinterpret_cast<const uint4*>(Bs + br * kDK + 16 * ((c0 + 1) ^ dswz(br)));
-          mma_f8_32x32x64(av[0][0], av[0][1], b0, b1, acc[0][j]);
-          mma_f8_32x32x64(av[1][0], av[1][1], b0, b1, acc[1][j]);
-        }
-      }
-      return;
-    }
-#pragma unroll
-    for (int sl = 0; sl < kDK / 32; ++sl) {
-      const int c = 2 * sl + half;
-      uint4 av[2], bv[4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int ar = wr * 64 + i * 32 + r;
-        av[i] = *reinterpret_cast<const uint4*>(As + ar * kDK + 16 * (c ^ dswz(ar)));
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int br = wq * 128 + j * 32 + r;
-        bv[j] = *reinterpret_cast<const uint4*>(Bs + br * kDK + 16 * (c ^ dswz(br)));
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) mma16<FMT>(av[i], bv[j], acc[i][j]);
-    }
-  };
-  // Step s: stage s is in LDS buffer s % 2 and stage s + 1 in flight into the
-  // register set.  After the barrier (every wave is done with stage s - 1,
-  // whose buffer now takes stage s + 1) the set is written out and refilled
-  // with stage s + 2, and stage s is multiplied: a load has one stage of
-  // matrix work (32 MFMAs per wave) to arrive.  Loads past the last stage
-  // re-read it.
-  DenseRegs R;
-  dense_gload(sl8, 0, slast, R);
-  dense_lwrite(sl8, R, lds0);
-  dense_gload(sl8, 1, slast, R);
-  // stage pairs, so that both halves of the loop body keep the accumulators
-  // in the same registers; an odd last stage follows the loop
-  int s = 0;
-  // (the scheduling barriers keep each stage's loads ahead of the matrix
-  // work they are meant to overlap; the compiler would otherwise sink them)
-  for (; s + 1 < nst; s += 2) {
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's LDS accesses are done
-    __builtin_amdgcn_s_barrier();
-    dense_lwrite(sl8, R, lds1);
-    dense_gload(sl8, s + 2, slast, R);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(lds0);
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    __builtin_amdgcn_s_barrier();
-    dense_lwrite(sl8, R, lds0);
-    dense_gload(sl8, s + 3, slast, R);
-    __builtin_amdgcn_sched_barrier(0);
-    compute(lds1);
-  }
-  if (s < nst) {
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    __builtin_amdgcn_s_barrier();
-    compute(lds0);
-  }
-
-  unsigned long long pairs = 0;
+  // Output inputs, loaded now so that they arrive during the products: the
+  // thresholds of the wave's two tiles and the parent masks of its 8 blocks
+  // of 32 pools (lane r < 32: pool row r of the block).
+  float thr[2][2];
+  uint64_t pm[2][4];
 #pragma unroll
   for (int tt = 0; tt < 2; ++tt) {
     const int t = qb * kDTiles + 2 * wq + tt;
-    if (t >= a.nt) break;
-    float thr[2];
-    dense_thresholds<FMT>(a, t, r, thr);
+    thr[tt][0] = thr[tt][1] = 0.0f;
+    if (t < a.nt) dense_thresholds<FMT>(a, t, r, thr[tt]);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-      dense_block_out<FMT>(a, acc[i][2 * tt], acc[i][2 * tt + 1], row0 + wr * 64 + i * 32, t, thr,
-                           lane, pairs);
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = row0 + wr * 128 + i * 32 + r;
+      pm[tt][i] = 0ull;
+      if (t < a.nt && lane < 32 && row < rows)
+        pm[tt][i] = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
+    }
+  }
+
+  // Stage s sits in buffer s % 2.  Stage s + 1 is loaded while stage s is
+  // multiplied.  At the last K step of stage s a barrier, after this wave's
+  // reads of stage s and its loads of stage s + 1 are complete, tells that
+  // every wave is done with stage s (its buffer then takes stage s + 2) and
+  // that stage s + 1 has landed; the first step of stage s + 1 is read while
+  // the last step of stage s is multiplied.  The scheduling barriers keep
+  // each step's LDS reads ahead of the matrix work that hides them.
+  // (operands alternate between two register sets by the parity of the K
+  // step, which is static: a stage has an even number of steps.  The loop
+  // runs an even number of stages and holds no data-dependent branch around
+  // the reads, so that both sets keep their registers: for an odd number of
+  // K stages, position 0 is a stage of zeros and position p holds K stage
+  // p - 1.  A step issues its first row of products before the next step's
+  // reads: with direct-to-LDS loads in flight the compiler waits for all LDS
+  // reads before a step's products, and by then they have had the other
+  // twelve products' time.)
+  DenseOps<FMT> ops[2];
+  const int odd = nst & 1, npos = nst + odd;
+  L.pool -= odd * kDK;
+  L.query -= odd * kDK;
+  // One position from buffer cb; with `next`, its last step crosses the
+  // barrier into position p + 1 in buffer nb and, if `issue`, loads position
+  // p + 2 into cb.
+  auto stage = [&](unsigned char* cb, unsigned char* nb, int p, bool next, bool issue) {
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const DenseOps<FMT>& cu = ops[st & 1];
+      DenseOps<FMT>& nx = ops[(st + 1) & 1];
+      dense_mma<FMT, 0, 1>(cu, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      if (st + 1 < NS) {
+        dense_read<FMT>(cb, st + 1, abase, bbase, nx);
+      } else if (next) {
+        __builtin_amdgcn_s_waitcnt(0x0070);  // vmcnt(0) lgkmcnt(0)
+        __syncthreads();
+        if (issue) dense_issue(L, cb, p + 2, wave_off);
+        dense_read<FMT>(nb, 0, abase, bbase, nx);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      dense_mma<FMT, 1, 4>(cu, acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  if (odd) {
+    for (int i = tid; i < kDStage / 16; i += kDThreads)
+      *reinterpret_cast<uint4*>(lds0 + 16 * i) = make_uint4(0u, 0u, 0u, 0u);
+  } else {
+    dense_issue(L, lds0, 0, wave_off);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0070);
+  __syncthreads();
+  dense_issue(L, lds1, 1, wave_off);
+  dense_read<FMT>(lds0, 0, abase, bbase, ops[0]);
+  int p = 0;
+  for (; p + 3 < npos; p += 2) {  // positions p + 2 and p + 3 exist
+    stage(lds0, lds1, p, true, true);
+    stage(lds1, lds0, p + 1, true, true);
+  }
+  stage(lds0, lds1, p, true, false);
+  stage(lds1, lds0, p + 1, false, false);
+
+  // Output: the wave's 8 blocks (tile tt, pool block i).  Child j survives
+  // for query b iff its parent's bit b is set and its score reaches tau'_b.
+  // All blocks' masks first, then one batch of frontier reservations (their
+  // round trips overlap), then the writes: per-(pool, tile) masks for a
+  // following dense level, or the bucketed sparse frontier (and, for the
+  // subtraction step, the kept pools' score records).
+  const int bshift = a.level - a.nb;  // node -> bucket of the sparse output
+  unsigned long long pairs = 0;
+  uint64_t mine[2][4];
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = row0 + wr * 128 + i * 32 + r;
+      mine[tt][i] = dense_block_mask(acc[i][2 * tt], acc[i][2 * tt + 1], thr[tt], lane) & pm[tt][i];
+      pairs += (unsigned long long)__popcll(pm[tt][i]);
+      if (a.bitmap && pm[tt][i])
+        atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
+    }
+  if (a.out_dense) {
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+      const int t = qb * kDTiles + 2 * wq + tt;
+      if (t >= a.nt) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + wr * 128 + i * 32 + r;
+        if (lane < 32 && row < rows) a.out_dense[row * a.nt + t] = mine[tt][i];
+        const uint64_t eb = __ballot(mine[tt][i] != 0ull);
+        if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
+      }
+    }
+  } else {
+    // reservations: one per block when its 32 rows (aligned) share a bucket,
+    // else one per row
+    uint32_t res[2][4];
+    int64_t oe[2][4];  // output entry of this lane's row (-1: none)
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = qb * kDTiles + 2 * wq + tt;
+        const int64_t rb0 = row0 + wr * 128 + i * 32;
+        const uint64_t eb = __ballot(mine[tt][i] != 0ull);
+        res[tt][i] = 0u;
+        oe[tt][i] = -1;
+        if (bshift >= 5) {
+          if (lane == 0 && eb)
+            res[tt][i] = atomicAdd(&a.out_count[(uint32_t)(rb0 >> bshift) * (uint32_t)a.nt + t],
+                                   (uint32_t)__popcll(eb));
+        } else if (mine[tt][i]) {
+          res[tt][i] =
+              atomicAdd(&a.out_count[(uint32_t)((rb0 + r) >> bshift) * (uint32_t)a.nt + t], 1u);
+        }
+      }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = qb * kDTiles + 2 * wq + tt;
+        const int64_t row = row0 + wr * 128 + i * 32 + r;
+        const uint64_t eb = __ballot(mine[tt][i] != 0ull);
+        if (!eb) continue;
+        const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
+        const uint32_t pos =
+            bshift >= 5 ? (uint32_t)__builtin_amdgcn_readfirstlane(res[tt][i]) +
+                              (uint32_t)__popcll(eb & ((1ull << lane) - 1ull))
+                        : res[tt][i];
+        if (mine[tt][i]) {
+          if (pos < a.bcap) {
+            const int64_t o = (int64_t)slot * a.bcap + pos;
+            oe[tt][i] = o;
+            a.out_node[o] = (uint32_t)row;
+            a.out_mask[o] = mine[tt][i];
+          } else {
+            atomicOr(a.over, 1u);
+          }
+        }
+      }
+    if (FMT == GT_POOL_BF16 && a.out_rec) {
+      // (the stage buffers are free once every wave is past its last reads;
+      // each wave stages its 8 blocks in 32 KB of its own)
+      __syncthreads();
+      unsigned char* region = (wave < 2 ? lds0 : lds1) + (wave & 1) * 32768;
+      const float aup = score_abs_up(a.dp);
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          dense_stage_records(region + (tt * 4 + i) * 4096, aup, acc[i][2 * tt],
+                              acc[i][2 * tt + 1], lane);
+      __syncthreads();
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          dense_copy_records(a.out_rec, region + (tt * 4 + i) * 4096, oe[tt][i], lane);
+    }
   }
   if (a.stat_pairs) {
     for (int o = 32; o >= 1; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
