@@ -476,6 +476,16 @@ def main():
             r2, wall2, lat2 = run(pool, args.side_steps, 1)
             comparators[f"walk_{pool}_qps"] = round(args.nq * args.side_steps / wall2, 1)
             comparators[f"walk_{pool}_ms"] = round(wall2 / args.side_steps * 1e3, 3)
+            if pool == "fp8":
+                # the precision variant in the headline's own launch shape
+                # (batches back to back over the same workspaces and streams)
+                rp, wp = run_pipelined(pool, args.steps, args.warmup, args.streams)
+                comparators["walk_fp8_pipelined_qps"] = round(args.nq * args.steps / wp, 1)
+                comparators["walk_fp8_pipelined_ms"] = round(wp / args.steps * 1e3, 4)
+                comparators["walk_fp8_ids_identical"] = rp.total == res.total and all(
+                    np.array_equal(a[0], b[0]) for a, b in zip(rp.to_lists(), res.to_lists()))
+                log(f"fp8 walk, batches back to back: {comparators['walk_fp8_pipelined_ms']} ms/batch, "
+                    f"{comparators['walk_fp8_pipelined_qps']:.0f} queries/s")
             if pool == "max_bf16":
                 # Our-Max pools (paper Sec. 2): same result set, other pruning
                 comparators["walk_max_bf16_results_identical"] = r2.total == res.total and all(

@@ -1341,6 +1341,10 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
   // loads in flight into the other)
   __shared__ __attribute__((aligned(1024))) unsigned char lds0[kDStage];
   __shared__ __attribute__((aligned(1024))) unsigned char lds1[kDStage];
+  // output reservations of the workgroup: entries per (tile, bucket) of its
+  // 256 pools (at most 8 buckets once a bucket holds 32 pools or more), and
+  // the slots' bases
+  __shared__ uint32_t wg_cnt[kDTiles][8], wg_base[kDTiles][8];
   const int64_t rows = a.rows;  // pools holding a row below the call's epoch
   const int64_t RB = (rows + kDM - 1) / kDM;
   const int QB = (a.nt + kDTiles - 1) / kDTiles;
@@ -1375,25 +1379,6 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int x = 0; x < 16; ++x) acc[i][j][x] = 0.0f;
-
-  // Output inputs, loaded now so that they arrive during the products: the
-  // thresholds of the wave's two tiles and the parent masks of its 8 blocks
-  // of 32 pools (lane r < 32: pool row r of the block).
-  float thr[2][2];
-  uint64_t pm[2][4];
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt) {
-    const int t = qb * kDTiles + 2 * wq + tt;
-    thr[tt][0] = thr[tt][1] = 0.0f;
-    if (t < a.nt) dense_thresholds<FMT>(a, t, r, thr[tt]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t row = row0 + wr * 128 + i * 32 + r;
-      pm[tt][i] = 0ull;
-      if (t < a.nt && lane < 32 && row < rows)
-        pm[tt][i] = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
-    }
-  }
 
   // Stage s sits in buffer s % 2.  Stage s + 1 is loaded while stage s is
   // multiplied.  At the last K step of stage s a barrier, after this wave's
@@ -1438,6 +1423,7 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
       __builtin_amdgcn_sched_barrier(0);
     }
   };
+  if (tid < kDTiles * 8) (&wg_cnt[0][0])[tid] = 0u;
   if (odd) {
     for (int i = tid; i < kDStage / 16; i += kDThreads)
       *reinterpret_cast<uint4*>(lds0 + 16 * i) = make_uint4(0u, 0u, 0u, 0u);
@@ -1458,10 +1444,27 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
 
   // Output: the wave's 8 blocks (tile tt, pool block i).  Child j survives
   // for query b iff its parent's bit b is set and its score reaches tau'_b.
-  // All blocks' masks first, then one batch of frontier reservations (their
-  // round trips overlap), then the writes: per-(pool, tile) masks for a
-  // following dense level, or the bucketed sparse frontier (and, for the
-  // subtraction step, the kept pools' score records).
+  // All blocks' masks first; the workgroup's frontier reservations are then
+  // gathered in LDS and made with one atomic per (bucket, tile) slot (the
+  // slot counters share a few cache lines, and one atomic per block and wave
+  // queues on them); then the writes: per-(pool, tile) masks for a following
+  // dense level, or the bucketed sparse frontier (and, for the subtraction
+  // step, the kept pools' score records).
+  float thr[2][2];
+  uint64_t pm[2][4];  // parent masks (lane r < 32: pool row r of the block)
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int t = qb * kDTiles + 2 * wq + tt;
+    thr[tt][0] = thr[tt][1] = 0.0f;
+    if (t < a.nt) dense_thresholds<FMT>(a, t, r, thr[tt]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = row0 + wr * 128 + i * 32 + r;
+      pm[tt][i] = 0ull;
+      if (t < a.nt && lane < 32 && row < rows)
+        pm[tt][i] = a.parent ? a.parent[(row >> 1) * a.nt + t] : a.tile_mask[t];
+    }
+  }
   const int bshift = a.level - a.nb;  // node -> bucket of the sparse output
   unsigned long long pairs = 0;
   uint64_t mine[2][4];
@@ -1476,23 +1479,26 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
         atomicOr(&a.bitmap[(a.bit_base + row) >> 5], 1u << ((a.bit_base + row) & 31));
     }
   if (a.out_dense) {
+    // non-empty masks per tile, one atomic per tile and workgroup
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int t = qb * kDTiles + 2 * wq + tt;
-      if (t >= a.nt) break;
+    for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        const int t = qb * kDTiles + 2 * wq + tt;
         const int64_t row = row0 + wr * 128 + i * 32 + r;
-        if (lane < 32 && row < rows) a.out_dense[row * a.nt + t] = mine[tt][i];
+        if (t < a.nt && lane < 32 && row < rows) a.out_dense[row * a.nt + t] = mine[tt][i];
         const uint64_t eb = __ballot(mine[tt][i] != 0ull);
-        if (lane == 0 && eb) atomicAdd(&a.out_count[t], (uint32_t)__popcll(eb));
+        if (lane == 0 && eb) atomicAdd(&wg_cnt[2 * wq + tt][0], (uint32_t)__popcll(eb));
       }
-    }
+    __syncthreads();
+    if (tid < kDTiles && qb * kDTiles + tid < a.nt && wg_cnt[tid][0])
+      atomicAdd(&a.out_count[qb * kDTiles + tid], wg_cnt[tid][0]);
   } else {
-    // reservations: one per block when its 32 rows (aligned) share a bucket,
-    // else one per row
-    uint32_t res[2][4];
-    int64_t oe[2][4];  // output entry of this lane's row (-1: none)
+    // one reservation per (bucket, tile) slot of the workgroup when a
+    // bucket holds 32 pools or more, else one per row
+    const bool grouped = bshift >= 5;
+    int64_t oe[2][4];    // output entry of this lane's row (-1: none)
+    uint32_t off[2][4];  // the block's first entry within the workgroup's slot
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
@@ -1500,30 +1506,41 @@ __global__ __launch_bounds__(kDThreads, 1) void k_dense_level(DenseLevelArgs a) 
         const int t = qb * kDTiles + 2 * wq + tt;
         const int64_t rb0 = row0 + wr * 128 + i * 32;
         const uint64_t eb = __ballot(mine[tt][i] != 0ull);
-        res[tt][i] = 0u;
         oe[tt][i] = -1;
-        if (bshift >= 5) {
-          if (lane == 0 && eb)
-            res[tt][i] = atomicAdd(&a.out_count[(uint32_t)(rb0 >> bshift) * (uint32_t)a.nt + t],
-                                   (uint32_t)__popcll(eb));
+        off[tt][i] = 0u;
+        if (grouped) {
+          const int bi = (int)((rb0 >> bshift) - (row0 >> bshift));
+          if (lane == 0 && eb) off[tt][i] = atomicAdd(&wg_cnt[2 * wq + tt][bi], (uint32_t)__popcll(eb));
         } else if (mine[tt][i]) {
-          res[tt][i] =
-              atomicAdd(&a.out_count[(uint32_t)((rb0 + r) >> bshift) * (uint32_t)a.nt + t], 1u);
+          off[tt][i] = atomicAdd(&a.out_count[(uint32_t)((rb0 + r) >> bshift) * (uint32_t)a.nt + t], 1u);
         }
       }
+    if (grouped) {
+      __syncthreads();
+      if (tid < kDTiles * 8) {
+        const int tw = tid >> 3, bi = tid & 7, t = qb * kDTiles + tw;
+        const uint32_t c = wg_cnt[tw][bi];
+        if (c && t < a.nt)
+          wg_base[tw][bi] =
+              atomicAdd(&a.out_count[(uint32_t)((row0 >> bshift) + bi) * (uint32_t)a.nt + t], c);
+      }
+      __syncthreads();
+    }
 #pragma unroll
     for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int t = qb * kDTiles + 2 * wq + tt;
-        const int64_t row = row0 + wr * 128 + i * 32 + r;
+        const int64_t rb0 = row0 + wr * 128 + i * 32, row = rb0 + r;
         const uint64_t eb = __ballot(mine[tt][i] != 0ull);
         if (!eb) continue;
         const uint32_t slot = (uint32_t)(row >> bshift) * (uint32_t)a.nt + t;
-        const uint32_t pos =
-            bshift >= 5 ? (uint32_t)__builtin_amdgcn_readfirstlane(res[tt][i]) +
-                              (uint32_t)__popcll(eb & ((1ull << lane) - 1ull))
-                        : res[tt][i];
+        uint32_t pos = off[tt][i];
+        if (grouped) {
+          const int bi = (int)((rb0 >> bshift) - (row0 >> bshift));
+          pos = wg_base[2 * wq + tt][bi] + (uint32_t)__builtin_amdgcn_readfirstlane(off[tt][i]) +
+                (uint32_t)__popcll(eb & ((1ull << lane) - 1ull));
+        }
         if (mine[tt][i]) {
           if (pos < a.bcap) {
             const int64_t o = (int64_t)slot * a.bcap + pos;
