@@ -336,12 +336,15 @@ def run_poisson(server: Server, schedule, make_queries, rho_of, duration_s: floa
                 insert_every_s: float | None = None, insert_rows=None, progress=None):
     """Drives `server` in wall-clock time.  schedule: [(arrival s, batch size)];
     make_queries(i, size) -> queries; rho_of(i, size) -> thresholds;
-    insert_rows(k) -> rows for the k-th insert group (applied every
-    insert_every_s between steps); progress(s) is called about every 10 s of
-    the run.  Returns (requests, wall seconds, inserts)."""
+    insert_rows(k) -> rows for the k-th insert group, due every insert_every_s
+    up to duration_s; the groups that are due are applied together between
+    steps, so a long step delays them but none is skipped.  progress(s) is
+    called about every 10 s of the run.  Returns (requests, wall seconds,
+    insert groups applied)."""
     reqs = []
     nxt = 0
     k_ins = 0
+    n_groups = int(duration_s / insert_every_s + 1e-9) if insert_every_s and insert_rows else 0
     next_report = 10.0
     t_start = server.now()
     while True:
@@ -352,10 +355,14 @@ def run_poisson(server: Server, schedule, make_queries, rho_of, duration_s: floa
             server.submit(r)
             reqs.append(r)
             nxt += 1
-        if insert_every_s and insert_rows is not None and now >= (k_ins + 1) * insert_every_s \
-                and now < duration_s:
-            server.backend.insert(insert_rows(k_ins))
+        # every insert group that is due is applied now, in one call: a step
+        # that ran long must not let the inserts fall behind their schedule
+        due = []
+        while k_ins < n_groups and now >= (k_ins + 1) * insert_every_s:
+            due.append(insert_rows(k_ins))
             k_ins += 1
+        if due:
+            server.backend.insert(due[0] if len(due) == 1 else server.backend.concat(due))
         server.step()
         if progress is not None and now >= next_report:
             progress(now)

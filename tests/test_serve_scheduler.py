@@ -312,3 +312,48 @@ def test_admission_timeout():
     srv.drain(timeout_s=30)
     assert r0.status == "done" and r2.status == "done" and r1.results is None
     assert [r.rid for r in srv.finished] == [0, 2]
+
+
+def test_inserts_keep_their_schedule_when_steps_run_long():
+    """Insert groups are due every 10 ms; with every poll taking 25 ms the
+    driver applies the groups that fell due together, so all groups up to the
+    run's end are applied and every request still matches the oracle over
+    the rows of its epoch."""
+    import time
+
+    F, Q = _workload()
+    extra = np.abs(np.random.default_rng(3).normal(size=(2000, F.shape[1]))).astype(np.float32)
+    extra /= np.linalg.norm(extra, axis=1, keepdims=True)
+
+    class SlowBackend(FakeBackend):
+        def slot(self, ws_id):
+            ws = super().slot(ws_id)
+            poll = ws.poll
+
+            def slow_poll():
+                time.sleep(0.025)
+                return poll()
+
+            ws.poll = slow_poll
+            return ws
+
+    be = SlowBackend(F, polls_needed=1)
+    srv = serve.Server(be, 1 << 30, streams=2, max_queries=32)
+    sched = [(0.3 * i / 11, 4) for i in range(12)]   # the last at the run's end
+    groups = []
+
+    def rows(k):
+        r = extra[20 * k:20 * k + 20]
+        groups.append(len(r))
+        return r
+
+    reqs, wall, applied = serve.run_poisson(
+        srv, sched, lambda i, k: Q[4 * i:4 * i + k], lambda i, k: np.full(k, 0.9),
+        duration_s=0.3, insert_every_s=0.01, insert_rows=rows)
+    assert applied == 30 and len(groups) == 30
+    assert be.n == len(F) + 600
+    assert max(r.epoch_n for r in reqs) > len(F)
+    for r in reqs:
+        want = ob.range_search(be.feats[:r.epoch_n], r.queries, r.rho)
+        for (gi, _), (wi, _) in zip(r.results, want):
+            np.testing.assert_array_equal(gi, wi)
