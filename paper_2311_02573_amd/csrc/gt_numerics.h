@@ -145,13 +145,17 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // (64 lanes).  In chunk c (1024 elements), lane l owns the 16 elements
 //   c*1024 + 256 v + 4 l + j      (v, j = 0..3),
 // so each of the lane's four 16-byte loads belongs to one contiguous 1 KB
-// piece read by the whole wave.  The 16 products are summed pairwise:
-//   slice v:  (x0 y0 + x1 y1) + (x2 y2 + x3 y3)
+// piece read by the whole wave.  The 16 products are summed pairwise, each
+// pair by one fused multiply-add (written out, so that no compiler
+// contraction can change it):
+//   slice v:  fma(x0, y0, x1 y1) + fma(x2, y2, x3 y3)
 //   chunk:    (slice 0 + slice 1) + (slice 2 + slice 3)
 // Callers add the chunks in order and then sum over the lanes with
 // wave_reduce8; the result depends only on the two rows.  Slices past dp
 // count as zero; their loads are redirected to the last slice of the row so
 // that every load stays in bounds and no branch is needed.
+// Each product meets at most three roundings within its slice (as with
+// separate products), so
 // Bound: |error| <= (5 + (chunks - 1) + 6) * 2^-24 * exact sum.
 __device__ __forceinline__ int slice_index(int chunk, int v, int lane, int dp, bool& ok) {
   const int e4 = chunk * 256 + 64 * v + lane;  // float4 index within the row
@@ -159,8 +163,8 @@ __device__ __forceinline__ int slice_index(int chunk, int v, int lane, int dp, b
   return ok ? e4 : (dp >> 2) - 1;
 }
 __device__ __forceinline__ float slice_dot4(const float4& x, const float4& y) {
-  return __fadd_rn(__fadd_rn(__fmul_rn(x.x, y.x), __fmul_rn(x.y, y.y)),
-                   __fadd_rn(__fmul_rn(x.z, y.z), __fmul_rn(x.w, y.w)));
+  return __fadd_rn(__builtin_fmaf(x.x, y.x, __fmul_rn(x.y, y.y)),
+                   __builtin_fmaf(x.z, y.z, __fmul_rn(x.w, y.w)));
 }
 __device__ __forceinline__ float chunk_sum4(float s0, float s1, float s2, float s3) {
   return __fadd_rn(__fadd_rn(s0, s1), __fadd_rn(s2, s3));
@@ -175,7 +179,8 @@ __device__ __forceinline__ float lane_partial16(const float* __restrict__ a,
     const int ec = slice_index(chunk, v, lane, dp, ok);
     const float4 x = reinterpret_cast<const float4*>(a)[ec];
     const float4 y = reinterpret_cast<const float4*>(b)[ec];
-    sv[v] = ok ? slice_dot4(x, y) : 0.0f;
+    const float dv = slice_dot4(x, y);
+    sv[v] = ok ? dv : 0.0f;
   }
   return chunk_sum4(sv[0], sv[1], sv[2], sv[3]);
 }

@@ -1729,7 +1729,12 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
             for (int k = 0; k < 2; ++k)
 #pragma unroll
               for (int l = 0; l < 2; ++l)
-                sv[4 * s2 + 2 * k + l][v] = ok ? slice_dot4(qx[s2][k], fx[s2][l]) : 0.0f;
+              {
+                // computed for every slice (a redirected slice holds valid
+                // data), then selected: no branch per slice
+                const float dv = slice_dot4(qx[s2][k], fx[s2][l]);
+                sv[4 * s2 + 2 * k + l][v] = ok ? dv : 0.0f;
+              }
         }
 #pragma unroll
         for (int vi = 0; vi < 8; ++vi) {
