@@ -1674,9 +1674,7 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
       for (int c = 0; c < 2; ++c) {
         const int64_t i = 2 * (int64_t)en[s2].p + c;
         inv[s2][c] = en[s2].m ? (c == 0 ? en[s2].inv0 : en[s2].inv1) : 0.0f;
-        // a vector past the epoch (inverse norm 0, never a member) may lie
-        // past the allocation when the index is full: load the last row instead
-        frow[s2][c] = a.leaves + (i < a.n_epoch ? i : a.n_epoch - 1) * a.dp;
+        frow[s2][c] = a.leaves + i * a.dp;
         if (a.bitmap && lane == 0 && inv[s2][c] != 0.0f)
           atomicOr(&a.bitmap[(a.bit_base + i) >> 5], 1u << ((a.bit_base + i) & 31));
       }

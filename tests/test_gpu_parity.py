@@ -95,19 +95,19 @@ def test_ragged_shapes(gtmod, n, d, nq, cap):
         run_all(gtmod, w.feats, w.queries, rho, capacity=cap, label=f"ragged n={n} d={d} nq={nq} rho={rho}")
 
 
-def test_full_odd_index_last_vector(gtmod):
-    """A full index of odd size (capacity = N = 2^k + 1): the last level's
-    last pool pairs vector N - 1 with a slot past the allocation.  Queries
-    equal to the last vectors find them (the leaf test never reads past the
-    epoch), against the oracle for every pool format and the exhaustive path."""
+def test_odd_size_index_last_vectors(gtmod):
+    """An index of odd size N = 2^k + 1 (capacity 2^(k+1)): the last pool of
+    the last tested level pairs vector N - 1 with a slot past the epoch.
+    Queries equal to the last four vectors find them, against the oracle for
+    every pool format and the exhaustive path."""
     for n in (1025, 4097):
         w = synth.workload_small(n, 96, 8, temp=0.25, seed_offset=70 + n % 13)
         F = np.asarray(w.feats)
         Q = w.queries.copy()
         Q[:4] = F[n - 4:]
         rho = np.full(len(Q), 0.9)
-        say(f"full odd index n={n}")
-        ora = run_all(gtmod, F, Q, rho, label=f"full odd n={n}")
+        say(f"odd-size index n={n}")
+        ora = run_all(gtmod, F, Q, rho, label=f"odd-size n={n}")
         assert all(n - 4 + i in set(ora[i][0].tolist()) for i in range(4))
 
 
