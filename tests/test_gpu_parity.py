@@ -548,6 +548,35 @@ def test_more_tiles_than_workgroups_per_xcd(gtmod, grid):
         idx.close()
 
 
+def test_maximum_queries_per_call(gtmod):
+    """The largest call a format takes: 1024 query tiles (65,536 queries for
+    bf16 and fp8 pools, 32,768 for float32 rows), on a small index so that
+    every tile's frontier is short; the oracle on every 16th query and the
+    whole last tile.  One query more is refused."""
+    n, d = 8192, 64
+    w = synth.workload_small(n, d, 64, temp=0.25, seed_offset=33)
+    F = np.asarray(w.feats)
+    g = np.random.default_rng(33)
+    idx = gtmod.GTIndex(_dev(F))
+    try:
+        for fmt, nq in (("bf16", 65536), ("fp8", 65536), ("f32", 32768)):
+            # queries near random rows, so that most have a few neighbours
+            base = F[g.integers(0, n, nq)].astype(np.float64)
+            Q = base * np.exp(g.normal(0.0, 0.08, size=base.shape))
+            Q = (Q / np.linalg.norm(Q, axis=1, keepdims=True)).astype(np.float32)
+            sample = np.unique(np.concatenate([np.arange(0, nq, 16), np.arange(nq - 64, nq)]))
+            ora = ob.range_search(F, Q[sample], 0.9)
+            say(f"maximum call {fmt} nq={nq}")
+            got = idx.query(_dev(Q), 0.9, pool=fmt).to_lists()
+            assert len(got) == nq
+            assert_same([got[i] for i in sample], ora, f"max call {fmt}")
+            assert sum(len(o[0]) for o in ora) > len(sample)
+            with pytest.raises(gtmod.GTError):
+                idx.query(_dev(np.concatenate([Q, Q[:1]])), 0.9, pool=fmt)
+    finally:
+        idx.close()
+
+
 def test_result_segments_beyond_4096(gtmod):
     """Queries with more than 4096 results each take the radix-sort branch of
     the per-query sort: rho <= 0 on 6500 rows (every non-zero row), and a
