@@ -423,13 +423,25 @@ def main():
         ref_lists = None
         for pool in ("bf16", "fp8"):
             steps_v = max(5, args.steps // 2)
-            rv, wv = run_pipelined(pool, steps_v, 2, args.streams, qq=qv)
+            # the stream count for this batch size, from a short untimed
+            # trial: with 4096-query batches two streams measured faster than
+            # three (a third batch in flight only competes for L2), with
+            # 1024-query batches three
+            trial = {}
+            for sv in sorted({2, args.streams}):
+                _, wt = run_pipelined(pool, 4, 2, sv, qq=qv)
+                trial[sv] = wt
+            sv = min(trial, key=trial.get)
+            rv, wv = run_pipelined(pool, steps_v, 2, sv, qq=qv)
             rl, _, _ = measure_roofline(idx, qv, args.rho, pool, nqv, args.walk_subtract, w.d, 3)
             lists = rv.to_lists()
             same = ref_lists is None or all(np.array_equal(a[0], b[0]) for a, b in zip(lists, ref_lists))
             ref_lists = ref_lists or lists
             variant[pool] = {"queries_per_s": round(nqv * steps_v / wv, 1),
                              "ms_per_batch": round(wv / steps_v * 1e3, 4), "results": rv.total,
+                             "pipeline": {"workspaces": max(2, sv), "streams": sv,
+                                          "trial_ms_per_batch": {str(k): round(v / 4 * 1e3, 3)
+                                                                 for k, v in trial.items()}},
                              "ids_identical_to_bf16": bool(same), "roofline": rl}
             log(f"{nqv}-query batches, {pool} pools: {variant[pool]['ms_per_batch']} ms/batch, "
                 f"{variant[pool]['queries_per_s']:.0f} queries/s, roofline {rl['kernel']} "
